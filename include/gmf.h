@@ -1,0 +1,196 @@
+/*
+ * gmf.h -- C ABI of libgmf: block-wise adaptive SGD for generalized matrix
+ * factorization (GMF) on one AMD Instinct MI355X (gfx950).
+ *
+ * Model (Section 2, eq. 1-3).  Y is an n x m matrix whose entries follow an
+ * exponential dispersion family with mean mu_ij and
+ *     g(mu_ij) = eta_ij = x_i' beta_j + gamma_i' z_j + u_i' v_j,
+ * i.e. eta = X B' + Gamma Z' + U V' with X n x p, B m x p, Gamma n x q,
+ * Z m x q, U n x d, V m x d.  The penalised negative log-likelihood of eq. 6
+ * is minimised by the block-wise adaptive SGD of Algorithm 1, extended to the
+ * covariate effects as in Appendix A.
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers unless the name ends in _host.
+ *     Matrices are row-major, dense, in the caller's original row/column
+ *     order, float32 unless stated.
+ *   - The caller owns every buffer it passes.  The library keeps no pointer to
+ *     a caller array after the call returns, except the workspace given to
+ *     gmf_init, which must stay alive until gmf_destroy.
+ *   - The library allocates no device memory: all device state lives in the
+ *     caller's workspace (size from gmf_workspace_bytes).  It allocates a small
+ *     host-side context object.
+ *   - Work is enqueued on the caller's HIP stream; calls that return a *_host
+ *     value synchronise that stream first.
+ *   - Every call returns GMF_OK (0) or a negative code; gmf_last_error() gives
+ *     a message for the calling thread.  A non-finite parameter produced by a
+ *     step raises a device flag that the next synchronising call reports as
+ *     GMF_ENUMERIC.
+ *   - Calls on one context must not overlap (one stream, one thread at a time).
+ */
+#ifndef GMF_H_
+#define GMF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GMF_OK = 0,
+  GMF_EINVAL = -1,      /* bad argument, shape or configuration */
+  GMF_EWORKSPACE = -2,  /* workspace NULL, misaligned or too small */
+  GMF_EDEVICE = -3,     /* HIP runtime error or missing gfx950 device */
+  GMF_ENUMERIC = -4,    /* a step produced a non-finite value */
+  GMF_ENOTCONV = -5     /* gmf_fit stopped at max_epochs without meeting tol */
+};
+
+/* Families and links of Supplementary Table 1 supported on the device path. */
+enum { GMF_POISSON = 0, GMF_NEGBIN = 1, GMF_GAUSSIAN = 2 };
+enum { GMF_LINK_LOG = 0, GMF_LINK_IDENTITY = 1 };
+/* Arithmetic of the block contractions (eta and the four gradient sums).
+ * FP32: float32 matrix-core products with float32 accumulation.
+ * BF16: bfloat16 operands (round to nearest even), float32 accumulation.
+ * In both, the smoothed moments and the deviance sums are float64. */
+enum { GMF_PREC_FP32 = 0, GMF_PREC_BF16 = 1 };
+/* Element type of the Y array handed to gmf_init. */
+enum { GMF_Y_INT32 = 0, GMF_Y_FLOAT32 = 1 };
+
+typedef struct gmf_config {
+  int32_t family;     /* GMF_POISSON, GMF_NEGBIN or GMF_GAUSSIAN             */
+  int32_t link;       /* GMF_LINK_LOG (Poisson, NB) or GMF_LINK_IDENTITY     */
+  int32_t precision;  /* GMF_PREC_FP32 or GMF_PREC_BF16                       */
+  int32_t bias_mode;  /* 0: alpha_t = (1-(1-a2)^t)/(1-(1-a1)^t) (Adam form);
+                         1: alpha_t = (1-a2^t)/(1-a1^t) as printed (eq. 11)    */
+  int64_t n, m;       /* rows and columns of Y                                 */
+  int32_t d, p, q;    /* rank and covariate counts; p, q >= 0, 1 <= d,
+                         p + q + d <= 64                                       */
+  int32_t R, S;       /* number of row blocks and column blocks (Algorithm 1) */
+  double phi;         /* dispersion (1 for Poisson and NB)                     */
+  double nb_alpha;    /* NB shape alpha > 0: Var = mu + mu^2/alpha             */
+  double lambda[4];   /* ridge weights for B, Gamma, U, V (eq. 6, Appendix A) */
+  double rate0, decay, tau; /* rho_t = rate0 / (1 + rate0 decay t)^tau        */
+  double alpha1, alpha2;    /* EMA weights of the new estimate (eq. 12)       */
+  double damping;     /* delta added to the smoothed Hessian in the step      */
+  double eps;         /* mu floor: eta is clamped to >= log(eps) (log link)   */
+  double eta_max;     /* eta ceiling for the log link                         */
+  uint64_t seed;      /* schedule seed: partitions and row-block draws        */
+} gmf_config;
+
+/* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
+ * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
+ * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
+ * bias_mode=0, seed=0. */
+void gmf_config_default(gmf_config* cfg);
+
+/* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
+ * matrix will be passed).  Returns 0 for an invalid cfg. */
+size_t gmf_workspace_bytes(const gmf_config* cfg, int32_t with_weights);
+
+/* gmf_init -- set up a context: draw the partitions {I_r}, {J_s} once
+ * (Algorithm 1, before the loop) from SplitMix64 stream 0/1 of cfg->seed with
+ * Fisher-Yates shuffles, and copy Y, W, X, Z and the starting parameters into
+ * the workspace, physically permuted so that every block I_r x J_s is a dense
+ * rectangle.
+ *   Y  n x m, GMF_Y_INT32 counts (0 <= y < 2^24) or GMF_Y_FLOAT32 reals.
+ *   X  n x p, Z m x q (may be NULL when p or q is 0).
+ *   W  n x m positive weights w_ij of a_ij(phi) = phi/w_ij (eq. 2), or NULL
+ *      for w = 1; non-NULL requires with_weights in gmf_workspace_bytes.
+ *   B0 m x p, A0 n x q (Gamma), U0 n x d, V0 m x d starting values.
+ *   stream: hipStream_t (NULL = default stream).
+ * Synchronises the stream.  Errors: GMF_EINVAL (shapes, cfg, NULL arrays),
+ * GMF_EWORKSPACE, GMF_EDEVICE. */
+int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
+             size_t ws_bytes, void* stream, const void* Y, int32_t y_dtype,
+             const float* X, const float* Z, const float* W, const float* B0,
+             const float* A0, const float* U0, const float* V0);
+
+/* gmf_step -- run nsteps iterations of Algorithm 1 (steps 1-4) with the
+ * covariate extension of Appendix A.  Iteration t (global counter, from 1):
+ * column block s_t = (t-1) mod S, row block r_t drawn uniformly with
+ * replacement (SplitMix64 stream 2, draw t-1); on B = I_r x J_s it forms
+ * eta = [X,Gamma,U]_I [B,Z,V]_J', mu = g^-1(clamp(eta)), the deviance
+ * derivatives D1 = -w(y-mu)/(phi nu g'), D2 = w/(phi nu g'^2) (Section 3),
+ * the minibatch gradients of eq. 15 / Appendix A for [Gamma,U]_I and [B,V]_J
+ * from the pre-step parameters, the EMAs of eq. 12 (float64) and the step
+ * theta -= rho_t alpha_t Gbar / (Hbar + damping) (eq. 13-14).  It also records
+ * the block deviance sum_B w D(y, mu) (float64).  Asynchronous.
+ * Errors: GMF_EINVAL (nsteps < 0), GMF_EDEVICE. */
+int gmf_step(void* ctx, int64_t nsteps);
+
+/* gmf_fit -- run epochs of R*S steps (one epoch = R sweeps over J_1..J_S) up
+ * to max_epochs; every eval_every epochs evaluate the full deviance and stop
+ * when its relative change is below tol (tol <= 0: run all epochs).
+ * dev_trace_host (may be NULL) receives one deviance per evaluation (room for
+ * max_epochs/eval_every values); *epochs_done_host the epochs run.
+ * Returns GMF_OK, GMF_ENOTCONV (tol > 0 not met), GMF_ENUMERIC, GMF_EDEVICE. */
+int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
+            double* dev_trace_host, int32_t* epochs_done_host);
+
+/* gmf_deviance -- full deviance sum_ij w_ij D(y_ij, mu_ij) of the current
+ * parameters (D as defined after eq. 2, Supplementary Table 1 times 2;
+ * NB deviance of Appendix A), accumulated in float64 in a fixed order, and the
+ * penalised objective D/(2 phi) + sum_k lambda_k/2 ||theta_k||_F^2 (eq. 6).
+ * Either host pointer may be NULL.  Synchronises. */
+int gmf_deviance(void* ctx, double* total_host, double* penalized_host);
+
+/* gmf_block_deviance -- the block deviances of the last `count` steps, oldest
+ * first, into host memory (count <= min(steps done, 4096)).  Synchronises. */
+int gmf_block_deviance(void* ctx, double* out_host, int64_t count);
+
+/* gmf_get_params -- copy B (m x p), Gamma (n x q), U (n x d), V (m x d) into
+ * caller device arrays in original order (any pointer may be NULL to skip).
+ * postprocess = 0: the raw iterate.  postprocess = 1: the identifiability
+ * projection of Algorithm 2, constraints (A) then (B1), computed in float64
+ * on the device (Gram matrices, CholeskyQR2, one-sided Jacobi SVD of the
+ * d x d core, sign rule: first non-zero entry of each V column positive);
+ * the context's iterate is left unchanged.  Enqueued; synchronises only to
+ * check errors. */
+int gmf_get_params(void* ctx, float* B, float* A, float* U, float* V,
+                   int32_t postprocess);
+
+/* gmf_get_moments -- copy the smoothed gradients/Hessians (float64, original
+ * order): Grow, Hrow n x (q+d) for [Gamma, U]; Gcol, Hcol m x (p+d) for
+ * [B, V].  Any pointer may be NULL. */
+int gmf_get_moments(void* ctx, double* Grow, double* Hrow, double* Gcol,
+                    double* Hcol);
+
+/* gmf_set_params -- overwrite the iterate (original order, like gmf_init's
+ * starting values); the moments and the step counter are kept. */
+int gmf_set_params(void* ctx, const float* B, const float* A, const float* U,
+                   const float* V);
+
+/* gmf_get_schedule -- the drawn schedule, for checking: row_perm_host (n) and
+ * col_perm_host (m) receive the permutations (block r holds
+ * row_perm[floor(rn/R) .. floor((r+1)n/R)-1]); r_host receives the row
+ * blocks of steps t_first .. t_first+count-1 (t from 1).  Any may be NULL. */
+int gmf_get_schedule(void* ctx, int32_t* row_perm_host, int32_t* col_perm_host,
+                     int64_t t_first, int64_t count, int32_t* r_host);
+
+/* gmf_schedule_host -- the same schedule without a context or device (host
+ * arrays): the permutations of gmf_init for (seed, n, m) and the row blocks
+ * r_t of steps t_first .. t_first+count-1 for R row blocks.  Any output may
+ * be NULL.  Pure host computation. */
+int gmf_schedule_host(uint64_t seed, int64_t n, int64_t m, int32_t R, int64_t t_first,
+                      int64_t count, int32_t* row_perm_host, int32_t* col_perm_host,
+                      int32_t* r_host);
+
+/* Steps run so far (the global counter t of the last step). */
+int64_t gmf_steps_done(void* ctx);
+
+/* gmf_sync -- wait for the context's stream and report GMF_ENUMERIC if a
+ * non-finite value was produced since the last check (the flag is cleared). */
+int gmf_sync(void* ctx);
+
+/* Release the context (not the workspace). NULL is ignored. */
+void gmf_destroy(void* ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* gmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMF_H_ */

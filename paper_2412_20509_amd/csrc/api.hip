@@ -1,0 +1,683 @@
+// Host side of libgmf: configuration checks, workspace planning, the seeded
+// schedule of Algorithm 1 and the C ABI declared in include/gmf.h.
+//
+// Schedule (Algorithm 1): the row and column partitions are drawn once, from
+// Fisher-Yates shuffles driven by SplitMix64 (Steele, Lea and Flood 2014) on
+// sub-streams 0 and 1 of the seed; block r of the rows is the slice
+// [floor(r n / R), floor((r+1) n / R)) of the row permutation (likewise for
+// columns).  Step t (from 1) uses column block (t-1) mod S and row block
+// floor(u_t R / 2^64), u_t being draw t-1 of sub-stream 2 (uniform, with
+// replacement).  Sub-stream k starts at the (k+1)-th SplitMix64 output of the
+// seed; draw j of a stream with start state x is mix(x + (j+1) * golden).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gmf.h"
+#include "gmf_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(GMF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ----------------------------------------------------------------- SplitMix64
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ULL;
+
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+uint64_t stream_start(uint64_t seed, uint64_t stream) { return mix64(seed + (stream + 1) * kGolden); }
+uint64_t stream_draw(uint64_t start, uint64_t j) { return mix64(start + (j + 1) * kGolden); }
+uint64_t below(uint64_t u, uint64_t n) {
+  return (uint64_t)(((unsigned __int128)u * (unsigned __int128)n) >> 64);
+}
+
+std::vector<int> shuffle(uint64_t seed, uint64_t stream, int64_t n) {
+  std::vector<int> perm(n);
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+  const uint64_t x0 = stream_start(seed, stream);
+  for (int64_t i = n - 1; i >= 1; --i) {
+    const int64_t j = (int64_t)below(stream_draw(x0, (uint64_t)(n - 1 - i)), (uint64_t)(i + 1));
+    std::swap(perm[i], perm[j]);
+  }
+  return perm;
+}
+
+// ---------------------------------------------------------------- planning --
+int round_up(int x, int a) { return (x + a - 1) / a * a; }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+  int64_t n = 0, m = 0;
+  int R = 0, S = 0, p = 0, q = 0, d = 0, k = 0, KP = 0, KU = 0, KV = 0;
+  int prec = 0, fam = 0, with_w = 0;
+  std::vector<int> ro, co, ld, rpw, nrr, nct;
+  std::vector<int64_t> coP;
+  int64_t LDtot = 0;
+  int64_t upart_elems = 0, vpart_elems = 0;
+  int max_tiles = 0, dev_tiles = 0;
+  // byte offsets into the workspace
+  size_t o_Yb, o_Wb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Gcol, o_Hcol, o_Upart, o_Vpart,
+      o_devpart, o_devring, o_flag, o_rowperm, o_colperm, o_rowblk, o_rowloc, o_colblk,
+      o_colloc, o_blkrowbase, o_blknrows, o_blkcoloff, o_blkld, o_tileblk, o_tilefirst,
+      o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
+      o_scal, o_sumsq, o_post, o_firstnz, total;
+};
+
+constexpr int kDevRing = 4096;
+constexpr int kSumsqBlocks = 256;
+
+std::string check_config(const gmf_config* c) {
+  if (!c) return "cfg is NULL";
+  if (c->n < 1 || c->m < 1) return "n and m must be >= 1";
+  if (c->n > (int64_t)1 << 31 || c->m > (int64_t)1 << 31) return "n, m must be < 2^31";
+  if (c->d < 1 || c->p < 0 || c->q < 0) return "need d >= 1, p >= 0, q >= 0";
+  if (c->p + c->q + c->d > 64) return "p + q + d must be <= 64";
+  if (c->R < 1 || c->S < 1 || c->R > c->n || c->S > c->m) return "need 1 <= R <= n, 1 <= S <= m";
+  if (c->family < GMF_POISSON || c->family > GMF_GAUSSIAN) return "unknown family";
+  if (c->family == GMF_GAUSSIAN && c->link != GMF_LINK_IDENTITY)
+    return "Gaussian family supports the identity link only";
+  if (c->family != GMF_GAUSSIAN && c->link != GMF_LINK_LOG)
+    return "Poisson and NB families support the log link only";
+  if (c->precision != GMF_PREC_FP32 && c->precision != GMF_PREC_BF16) return "unknown precision";
+  if (!(c->phi > 0) || !(c->nb_alpha > 0)) return "phi and nb_alpha must be > 0";
+  if (!(c->rate0 > 0) || !(c->decay >= 0) || !(c->tau > 0)) return "bad learning-rate parameters";
+  if (!(c->alpha1 > 0 && c->alpha1 <= 1) || !(c->alpha2 > 0 && c->alpha2 <= 1))
+    return "alpha1, alpha2 must be in (0, 1]";
+  if (c->bias_mode != 0 && c->bias_mode != 1) return "bias_mode must be 0 or 1";
+  if (c->bias_mode == 1 && c->alpha1 >= 1.0) return "bias_mode 1 needs alpha1 < 1";
+  if (!(c->damping >= 0) || !(c->eps > 0) || !std::isfinite(c->eta_max)) return "bad damping/eps/eta_max";
+  for (int i = 0; i < 4; ++i)
+    if (!(c->lambda[i] >= 0)) return "lambda must be >= 0";
+  return "";
+}
+
+void make_plan(const gmf_config* c, int with_w, Plan& P) {
+  P.n = c->n; P.m = c->m; P.R = c->R; P.S = c->S;
+  P.p = c->p; P.q = c->q; P.d = c->d; P.k = c->p + c->q + c->d;
+  P.prec = c->precision; P.fam = c->family; P.with_w = with_w ? 1 : 0;
+  P.KP = (P.prec == GMF_PREC_BF16) ? round_up(P.k, 32) : round_up(P.k, 16);
+  P.KU = P.q + P.d; P.KV = P.p + P.d;
+  P.ro.resize(P.R + 1); P.co.resize(P.S + 1);
+  for (int r = 0; r <= P.R; ++r) P.ro[r] = (int)((int64_t)r * P.n / P.R);
+  for (int s = 0; s <= P.S; ++s) P.co[s] = (int)((int64_t)s * P.m / P.S);
+  P.ld.resize(P.S); P.coP.assign(P.S + 1, 0); P.nct.resize(P.S);
+  int nct_max = 1;
+  for (int s = 0; s < P.S; ++s) {
+    const int ms = P.co[s + 1] - P.co[s];
+    P.ld[s] = round_up(ms, 4);
+    P.coP[s + 1] = P.coP[s] + P.ld[s];
+    P.nct[s] = (ms + gmf::kTileCols - 1) / gmf::kTileCols;
+    nct_max = std::max(nct_max, P.nct[s]);
+  }
+  P.LDtot = P.coP[P.S];
+  P.rpw.resize(P.R); P.nrr.resize(P.R);
+  for (int r = 0; r < P.R; ++r) {
+    const int nr = P.ro[r + 1] - P.ro[r];
+    int rpw = round_up((int)std::ceil((double)nr * nct_max / 256.0), gmf::kRowGroup);
+    rpw = std::max(gmf::kRowGroup, std::min(rpw, 4096));
+    P.rpw[r] = rpw;
+    P.nrr[r] = (nr + rpw - 1) / rpw;
+  }
+  P.upart_elems = P.vpart_elems = 0; P.max_tiles = 0; P.dev_tiles = 0;
+  for (int r = 0; r < P.R; ++r)
+    for (int s = 0; s < P.S; ++s) {
+      const int64_t nr = P.ro[r + 1] - P.ro[r], ms = P.co[s + 1] - P.co[s];
+      P.upart_elems = std::max<int64_t>(P.upart_elems, (int64_t)P.nct[s] * nr * 2 * P.KU);
+      P.vpart_elems = std::max<int64_t>(P.vpart_elems, (int64_t)P.nrr[r] * ms * 2 * P.KV);
+      P.max_tiles = std::max(P.max_tiles, P.nrr[r] * P.nct[s]);
+      P.dev_tiles += P.nrr[r] * P.nct[s];
+    }
+  const int nb = P.R * P.S;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  P.o_Yb = take(sizeof(float) * (size_t)P.n * P.LDtot);
+  P.o_Wb = take(P.with_w ? sizeof(float) * (size_t)P.n * P.LDtot : 0);
+  P.o_Prow = take(sizeof(float) * (size_t)P.n * P.KP);
+  P.o_Pcol = take(sizeof(float) * (size_t)P.m * P.KP);
+  P.o_Grow = take(sizeof(double) * (size_t)P.n * P.KU);
+  P.o_Hrow = take(sizeof(double) * (size_t)P.n * P.KU);
+  P.o_Gcol = take(sizeof(double) * (size_t)P.m * P.KV);
+  P.o_Hcol = take(sizeof(double) * (size_t)P.m * P.KV);
+  P.o_Upart = take(sizeof(float) * (size_t)P.upart_elems);
+  P.o_Vpart = take(sizeof(float) * (size_t)P.vpart_elems);
+  P.o_devpart = take(sizeof(double) * (size_t)P.max_tiles);
+  P.o_devring = take(sizeof(double) * kDevRing);
+  P.o_flag = take(sizeof(int) * 4);
+  P.o_rowperm = take(sizeof(int) * (size_t)P.n);
+  P.o_colperm = take(sizeof(int) * (size_t)P.m);
+  P.o_rowblk = take(sizeof(int) * (size_t)P.n);
+  P.o_rowloc = take(sizeof(int) * (size_t)P.n);
+  P.o_colblk = take(sizeof(int) * (size_t)P.m);
+  P.o_colloc = take(sizeof(int) * (size_t)P.m);
+  P.o_blkrowbase = take(sizeof(int64_t) * P.R);
+  P.o_blknrows = take(sizeof(int) * P.R);
+  P.o_blkcoloff = take(sizeof(int64_t) * P.S);
+  P.o_blkld = take(sizeof(int) * P.S);
+  P.o_tileblk = take(sizeof(int) * (size_t)P.dev_tiles);
+  P.o_tilefirst = take(sizeof(int) * nb);
+  P.o_byoff = take(sizeof(int64_t) * nb);
+  P.o_brow0 = take(sizeof(int) * nb);
+  P.o_bcol0 = take(sizeof(int) * nb);
+  P.o_bnb = take(sizeof(int) * nb);
+  P.o_bmb = take(sizeof(int) * nb);
+  P.o_bldy = take(sizeof(int) * nb);
+  P.o_brpw = take(sizeof(int) * nb);
+  P.o_bnct = take(sizeof(int) * nb);
+  P.o_devpartial = take(sizeof(double) * (size_t)P.dev_tiles);
+  P.o_scal = take(sizeof(double) * 16);
+  P.o_sumsq = take(sizeof(double) * kSumsqBlocks * 4);
+  P.o_post = take(sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks));
+  P.o_firstnz = take(sizeof(int) * 64);
+  P.total = o;
+}
+
+struct Ctx {
+  gmf_config cfg;
+  Plan P;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  std::vector<int> row_perm, col_perm;
+  uint64_t draw_start = 0;
+  int64_t t = 0;
+  int want_block_dev = 1;
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+Ctx* as_ctx(void* c) { return static_cast<Ctx*>(c); }
+
+int row_block_of_step(const Ctx* c, int64_t t) {
+  return (int)below(stream_draw(c->draw_start, (uint64_t)(t - 1)), (uint64_t)c->P.R);
+}
+
+double learning_rate(const gmf_config& c, int64_t t) {
+  return c.rate0 / std::pow(1.0 + c.rate0 * c.decay * (double)t, c.tau);
+}
+double bias_factor(const gmf_config& c, int64_t t) {
+  const double a1 = c.alpha1, a2 = c.alpha2, tt = (double)t;
+  if (c.bias_mode == 0) return (1.0 - std::pow(1.0 - a2, tt)) / (1.0 - std::pow(1.0 - a1, tt));
+  return (1.0 - std::pow(a2, tt)) / (1.0 - std::pow(a1, tt));
+}
+
+gmf::FamilyArgs family_args(const gmf_config& c) {
+  gmf::FamilyArgs f;
+  f.phi_inv = (float)(1.0 / c.phi);
+  f.nb_alpha = (float)c.nb_alpha;
+  f.eta_lo = (float)std::log(c.eps);
+  f.eta_hi = (float)c.eta_max;
+  return f;
+}
+
+int check_flag(Ctx* c) {
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c->at<int>(c->P.o_flag), sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (flag) {
+    HIP_TRY(gmf::launch_fill_i32(c->at<int>(c->P.o_flag), 1, 0, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    if (flag & 2) return fail(GMF_EINVAL, "input contains a negative, too large or non-finite value");
+    if (flag & 4) return fail(GMF_ENUMERIC, "post-processing: X'X, Z'Z or a factor Gram is not positive definite");
+    return fail(GMF_ENUMERIC, "a step produced a non-finite parameter");
+  }
+  return GMF_OK;
+}
+
+int enqueue_steps(Ctx* c, int64_t nsteps) {
+  const Plan& P = c->P;
+  const gmf_config& cf = c->cfg;
+  const gmf::FamilyArgs fa = family_args(cf);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t t = c->t + 1;
+    const int r = row_block_of_step(c, t);
+    const int s = (int)((t - 1) % P.S);
+    const int nb = P.ro[r + 1] - P.ro[r];
+    const int mb = P.co[s + 1] - P.co[s];
+    gmf::TileArgs ta;
+    ta.b.Y = c->at<float>(P.o_Yb) + (int64_t)P.ro[r] * P.LDtot + (int64_t)nb * P.coP[s];
+    ta.b.W = P.with_w ? c->at<float>(P.o_Wb) + (int64_t)P.ro[r] * P.LDtot + (int64_t)nb * P.coP[s]
+                      : nullptr;
+    ta.b.Prow = c->at<float>(P.o_Prow) + (int64_t)P.ro[r] * P.KP;
+    ta.b.Pcol = c->at<float>(P.o_Pcol) + (int64_t)P.co[s] * P.KP;
+    ta.b.ldy = P.ld[s];
+    ta.b.n_b = nb;
+    ta.b.m_b = mb;
+    ta.b.rows_per_wg = P.rpw[r];
+    ta.b.n_rr = P.nrr[r];
+    ta.b.n_ct = P.nct[s];
+    ta.f = fa;
+    ta.Upart = c->at<float>(P.o_Upart);
+    ta.Vpart = c->at<float>(P.o_Vpart);
+    ta.devpart = c->at<double>(P.o_devpart);
+    ta.p = P.p; ta.q = P.q; ta.d = P.d; ta.KU = P.KU; ta.KV = P.KV;
+    ta.want_dev = c->want_block_dev;
+    HIP_TRY(gmf::launch_tile(P.prec, P.fam, P.KP, ta, c->st));
+
+    gmf::UpdateArgs ua;
+    ua.Prow = c->at<float>(P.o_Prow) + (int64_t)P.ro[r] * P.KP;
+    ua.Pcol = c->at<float>(P.o_Pcol) + (int64_t)P.co[s] * P.KP;
+    ua.Grow = c->at<double>(P.o_Grow) + (int64_t)P.ro[r] * P.KU;
+    ua.Hrow = c->at<double>(P.o_Hrow) + (int64_t)P.ro[r] * P.KU;
+    ua.Gcol = c->at<double>(P.o_Gcol) + (int64_t)P.co[s] * P.KV;
+    ua.Hcol = c->at<double>(P.o_Hcol) + (int64_t)P.co[s] * P.KV;
+    ua.Upart = ta.Upart; ua.Vpart = ta.Vpart; ua.devpart = ta.devpart;
+    ua.n_b = nb; ua.m_b = mb; ua.n_ct = P.nct[s]; ua.n_rr = P.nrr[r];
+    ua.n_tiles = P.nct[s] * P.nrr[r];
+    ua.p = P.p; ua.q = P.q; ua.d = P.d; ua.KU = P.KU; ua.KV = P.KV; ua.KP = P.KP;
+    ua.scale_m = (double)P.m / mb;
+    ua.scale_n = (double)P.n / nb;
+    ua.lam_B = cf.lambda[0]; ua.lam_A = cf.lambda[1]; ua.lam_U = cf.lambda[2]; ua.lam_V = cf.lambda[3];
+    ua.a1 = cf.alpha1; ua.a2 = cf.alpha2;
+    ua.stepsize = learning_rate(cf, t) * bias_factor(cf, t);
+    ua.damping = cf.damping;
+    ua.dev_out = c->at<double>(P.o_devring) + (t - 1) % kDevRing;
+    ua.err_flag = c->at<int>(P.o_flag);
+    ua.want_dev = c->want_block_dev;
+    HIP_TRY(gmf::launch_update(ua, c->st));
+    c->t = t;
+  }
+  return GMF_OK;
+}
+
+int compute_deviance(Ctx* c, double* total, double* pen) {
+  const Plan& P = c->P;
+  gmf::DevArgs a;
+  a.Y = c->at<float>(P.o_Yb);
+  a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+  a.Prow = c->at<float>(P.o_Prow);
+  a.Pcol = c->at<float>(P.o_Pcol);
+  a.tile_block = c->at<int>(P.o_tileblk);
+  a.tile_first = c->at<int>(P.o_tilefirst);
+  a.blk_yoff = c->at<int64_t>(P.o_byoff);
+  a.blk_row0 = c->at<int>(P.o_brow0);
+  a.blk_col0 = c->at<int>(P.o_bcol0);
+  a.blk_nb = c->at<int>(P.o_bnb);
+  a.blk_mb = c->at<int>(P.o_bmb);
+  a.blk_ldy = c->at<int>(P.o_bldy);
+  a.blk_rpw = c->at<int>(P.o_brpw);
+  a.blk_nct = c->at<int>(P.o_bnct);
+  a.f = family_args(c->cfg);
+  a.partial = c->at<double>(P.o_devpartial);
+  a.n_tiles = P.dev_tiles;
+  // The deviance monitor uses float32 products regardless of the step
+  // precision, so its panel stride must be a float32 case (16, 32, 48, 64).
+  HIP_TRY(gmf::launch_deviance(P.fam, P.KP, a, c->st));
+  double* scal = c->at<double>(P.o_scal);
+  HIP_TRY(gmf::launch_sum_partials(a.partial, P.dev_tiles, scal + 0, c->st));
+  double* sq = c->at<double>(P.o_sumsq);
+  const int cols[4][3] = {{1, 0, P.p},           // B: column panel, cols [0, p)
+                          {0, P.p, P.q},         // Gamma: row panel, [p, p+q)
+                          {0, P.p + P.q, P.d},   // U: row panel
+                          {1, P.p + P.q, P.d}};  // V: column panel
+  for (int i = 0; i < 4; ++i) {
+    const bool colside = cols[i][0] == 1;
+    const float* Pn = colside ? c->at<float>(P.o_Pcol) : c->at<float>(P.o_Prow);
+    const int64_t rows = colside ? P.m : P.n;
+    if (cols[i][2] > 0) {
+      HIP_TRY(gmf::launch_sumsq(Pn, P.KP, rows, cols[i][1], cols[i][2], sq + i * kSumsqBlocks,
+                                kSumsqBlocks, c->st));
+    } else {
+      HIP_TRY(gmf::launch_fill_f64(sq + i * kSumsqBlocks, kSumsqBlocks, 0.0, c->st));
+    }
+    HIP_TRY(gmf::launch_sum_partials(sq + i * kSumsqBlocks, kSumsqBlocks, scal + 1 + i, c->st));
+  }
+  double h[5];
+  HIP_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (total) *total = h[0];
+  if (pen) {
+    const double* lam = c->cfg.lambda;
+    *pen = h[0] / (2.0 * c->cfg.phi) +
+           0.5 * (lam[0] * h[1] + lam[1] * h[2] + lam[2] * h[3] + lam[3] * h[4]);
+  }
+  return check_flag(c);
+}
+
+}  // namespace
+
+// =================================================================== C ABI ==
+extern "C" {
+
+void gmf_config_default(gmf_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->family = GMF_POISSON;
+  c->link = GMF_LINK_LOG;
+  c->precision = GMF_PREC_FP32;
+  c->bias_mode = 0;
+  c->d = 1;
+  c->R = 10;
+  c->S = 5;
+  c->phi = 1.0;
+  c->nb_alpha = 5.0;
+  c->lambda[0] = 0.0; c->lambda[1] = 0.0; c->lambda[2] = 1.0; c->lambda[3] = 1.0;
+  c->rate0 = 0.05; c->decay = 0.05; c->tau = 0.75;
+  c->alpha1 = 0.1; c->alpha2 = 0.01;
+  c->damping = 1e-3; c->eps = 1e-8; c->eta_max = 30.0;
+  c->seed = 0;
+}
+
+size_t gmf_workspace_bytes(const gmf_config* cfg, int32_t with_weights) {
+  if (!check_config(cfg).empty()) return 0;
+  Plan P;
+  make_plan(cfg, with_weights, P);
+  return P.total;
+}
+
+const char* gmf_last_error(void) { return g_last_error.c_str(); }
+
+int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_bytes,
+             void* stream, const void* Y, int32_t y_dtype, const float* X, const float* Z,
+             const float* W, const float* B0, const float* A0, const float* U0,
+             const float* V0) {
+  g_last_error.clear();
+  if (!ctx_out) return fail(GMF_EINVAL, "ctx_out is NULL");
+  *ctx_out = nullptr;
+  const std::string bad = check_config(cfg);
+  if (!bad.empty()) return fail(GMF_EINVAL, "invalid config: " + bad);
+  if (!Y || !U0 || !V0) return fail(GMF_EINVAL, "Y, U0 and V0 must be given");
+  if (y_dtype != GMF_Y_INT32 && y_dtype != GMF_Y_FLOAT32) return fail(GMF_EINVAL, "bad y_dtype");
+  if (cfg->p > 0 && (!X || !B0)) return fail(GMF_EINVAL, "p > 0 needs X and B0");
+  if (cfg->q > 0 && (!Z || !A0)) return fail(GMF_EINVAL, "q > 0 needs Z and A0");
+  // device check: gfx950 only
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GMF_EDEVICE, std::string("libgmf needs a gfx950 device, found ") + prop.gcnArchName);
+
+  Ctx* c = new Ctx();
+  c->cfg = *cfg;
+  make_plan(cfg, W != nullptr, c->P);
+  const Plan& P = c->P;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < P.total) {
+    delete c;
+    return fail(GMF_EWORKSPACE, "workspace NULL, not 256-byte aligned or smaller than " +
+                                    std::to_string(P.total) + " bytes");
+  }
+  c->ws = static_cast<char*>(workspace);
+  c->st = static_cast<hipStream_t>(stream);
+  c->row_perm = shuffle(cfg->seed, 0, P.n);
+  c->col_perm = shuffle(cfg->seed, 1, P.m);
+  c->draw_start = stream_start(cfg->seed, 2);
+
+  // host tables
+  std::vector<int> rowblk(P.n), rowloc(P.n), colblk(P.m), colloc(P.m), nrows(P.R);
+  std::vector<int64_t> rowbase(P.R), coloff(P.S);
+  for (int r = 0; r < P.R; ++r) {
+    nrows[r] = P.ro[r + 1] - P.ro[r];
+    rowbase[r] = (int64_t)P.ro[r] * P.LDtot;
+    for (int i = P.ro[r]; i < P.ro[r + 1]; ++i) {
+      rowblk[c->row_perm[i]] = r;
+      rowloc[c->row_perm[i]] = i - P.ro[r];
+    }
+  }
+  for (int s = 0; s < P.S; ++s) {
+    coloff[s] = P.coP[s];
+    for (int j = P.co[s]; j < P.co[s + 1]; ++j) {
+      colblk[c->col_perm[j]] = s;
+      colloc[c->col_perm[j]] = j - P.co[s];
+    }
+  }
+  const int nb = P.R * P.S;
+  std::vector<int> tileblk(P.dev_tiles), tilefirst(nb), brow0(nb), bcol0(nb), bnb(nb), bmb(nb),
+      bldy(nb), brpw(nb), bnct(nb);
+  std::vector<int64_t> byoff(nb);
+  int tcount = 0;
+  for (int r = 0; r < P.R; ++r)
+    for (int s = 0; s < P.S; ++s) {
+      const int b = r * P.S + s;
+      const int nr = P.ro[r + 1] - P.ro[r];
+      tilefirst[b] = tcount;
+      byoff[b] = (int64_t)P.ro[r] * P.LDtot + (int64_t)nr * P.coP[s];
+      brow0[b] = P.ro[r];
+      bcol0[b] = P.co[s];
+      bnb[b] = nr;
+      bmb[b] = P.co[s + 1] - P.co[s];
+      bldy[b] = P.ld[s];
+      brpw[b] = P.rpw[r];
+      bnct[b] = P.nct[s];
+      for (int k = 0; k < P.nrr[r] * P.nct[s]; ++k) tileblk[tcount++] = b;
+    }
+
+  hipStream_t st = c->st;
+  auto h2d = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+#define H2D(off, vec) \
+  if (e == hipSuccess) e = h2d(P.off, vec.data(), vec.size() * sizeof(vec[0]))
+  H2D(o_rowperm, c->row_perm); H2D(o_colperm, c->col_perm);
+  H2D(o_rowblk, rowblk); H2D(o_rowloc, rowloc); H2D(o_colblk, colblk); H2D(o_colloc, colloc);
+  H2D(o_blkrowbase, rowbase); H2D(o_blknrows, nrows); H2D(o_blkcoloff, coloff);
+  H2D(o_tileblk, tileblk); H2D(o_tilefirst, tilefirst); H2D(o_byoff, byoff);
+  H2D(o_brow0, brow0); H2D(o_bcol0, bcol0); H2D(o_bnb, bnb); H2D(o_bmb, bmb);
+  H2D(o_bldy, bldy); H2D(o_brpw, brpw); H2D(o_bnct, bnct);
+#undef H2D
+  if (e == hipSuccess) e = h2d(P.o_blkld, P.ld.data(), P.ld.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + P.o_Yb, 0, sizeof(float) * (size_t)P.n * P.LDtot, st);
+  if (e == hipSuccess && P.with_w)
+    e = hipMemsetAsync(c->ws + P.o_Wb, 0, sizeof(float) * (size_t)P.n * P.LDtot, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_flag), 4, 0, st);
+  if (e == hipSuccess)
+    e = gmf::launch_permute_y(Y, y_dtype == GMF_Y_INT32, W, P.n, P.m, c->at<int>(P.o_rowblk),
+                              c->at<int>(P.o_rowloc), c->at<int>(P.o_colblk),
+                              c->at<int>(P.o_colloc), c->at<int64_t>(P.o_blkrowbase),
+                              c->at<int>(P.o_blknrows), c->at<int64_t>(P.o_blkcoloff),
+                              c->at<int>(P.o_blkld), c->at<float>(P.o_Yb),
+                              P.with_w ? c->at<float>(P.o_Wb) : nullptr, c->at<int>(P.o_flag), st);
+  if (e == hipSuccess)
+    e = gmf::launch_pack_panel(X, P.p, A0, P.q, U0, P.d, c->at<int>(P.o_rowperm), P.n, P.KP,
+                               c->at<float>(P.o_Prow), st);
+  if (e == hipSuccess)
+    e = gmf::launch_pack_panel(B0, P.p, Z, P.q, V0, P.d, c->at<int>(P.o_colperm), P.m, P.KP,
+                               c->at<float>(P.o_Pcol), st);
+  for (size_t off : {P.o_Grow, P.o_Hrow})
+    if (e == hipSuccess) e = gmf::launch_fill_f64(c->at<double>(off), P.n * P.KU, 0.0, st);
+  for (size_t off : {P.o_Gcol, P.o_Hcol})
+    if (e == hipSuccess) e = gmf::launch_fill_f64(c->at<double>(off), P.m * P.KV, 0.0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_f64(c->at<double>(P.o_devring), kDevRing, 0.0, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(GMF_EDEVICE, std::string("gmf_init: ") + hipGetErrorString(e));
+  }
+  const int rc = check_flag(c);
+  if (rc != GMF_OK) {
+    delete c;
+    return rc;
+  }
+  *ctx_out = c;
+  return GMF_OK;
+}
+
+int gmf_step(void* ctx, int64_t nsteps) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(GMF_EINVAL, "nsteps < 0");
+  return enqueue_steps(as_ctx(ctx), nsteps);
+}
+
+int gmf_deviance(void* ctx, double* total_host, double* penalized_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  return compute_deviance(as_ctx(ctx), total_host, penalized_host);
+}
+
+int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
+            double* dev_trace_host, int32_t* epochs_done_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  if (max_epochs < 0 || eval_every < 1) return fail(GMF_EINVAL, "bad max_epochs / eval_every");
+  Ctx* c = as_ctx(ctx);
+  const int64_t per_epoch = (int64_t)c->P.R * c->P.S;
+  double prev = NAN;
+  int ntrace = 0;
+  int done = 0;
+  bool conv = false;
+  for (int e = 1; e <= max_epochs; ++e) {
+    int rc = enqueue_steps(c, per_epoch);
+    if (rc != GMF_OK) return rc;
+    done = e;
+    if (e % eval_every == 0) {
+      double dev = 0;
+      rc = compute_deviance(c, &dev, nullptr);
+      if (rc != GMF_OK) {
+        if (epochs_done_host) *epochs_done_host = done;
+        return rc;
+      }
+      if (dev_trace_host) dev_trace_host[ntrace] = dev;
+      ++ntrace;
+      if (tol > 0 && std::isfinite(prev) && std::fabs(prev - dev) <= tol * std::fabs(dev)) {
+        conv = true;
+        break;
+      }
+      prev = dev;
+    }
+  }
+  if (epochs_done_host) *epochs_done_host = done;
+  const int rc = check_flag(c);
+  if (rc != GMF_OK) return rc;
+  if (tol > 0 && !conv) return fail(GMF_ENOTCONV, "tolerance not met within max_epochs");
+  return GMF_OK;
+}
+
+int gmf_block_deviance(void* ctx, double* out_host, int64_t count) {
+  if (!ctx || !out_host) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (count < 0 || count > c->t || count > kDevRing) return fail(GMF_EINVAL, "bad count");
+  std::vector<double> ring(kDevRing);
+  HIP_TRY(hipMemcpyAsync(ring.data(), c->at<double>(c->P.o_devring), sizeof(double) * kDevRing,
+                         hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t t = c->t - count + 1 + k;
+    out_host[k] = ring[(t - 1) % kDevRing];
+  }
+  return check_flag(c);
+}
+
+int gmf_get_params(void* ctx, float* B, float* A, float* U, float* V, int32_t postprocess) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  if (postprocess) {
+    gmf::PostArgs a;
+    a.Prow = c->at<float>(P.o_Prow);
+    a.Pcol = c->at<float>(P.o_Pcol);
+    a.n = P.n; a.m = P.m; a.p = P.p; a.q = P.q; a.d = P.d; a.KP = P.KP;
+    a.row_perm = c->at<int>(P.o_rowperm);
+    a.col_perm = c->at<int>(P.o_colperm);
+    a.gram_part = c->at<double>(P.o_post);
+    a.small = nullptr;
+    a.first_nz = c->at<int>(P.o_firstnz);
+    a.err_flag = c->at<int>(P.o_flag);
+    a.B = B; a.A = A; a.U = U; a.V = V;
+    a.nblocks_row = kSumsqBlocks;
+    a.nblocks_col = kSumsqBlocks;
+    HIP_TRY(gmf::launch_postprocess(a, c->st));
+    return check_flag(c);
+  }
+  const int* rp = c->at<int>(P.o_rowperm);
+  const int* cp = c->at<int>(P.o_colperm);
+  HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, cp, P.m, 0, P.p, B, c->st));
+  HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Prow), P.KP, rp, P.n, P.p, P.q, A, c->st));
+  HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Prow), P.KP, rp, P.n, P.p + P.q, P.d, U, c->st));
+  HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, cp, P.m, P.p + P.q, P.d, V, c->st));
+  return check_flag(c);
+}
+
+int gmf_set_params(void* ctx, const float* B, const float* A, const float* U, const float* V) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  if (!U || !V || (P.p > 0 && !B) || (P.q > 0 && !A)) return fail(GMF_EINVAL, "missing array");
+  // The covariates are kept: read them back out of the panels first.
+  // Packing rewrites whole rows, so stage X and Z through the panel itself:
+  // pack only the parameter columns by unpacking X/Z into scratch.
+  float* scratch = reinterpret_cast<float*>(c->at<double>(P.o_post));
+  const size_t need = (size_t)std::max<int64_t>(P.n * P.p, P.m * P.q);
+  if (need * sizeof(float) > sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks))
+    return fail(GMF_EINVAL, "internal: scratch too small");
+  const int* rp = c->at<int>(P.o_rowperm);
+  const int* cp = c->at<int>(P.o_colperm);
+  if (P.p > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Prow), P.KP, rp, P.n, 0, P.p, scratch, c->st));
+  HIP_TRY(gmf::launch_pack_panel(scratch, P.p, A, P.q, U, P.d, rp, P.n, P.KP, c->at<float>(P.o_Prow), c->st));
+  if (P.q > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, cp, P.m, P.p, P.q, scratch, c->st));
+  HIP_TRY(gmf::launch_pack_panel(B, P.p, scratch, P.q, V, P.d, cp, P.m, P.KP, c->at<float>(P.o_Pcol), c->st));
+  return check_flag(c);
+}
+
+int gmf_get_moments(void* ctx, double* Grow, double* Hrow, double* Gcol, double* Hcol) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  const int* rp = c->at<int>(P.o_rowperm);
+  const int* cp = c->at<int>(P.o_colperm);
+  HIP_TRY(gmf::launch_unpack_moments(c->at<double>(P.o_Grow), P.KU, rp, P.n, Grow, c->st));
+  HIP_TRY(gmf::launch_unpack_moments(c->at<double>(P.o_Hrow), P.KU, rp, P.n, Hrow, c->st));
+  HIP_TRY(gmf::launch_unpack_moments(c->at<double>(P.o_Gcol), P.KV, cp, P.m, Gcol, c->st));
+  HIP_TRY(gmf::launch_unpack_moments(c->at<double>(P.o_Hcol), P.KV, cp, P.m, Hcol, c->st));
+  return check_flag(c);
+}
+
+int gmf_get_schedule(void* ctx, int32_t* row_perm_host, int32_t* col_perm_host,
+                     int64_t t_first, int64_t count, int32_t* r_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  if (row_perm_host) std::memcpy(row_perm_host, c->row_perm.data(), sizeof(int) * c->P.n);
+  if (col_perm_host) std::memcpy(col_perm_host, c->col_perm.data(), sizeof(int) * c->P.m);
+  if (r_host) {
+    if (t_first < 1 || count < 0) return fail(GMF_EINVAL, "t_first must be >= 1, count >= 0");
+    for (int64_t k = 0; k < count; ++k) r_host[k] = row_block_of_step(c, t_first + k);
+  }
+  return GMF_OK;
+}
+
+int gmf_schedule_host(uint64_t seed, int64_t n, int64_t m, int32_t R, int64_t t_first,
+                      int64_t count, int32_t* row_perm_host, int32_t* col_perm_host,
+                      int32_t* r_host) {
+  if (n < 0 || m < 0 || R < 1 || count < 0 || (r_host && t_first < 1))
+    return fail(GMF_EINVAL, "bad schedule arguments");
+  if (row_perm_host) {
+    const std::vector<int> rp = shuffle(seed, 0, n);
+    std::memcpy(row_perm_host, rp.data(), sizeof(int) * n);
+  }
+  if (col_perm_host) {
+    const std::vector<int> cp = shuffle(seed, 1, m);
+    std::memcpy(col_perm_host, cp.data(), sizeof(int) * m);
+  }
+  if (r_host) {
+    const uint64_t x0 = stream_start(seed, 2);
+    for (int64_t k = 0; k < count; ++k)
+      r_host[k] = (int)below(stream_draw(x0, (uint64_t)(t_first + k - 1)), (uint64_t)R);
+  }
+  return GMF_OK;
+}
+
+int64_t gmf_steps_done(void* ctx) { return ctx ? as_ctx(ctx)->t : -1; }
+
+int gmf_sync(void* ctx) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  return check_flag(as_ctx(ctx));
+}
+
+void gmf_destroy(void* ctx) { delete as_ctx(ctx); }
+
+}  // extern "C"

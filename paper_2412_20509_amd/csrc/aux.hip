@@ -1,0 +1,302 @@
+// Set-up, copy-out and monitoring kernels of libgmf (gfx950).
+//
+//  * permute_y_kernel: copies Y (and W) into the block-major permuted layout,
+//    so that every block I_r x J_s is one dense rectangle (row stride padded to
+//    a multiple of 4 floats).  Counts become float32 (exact below 2^24).
+//  * pack/unpack panel kernels: [X|Gamma|U] and [B|Z|V] panels in permuted
+//    order <-> caller arrays in original order.
+//  * deviance_kernel: full deviance sum_ij w D(y, mu) of the current iterate
+//    (definition after eq. 2; Supplementary Table 1; Appendix A for NB), eta on
+//    the float32 matrix cores, per-entry deviance in float32, float64
+//    accumulation in a fixed order (per-tile partials, then one ordered sum).
+#include <hip/hip_runtime.h>
+
+#include "family.hpp"
+#include "gmf_kernels.hpp"
+
+namespace gmf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ permute Y ----
+struct PermuteTables {
+  const int* row_block;        // original row i -> block r
+  const int* row_local;        // original row i -> row inside the block
+  const int* col_block;        // original col j -> block s
+  const int* col_local;        // original col j -> col inside the block
+  const int64_t* blk_row_base; // r -> offset of the first element of row block r
+  const int* blk_nrows;        // r -> |I_r|
+  const int64_t* blk_col_off;  // s -> padded column offset of J_s
+  const int* blk_ld;           // s -> padded width of J_s
+};
+
+__global__ void permute_y_kernel(const void* Y, int y_is_int, const float* W,
+                                 int64_t n, int64_t m, PermuteTables t,
+                                 float* Yb, float* Wb, int* err_flag) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m) return;
+  const int64_t i = idx / m;
+  const int64_t j = idx % m;
+  float y;
+  if (y_is_int) {
+    const int v = static_cast<const int*>(Y)[idx];
+    if (v < 0 || v >= (1 << 24)) atomicOr(err_flag, 2);
+    y = (float)v;
+  } else {
+    y = static_cast<const float*>(Y)[idx];
+    if (!isfinite(y)) atomicOr(err_flag, 2);
+  }
+  const int r = t.row_block[i];
+  const int s = t.col_block[j];
+  const int64_t dst = t.blk_row_base[r] + (int64_t)t.blk_nrows[r] * t.blk_col_off[s] +
+                      (int64_t)t.row_local[i] * t.blk_ld[s] + t.col_local[j];
+  Yb[dst] = y;
+  if (W) {
+    const float w = W[idx];
+    if (!(w > 0.f) || !isfinite(w)) atomicOr(err_flag, 2);
+    Wb[dst] = w;
+  }
+}
+
+hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t n,
+                            int64_t m, const int* row_block, const int* row_local,
+                            const int* col_block, const int* col_local,
+                            const int64_t* blk_row_base, const int* blk_nrows,
+                            const int64_t* blk_col_off, const int* blk_ld, float* Yb,
+                            float* Wb, int* err_flag, hipStream_t s) {
+  PermuteTables t{row_block, row_local, col_block, col_local,
+                  blk_row_base, blk_nrows, blk_col_off, blk_ld};
+  const int64_t tot = n * m;
+  const int64_t grid = (tot + 255) / 256;
+  hipLaunchKernelGGL(permute_y_kernel, dim3((unsigned)grid), dim3(256), 0, s, Y,
+                     y_is_int, W, n, m, t, Yb, Wb, err_flag);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- panels ---------
+__global__ void pack_panel_kernel(const float* M0, int c0, const float* M1, int c1,
+                                  const float* M2, int c2, const int* perm,
+                                  int64_t rows, int KP, float* P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * KP) return;
+  const int64_t ip = idx / KP;
+  const int c = (int)(idx % KP);
+  const int64_t io = perm[ip];
+  float v = 0.f;
+  if (c < c0) v = M0[io * c0 + c];
+  else if (c < c0 + c1) v = M1[io * c1 + (c - c0)];
+  else if (c < c0 + c1 + c2) v = M2[io * c2 + (c - c0 - c1)];
+  P[idx] = v;
+}
+
+hipError_t launch_pack_panel(const float* M0, int c0, const float* M1, int c1,
+                             const float* M2, int c2, const int* perm, int64_t rows,
+                             int KP, float* P, hipStream_t s) {
+  const int64_t tot = rows * KP;
+  hipLaunchKernelGGL(pack_panel_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256),
+                     0, s, M0, c0, M1, c1, M2, c2, perm, rows, KP, P);
+  return hipGetLastError();
+}
+
+__global__ void unpack_panel_kernel(const float* P, int KP, const int* perm,
+                                    int64_t rows, int col0, int ncols, float* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ncols) return;
+  const int64_t ip = idx / ncols;
+  const int c = (int)(idx % ncols);
+  out[(int64_t)perm[ip] * ncols + c] = P[ip * KP + col0 + c];
+}
+
+hipError_t launch_unpack_panel(const float* P, int KP, const int* perm, int64_t rows,
+                               int col0, int ncols, float* out, hipStream_t s) {
+  if (ncols <= 0 || rows <= 0 || !out) return hipSuccess;
+  const int64_t tot = rows * ncols;
+  hipLaunchKernelGGL(unpack_panel_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256),
+                     0, s, P, KP, perm, rows, col0, ncols, out);
+  return hipGetLastError();
+}
+
+__global__ void unpack_moments_kernel(const double* M, int K, const int* perm,
+                                      int64_t rows, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * K) return;
+  const int64_t ip = idx / K;
+  const int c = (int)(idx % K);
+  out[(int64_t)perm[ip] * K + c] = M[idx];
+}
+
+hipError_t launch_unpack_moments(const double* M, int K, const int* perm, int64_t rows,
+                                 double* out, hipStream_t s) {
+  if (K <= 0 || rows <= 0 || !out) return hipSuccess;
+  const int64_t tot = rows * K;
+  hipLaunchKernelGGL(unpack_moments_kernel, dim3((unsigned)((tot + 255) / 256)),
+                     dim3(256), 0, s, M, K, perm, rows, out);
+  return hipGetLastError();
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t count, double v) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) p[idx] = v;
+}
+__global__ void fill_i32_kernel(int* p, int64_t count, int v) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) p[idx] = v;
+}
+hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256),
+                     0, s, p, count, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256),
+                     0, s, p, count, v);
+  return hipGetLastError();
+}
+
+// Sum of squares of columns [col0, col0+ncols) of a panel: per-block partials.
+__global__ void sumsq_kernel(const float* P, int KP, int64_t rows, int col0, int ncols,
+                             double* partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const int64_t tot = rows * ncols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / ncols;
+    const int c = (int)(idx % ncols);
+    const double x = (double)P[r * KP + col0 + c];
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_sumsq(const float* P, int KP, int64_t rows, int col0, int ncols,
+                        double* partial, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks), dim3(256), 0, s, P, KP, rows, col0,
+                     ncols, partial);
+  return hipGetLastError();
+}
+
+// Ordered sum of `count` doubles by one workgroup (fixed assignment and tree).
+__global__ void sum_partials_kernel(const double* partial, int count, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_sum_partials(const double* partial, int count, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, count, out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- deviance --
+// One workgroup per (block, row range, column strip) of the step tiling; the
+// same 32x32 pieces and MFMA operand layout as the step kernel, float32 only.
+template <int FAM, int KP>
+__global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
+  __shared__ float sP[kRowGroup][KP + 4];
+  __shared__ double sDev[kTileWaves];
+  const int tile = blockIdx.x;
+  const int blk = a.tile_block[tile];
+  const int local = tile - a.tile_first[blk];
+  const int n_b = a.blk_nb[blk], m_b = a.blk_mb[blk];
+  const int ldy = a.blk_ldy[blk];
+  const int n_ct = a.blk_nct[blk];
+  const int rpw = a.blk_rpw[blk];
+  const float* Y = a.Y + a.blk_yoff[blk];
+  const float* W = a.W ? a.W + a.blk_yoff[blk] : nullptr;
+  const float* Prow = a.Prow + (int64_t)a.blk_row0[blk] * KP;
+  const float* Pcol = a.Pcol + (int64_t)a.blk_col0[blk] * KP;
+  const int ct = local % n_ct, rr = local / n_ct;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
+  const int colw = ct * kTileCols + wave * kWaveCols;
+
+  float pa[2][KP / 4];
+  for (int c = 0; c < 2; ++c) {
+    const int col = colw + 16 * c + l16;
+    for (int kk = 0; kk < KP / 4; ++kk)
+      pa[c][kk] = (col < m_b) ? Pcol[(int64_t)col * KP + 4 * kk + g] : 0.f;
+  }
+  double acc = 0.0;
+  for (int rg = row0; rg < row_end; rg += kRowGroup) {
+    __syncthreads();
+    for (int idx = tid; idx < kRowGroup * (KP / 4); idx += kTileThreads) {
+      const int r = idx / (KP / 4), c4 = idx % (KP / 4);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (rg + r < n_b) v = reinterpret_cast<const float4*>(Prow + (int64_t)(rg + r) * KP)[c4];
+      sP[r][4 * c4 + 0] = v.x; sP[r][4 * c4 + 1] = v.y;
+      sP[r][4 * c4 + 2] = v.z; sP[r][4 * c4 + 3] = v.w;
+    }
+    __syncthreads();
+    for (int R = 0; R < 2; ++R) {
+      const int row = rg + 16 * R + l16;
+      for (int C = 0; C < 2; ++C) {
+        // every lane takes part in the MFMA; masking happens afterwards
+        floatx4 e = {0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < KP / 4; ++kk)
+          e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], sP[16 * R + l16][4 * kk + g],
+                                                   e, 0, 0, 0);
+        const int colb = colw + 16 * C + 4 * g;
+        if (row < n_b && colb < ldy) {
+          const float4 y4 = *reinterpret_cast<const float4*>(Y + (int64_t)row * ldy + colb);
+          float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
+          if (W) w4 = *reinterpret_cast<const float4*>(W + (int64_t)row * ldy + colb);
+          const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+          const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+          for (int v = 0; v < 4; ++v) {
+            if (colb + v < m_b) {
+              float x1, x2, dv = 0.f;
+              family_entry<FAM>(e[v], ys[v], ws[v], a.f, true, x1, x2, dv);
+              acc += (double)dv;
+            }
+          }
+        }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) sDev[wave] = acc;
+  __syncthreads();
+  if (tid == 0) a.partial[tile] = ((sDev[0] + sDev[1]) + sDev[2]) + sDev[3];
+}
+
+template <int FAM>
+static hipError_t launch_dev_kp(int KP, const DevArgs& a, hipStream_t s) {
+  const dim3 grid(a.n_tiles), block(kTileThreads);
+  switch (KP) {
+    case 16: hipLaunchKernelGGL((deviance_kernel<FAM, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((deviance_kernel<FAM, 32>), grid, block, 0, s, a); break;
+    case 48: hipLaunchKernelGGL((deviance_kernel<FAM, 48>), grid, block, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((deviance_kernel<FAM, 64>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s) {
+  switch (fam) {
+    case kPoisson: return launch_dev_kp<kPoisson>(KP, a, s);
+    case kNegBin: return launch_dev_kp<kNegBin>(KP, a, s);
+    case kGaussian: return launch_dev_kp<kGaussian>(KP, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gmf

@@ -1,0 +1,336 @@
+"""ctypes binding of libgmf (include/gmf.h).
+
+The functions here only marshal arguments: every step of the computation runs
+in the HIP kernels of libgmf.so.  PyTorch provides device memory and the
+stream.  Importing this module raises if the shared library is missing; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmf.so")
+
+GMF_OK, GMF_EINVAL, GMF_EWORKSPACE, GMF_EDEVICE, GMF_ENUMERIC, GMF_ENOTCONV = 0, -1, -2, -3, -4, -5
+GMF_POISSON, GMF_NEGBIN, GMF_GAUSSIAN = 0, 1, 2
+GMF_LINK_LOG, GMF_LINK_IDENTITY = 0, 1
+GMF_PREC_FP32, GMF_PREC_BF16 = 0, 1
+GMF_Y_INT32, GMF_Y_FLOAT32 = 0, 1
+
+FAMILY_CODES = {"poisson": GMF_POISSON, "negbin": GMF_NEGBIN, "gaussian": GMF_GAUSSIAN}
+LINK_CODES = {"log": GMF_LINK_LOG, "identity": GMF_LINK_IDENTITY}
+PREC_CODES = {"fp32": GMF_PREC_FP32, "bf16": GMF_PREC_BF16}
+
+
+class gmf_config(C.Structure):
+    _fields_ = [
+        ("family", C.c_int32), ("link", C.c_int32), ("precision", C.c_int32),
+        ("bias_mode", C.c_int32),
+        ("n", C.c_int64), ("m", C.c_int64),
+        ("d", C.c_int32), ("p", C.c_int32), ("q", C.c_int32),
+        ("R", C.c_int32), ("S", C.c_int32),
+        ("phi", C.c_double), ("nb_alpha", C.c_double),
+        ("lambda_", C.c_double * 4),
+        ("rate0", C.c_double), ("decay", C.c_double), ("tau", C.c_double),
+        ("alpha1", C.c_double), ("alpha2", C.c_double),
+        ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+class GMFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libgmf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgmf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libgmf.so not found at {path}: build it with "
+                          f"`python -m paper_2412_20509_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    cfgp = C.POINTER(gmf_config)
+    sig = {
+        "gmf_config_default": (None, [cfgp]),
+        "gmf_workspace_bytes": (C.c_size_t, [cfgp, i32]),
+        "gmf_init": (C.c_int, [C.POINTER(vp), cfgp, vp, C.c_size_t, vp, vp, i32, vp, vp,
+                               vp, vp, vp, vp, vp]),
+        "gmf_step": (C.c_int, [vp, i64]),
+        "gmf_fit": (C.c_int, [vp, i32, C.c_double, i32, f64p, C.POINTER(i32)]),
+        "gmf_deviance": (C.c_int, [vp, f64p, f64p]),
+        "gmf_block_deviance": (C.c_int, [vp, f64p, i64]),
+        "gmf_get_params": (C.c_int, [vp, vp, vp, vp, vp, i32]),
+        "gmf_set_params": (C.c_int, [vp, vp, vp, vp, vp]),
+        "gmf_get_moments": (C.c_int, [vp, vp, vp, vp, vp]),
+        "gmf_get_schedule": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), i64, i64,
+                                       C.POINTER(i32)]),
+        "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
+                                        C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_steps_done": (i64, [vp]),
+        "gmf_sync": (C.c_int, [vp]),
+        "gmf_destroy": (None, [vp]),
+        "gmf_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != GMF_OK:
+        raise GMFError(rc, load_library().gmf_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# --------------------------------------------------------------- C ABI ----
+
+def gmf_config_default() -> gmf_config:
+    cfg = gmf_config()
+    load_library().gmf_config_default(C.byref(cfg))
+    return cfg
+
+
+def gmf_workspace_bytes(cfg: gmf_config, with_weights: bool = False) -> int:
+    return load_library().gmf_workspace_bytes(C.byref(cfg), int(with_weights))
+
+
+def gmf_init(cfg, workspace, stream, Y, y_dtype, X, Z, W, B0, A0, U0, V0):
+    ctx = C.c_void_p()
+    _check(load_library().gmf_init(C.byref(ctx), C.byref(cfg), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), stream,
+                                   _ptr(Y), y_dtype, _ptr(X), _ptr(Z), _ptr(W), _ptr(B0),
+                                   _ptr(A0), _ptr(U0), _ptr(V0)))
+    return ctx
+
+
+def gmf_step(ctx, nsteps: int):
+    return _check(load_library().gmf_step(ctx, int(nsteps)))
+
+
+def gmf_fit(ctx, max_epochs: int, tol: float = 0.0, eval_every: int = 1):
+    n_eval = max(1, max_epochs // eval_every)
+    trace = (C.c_double * n_eval)()
+    done = C.c_int32(0)
+    rc = load_library().gmf_fit(ctx, int(max_epochs), float(tol), int(eval_every), trace,
+                                C.byref(done))
+    if rc not in (GMF_OK, GMF_ENOTCONV):
+        _check(rc)
+    k = done.value // eval_every
+    return rc, list(trace)[:k], done.value
+
+
+def gmf_deviance(ctx):
+    tot, pen = C.c_double(), C.c_double()
+    _check(load_library().gmf_deviance(ctx, C.byref(tot), C.byref(pen)))
+    return tot.value, pen.value
+
+
+def gmf_block_deviance(ctx, count: int):
+    out = (C.c_double * count)()
+    _check(load_library().gmf_block_deviance(ctx, out, int(count)))
+    return np.array(list(out))
+
+
+def gmf_get_params(ctx, B, A, U, V, postprocess: int = 0):
+    return _check(load_library().gmf_get_params(ctx, _ptr(B), _ptr(A), _ptr(U), _ptr(V),
+                                                 int(postprocess)))
+
+
+def gmf_set_params(ctx, B, A, U, V):
+    return _check(load_library().gmf_set_params(ctx, _ptr(B), _ptr(A), _ptr(U), _ptr(V)))
+
+
+def gmf_get_moments(ctx, Grow, Hrow, Gcol, Hcol):
+    return _check(load_library().gmf_get_moments(ctx, _ptr(Grow), _ptr(Hrow), _ptr(Gcol),
+                                                  _ptr(Hcol)))
+
+
+def gmf_get_schedule(ctx, n: int, m: int, t_first: int = 1, count: int = 0):
+    rp = (C.c_int32 * n)()
+    cp = (C.c_int32 * m)()
+    rr = (C.c_int32 * max(count, 1))()
+    _check(load_library().gmf_get_schedule(ctx, rp, cp, int(t_first), int(count), rr))
+    return np.array(rp), np.array(cp), np.array(rr)[:count]
+
+
+def gmf_schedule_host(seed: int, n: int, m: int, R: int, t_first: int = 1, count: int = 0):
+    rp = (C.c_int32 * max(n, 1))()
+    cp = (C.c_int32 * max(m, 1))()
+    rr = (C.c_int32 * max(count, 1))()
+    _check(load_library().gmf_schedule_host(seed, n, m, R, t_first, count, rp, cp, rr))
+    return np.array(rp)[:n], np.array(cp)[:m], np.array(rr)[:count]
+
+
+def gmf_steps_done(ctx) -> int:
+    return load_library().gmf_steps_done(ctx)
+
+
+def gmf_sync(ctx):
+    return _check(load_library().gmf_sync(ctx))
+
+
+def gmf_destroy(ctx):
+    load_library().gmf_destroy(ctx)
+
+
+# ---------------------------------------------------- torch convenience ----
+
+@dataclass
+class FitConfig:
+    family: str = "poisson"
+    link: str = "log"
+    precision: str = "fp32"
+    d: int = 1
+    R: int = 10
+    S: int = 5
+    phi: float = 1.0
+    nb_alpha: float = 5.0
+    lam: tuple = (0.0, 0.0, 1.0, 1.0)
+    rate0: float = 0.05
+    decay: float = 0.05
+    tau: float = 0.75
+    alpha1: float = 0.1
+    alpha2: float = 0.01
+    damping: float = 1e-3
+    eps: float = 1e-8
+    eta_max: float = 30.0
+    bias_mode: int = 0
+    seed: int = 0
+
+    def to_c(self, n, m, p, q) -> gmf_config:
+        c = gmf_config_default()
+        c.family = FAMILY_CODES[self.family]
+        c.link = LINK_CODES[self.link]
+        c.precision = PREC_CODES[self.precision]
+        c.bias_mode = self.bias_mode
+        c.n, c.m, c.d, c.p, c.q = n, m, self.d, p, q
+        c.R, c.S = self.R, self.S
+        c.phi, c.nb_alpha = self.phi, self.nb_alpha
+        for i in range(4):
+            c.lambda_[i] = self.lam[i]
+        c.rate0, c.decay, c.tau = self.rate0, self.decay, self.tau
+        c.alpha1, c.alpha2 = self.alpha1, self.alpha2
+        c.damping, c.eps, c.eta_max = self.damping, self.eps, self.eta_max
+        c.seed = self.seed
+        return c
+
+
+class GMF:
+    """Owns a libgmf context, its workspace tensor and the device inputs."""
+
+    def __init__(self, fc: FitConfig, Y, X, Z, B0, A0, U0, V0, W=None, device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        self.device = dev
+        n, m = Y.shape
+        p = X.shape[1] if X is not None else 0
+        q = Z.shape[1] if Z is not None else 0
+        self.n, self.m, self.p, self.q, self.d = n, m, p, q, fc.d
+        self.cfg = fc.to_c(n, m, p, q)
+        nbytes = gmf_workspace_bytes(self.cfg, W is not None)
+        if nbytes == 0:
+            raise GMFError(GMF_EINVAL, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+
+        def f32(a, shape):
+            if a is None or (hasattr(a, "size") and np.size(a) == 0):
+                return None
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32).reshape(shape),
+                                   device=dev)
+
+        if np.issubdtype(np.asarray(Y).dtype, np.integer):
+            Yt = torch.as_tensor(np.ascontiguousarray(Y, dtype=np.int32), device=dev)
+            ydt = GMF_Y_INT32
+        else:
+            Yt = torch.as_tensor(np.ascontiguousarray(Y, dtype=np.float32), device=dev)
+            ydt = GMF_Y_FLOAT32
+        Xt, Zt = f32(X, (n, p)), f32(Z, (m, q))
+        Wt = f32(W, (n, m))
+        B0t, A0t = f32(B0, (m, p)), f32(A0, (n, q))
+        U0t, V0t = f32(U0, (n, fc.d)), f32(V0, (m, fc.d))
+        self.ctx = gmf_init(self.cfg, self._ws, self.stream.cuda_stream, Yt, ydt, Xt, Zt, Wt,
+                            B0t, A0t, U0t, V0t)
+
+    # thin forwards -------------------------------------------------------
+    def step(self, nsteps=1):
+        gmf_step(self.ctx, nsteps)
+
+    def fit(self, max_epochs, tol=0.0, eval_every=1):
+        return gmf_fit(self.ctx, max_epochs, tol, eval_every)
+
+    def deviance(self):
+        return gmf_deviance(self.ctx)
+
+    def block_deviance(self, count):
+        return gmf_block_deviance(self.ctx, count)
+
+    def params(self, postprocess=0):
+        t = self.torch
+        mk = lambda r, c: t.empty((r, c), dtype=t.float32, device=self.device) if c > 0 else None
+        B, A, U, V = mk(self.m, self.p), mk(self.n, self.q), mk(self.n, self.d), mk(self.m, self.d)
+        gmf_get_params(self.ctx, B, A, U, V, postprocess)
+        self.stream.synchronize()
+        cv = lambda x, r: np.zeros((r, 0)) if x is None else x.double().cpu().numpy()
+        return cv(B, self.m), cv(A, self.n), cv(U, self.n), cv(V, self.m)
+
+    def moments(self):
+        t = self.torch
+        ku, kv = self.q + self.d, self.p + self.d
+        out = [t.empty((r, c), dtype=t.float64, device=self.device)
+               for r, c in ((self.n, ku), (self.n, ku), (self.m, kv), (self.m, kv))]
+        gmf_get_moments(self.ctx, *out)
+        self.stream.synchronize()
+        return [o.cpu().numpy() for o in out]
+
+    def set_params(self, B, A, U, V):
+        t = self.torch
+        conv = lambda a, r, c: (t.as_tensor(np.ascontiguousarray(a, np.float32).reshape(r, c),
+                                            device=self.device) if c > 0 else None)
+        gmf_set_params(self.ctx, conv(B, self.m, self.p), conv(A, self.n, self.q),
+                       conv(U, self.n, self.d), conv(V, self.m, self.d))
+
+    def schedule(self, t_first=1, count=0):
+        return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)
+
+    def steps_done(self):
+        return gmf_steps_done(self.ctx)
+
+    def sync(self):
+        gmf_sync(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            gmf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,226 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (norm-wise relative error, max|x - ref| / max|ref|):
+  * FP32 path, one step from an identical state: 1e-5 on every output array
+    (parameters, the four moment arrays, the block deviance).
+  * FP32 path, trajectories of many steps: 2e-4 (float32 rounding of the
+    parameters compounds through the iteration).
+  * Full deviance of a fixed state: 1e-6 (float32 per-entry deviance,
+    float64 sums).
+  * Final deviance after several epochs: 1e-4.
+  * BF16 path: errors are reported per output; the final deviance is gated
+    at 1e-3 relative on the small Poisson case.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gmf_oracle as G
+from synth import gen_gaussian_lowrank, gen_nb, gen_poisson_small, gen_tiny
+
+from tests.gpu_helpers import compare_state, gpu_for, oracle_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_20509_amd import gmf  # noqa: F401  raises if libgmf.so is missing
+
+
+def _one_step_case(pr, **over):
+    o = oracle_for(pr, **over)
+    g = gpu_for(pr, **over)
+    dev_o = o.step()
+    g.step(1)
+    dev_g = g.block_deviance(1)[0]
+    errs = compare_state(g, o, 1e-5, pr.name)
+    assert rel_err([dev_g], [dev_o]) <= 1e-5, (dev_g, dev_o)
+    g.close()
+    return errs
+
+
+def test_first_step_poisson_c1():
+    pr = gen_poisson_small()
+    say("first step poisson c1 1000x500 d5")
+    _one_step_case(pr)
+
+
+@pytest.mark.parametrize("family", ["poisson", "negbin", "gaussian"])
+def test_first_step_tiny_with_covariates_and_weights(family):
+    pr = gen_tiny(family, n=37, m=23, d=3, p=2, q=2, R=4, S=3, weights=True)
+    say(f"first step tiny {family} 37x23 weights")
+    _one_step_case(pr, lam=(0.2, 0.3, 0.7, 0.5))
+
+
+@pytest.mark.parametrize("n,m,d,p,q,R,S", [
+    (1000, 700, 5, 1, 1, 3, 2),      # several row ranges and a ragged column strip
+    (517, 389, 12, 3, 1, 2, 3),      # KP 16, ragged everything
+    (300, 260, 30, 3, 1, 2, 2),      # k = 34 -> KP 48
+    (260, 200, 58, 3, 1, 2, 2),      # k = 62 -> KP 64
+    (130, 90, 4, 0, 0, 1, 1),        # no covariates, full batch
+])
+def test_first_step_shapes(n, m, d, p, q, R, S):
+    pr = gen_tiny("negbin", n=n, m=m, d=d, p=max(p, 1), q=max(q, 1), R=R, S=S, seed=1021)
+    if p == 0:
+        pr.p = pr.q = 0
+        pr.X = np.zeros((n, 0)); pr.Z = np.zeros((m, 0))
+        pr.B0 = np.zeros((m, 0)); pr.A0 = np.zeros((n, 0))
+    say(f"first step shape n={n} m={m} d={d} p={p} q={q} R={R} S={S}")
+    _one_step_case(pr)
+
+
+def test_trajectory_one_epoch_c1():
+    pr = gen_poisson_small()
+    say("trajectory c1 one epoch")
+    o = oracle_for(pr)
+    g = gpu_for(pr)
+    devs_o = o.epoch()
+    g.step(pr.R * pr.S)
+    devs_g = g.block_deviance(pr.R * pr.S)
+    compare_state(g, o, 2e-4, "c1 epoch")
+    assert rel_err(devs_g, devs_o) <= 1e-4
+    g.close()
+
+
+def test_trajectory_nb_covariates():
+    pr = gen_nb(n=2000, m=800, d=6, R=4, S=4, seed=1031)
+    say("trajectory nb 2000x800 d6 covariates, 40 steps")
+    o = oracle_for(pr)
+    g = gpu_for(pr)
+    o.steps(40)
+    g.step(40)
+    compare_state(g, o, 2e-4, "nb trajectory")
+    g.close()
+
+
+def test_schedule_of_context_matches_oracle():
+    pr = gen_poisson_small(n=300, m=200, R=7, S=3)
+    say("schedule from context")
+    g = gpu_for(pr)
+    rp, cp, rr = g.schedule(1, 100)
+    o = oracle_for(pr)
+    assert np.array_equal(rp, o.row_perm)
+    assert np.array_equal(cp, o.col_perm)
+    assert rr.tolist() == [o.block_of_step(t)[0] for t in range(1, 101)]
+    g.close()
+
+
+def test_full_deviance_matches_oracle():
+    for pr in (gen_poisson_small(), gen_nb(n=1500, m=700, d=5, R=3, S=2, seed=1032),
+               gen_tiny("gaussian", n=200, m=130, d=4, p=2, q=1, R=2, S=2, weights=True)):
+        say(f"full deviance {pr.name}")
+        o = oracle_for(pr)
+        g = gpu_for(pr)
+        dg, pg = g.deviance()
+        assert rel_err([dg], [o.full_deviance()]) <= 1e-6, (dg, o.full_deviance())
+        assert rel_err([pg], [o.objective()]) <= 1e-6
+        g.close()
+
+
+def test_final_deviance_after_epochs_c1():
+    pr = gen_poisson_small()
+    say("final deviance c1 after 20 epochs")
+    o = oracle_for(pr)
+    g = gpu_for(pr)
+    for _ in range(20):
+        o.epoch()
+    rc, trace, done = g.fit(20, 0.0, 5)
+    assert done == 20 and len(trace) == 4
+    d_o = o.full_deviance()
+    assert abs(trace[-1] - d_o) / d_o <= 1e-4, (trace[-1], d_o)
+    g.close()
+
+
+def test_steps_are_deterministic():
+    pr = gen_nb(n=1200, m=600, d=8, R=3, S=3, seed=1033)
+    say("determinism")
+    outs = []
+    for _ in range(2):
+        g = gpu_for(pr)
+        g.step(25)
+        outs.append(g.params())
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_postprocess_matches_oracle_projection():
+    pr = gen_nb(n=900, m=400, d=5, R=3, S=2, seed=1034)
+    say("postprocess A+B1")
+    g = gpu_for(pr)
+    g.step(30)
+    B, A, U, V = g.params(0)
+    Bp, Ap, Up, Vp = g.params(1)
+    rB, rA, rU, rV = G.postprocess_A_B1(pr.X, pr.Z, B, A, U, V)
+    for name, x, ref in (("B", Bp, rB), ("Gamma", Ap, rA), ("U", Up, rU), ("V", Vp, rV)):
+        assert rel_err(x, ref) <= 2e-5, (name, rel_err(x, ref))
+    # invariants hold on the device result too
+    eta = pr.X @ B.T + A @ pr.Z.T + U @ V.T
+    eta_p = pr.X @ Bp.T + Ap @ pr.Z.T + Up @ Vp.T
+    assert rel_err(eta_p, eta) <= 2e-5
+    np.testing.assert_allclose(Vp.T @ Vp, np.eye(pr.d), atol=2e-5)
+    g.close()
+
+
+def test_bf16_path_reports_errors_and_reaches_oracle_deviance():
+    pr = gen_poisson_small()
+    say("bf16 c1: per-output errors after one epoch, final deviance after 20 epochs")
+    o = oracle_for(pr)
+    g = gpu_for(pr, precision="bf16")
+    o.epoch()
+    g.step(pr.R * pr.S)
+    B, A, U, V = g.params()
+    errs = {"B": rel_err(B, o.B), "Gamma": rel_err(A, o.A), "U": rel_err(U, o.U),
+            "V": rel_err(V, o.V)}
+    print("bf16 one-epoch relative errors:", errs)
+    assert max(errs.values()) < 5e-2
+    for _ in range(19):
+        o.epoch()
+    g.step(19 * pr.R * pr.S)
+    dg, _ = g.deviance()
+    d_o = o.full_deviance()
+    print("bf16 final deviance rel err:", abs(dg - d_o) / d_o)
+    assert abs(dg - d_o) / d_o <= 1e-3
+    g.close()
+
+
+def test_error_paths():
+    from paper_2412_20509_amd.gmf import GMFError, GMF_ENUMERIC, GMF_EINVAL
+    pr = gen_tiny("poisson", n=40, m=30, d=2, R=2, S=2)
+    say("error paths")
+    bad = pr.Y.copy()
+    bad[3, 4] = -1
+    pr2 = gen_tiny("poisson", n=40, m=30, d=2, R=2, S=2)
+    pr2.Y = bad
+    with pytest.raises(GMFError) as ei:
+        gpu_for(pr2)
+    assert ei.value.code == GMF_EINVAL
+    g = gpu_for(pr, rate0=1e38, decay=0.0, damping=0.0)
+    g.step(3)
+    with pytest.raises(GMFError) as ei:
+        g.sync()
+    assert ei.value.code == GMF_ENUMERIC
+    g.close()
+
+
+def test_gaussian_full_batch_reaches_truncated_svd():
+    pr = gen_gaussian_lowrank()
+    say("gaussian full batch -> truncated SVD")
+    g = gpu_for(pr, lam=(0, 0, 0.5, 0.5), rate0=0.5, decay=0.0, alpha1=1.0, alpha2=1.0,
+                damping=0.0)
+    g.step(1500)
+    _, _, U, V = g.params()
+    P, s, Qt = np.linalg.svd(pr.Y, full_matrices=False)
+    M = (P[:, :3] * np.maximum(s[:3] - 0.5, 0)) @ Qt[:3]
+    assert np.linalg.norm(U @ V.T - M) / np.linalg.norm(M) < 1e-5
+    g.close()
