@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Benchmark of block-wise adaptive SGD for GMF on one MI355X.
+
+Workload (the headline configuration): negative binomial GMF (alpha = 5, log
+link), n = 10,000 x m = 2,000, rank d = 10, row covariates X = [1, batch
+indicator, N(0,1)] (p = 3), Z = 1 (q = 1), about 85 % zeros, blocks of 10 % of
+the rows x 20 % of the columns (R = 10, S = 5), plain FP32 path.
+
+One benchmark "step" is one epoch: R*S = 50 block steps of Algorithm 1 (block
+select, eta, inverse link, D1/D2, the four contractions, EMA and step, block
+deviance) followed by one evaluation of the full deviance.  Inputs are resident
+in HBM before the timed region starts.
+
+Printed JSON line:
+  value             epochs/s of the FP32 arm (whole job, one GPU)
+  s_to_1e-4         wall seconds until the full deviance is within 1e-4
+                    (relative) of D*, the FP64 oracle's deviance after 200
+                    epochs of the same seeded schedule (tests/golden)
+  roofline          dominant kernel (the fused tile kernel): algorithmic
+                    bytes per launch / mean launch time from HIP events on the
+                    library's stream, against the 8 TB/s HBM peak
+  cpu_baseline      the FP64 oracle on the host, bounded sample
+  arms              the same measurements for the BF16 arm
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GMF SGD epochs/s + s to 1e-4 rel deviance; BF16/warm vs FP32 plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_target(name):
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_trace_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def make_gmf(pr, precision):
+    from paper_2412_20509_amd.gmf import GMF, FitConfig
+    fc = FitConfig(family=pr.family, link=pr.link, precision=precision, d=pr.d, R=pr.R,
+                   S=pr.S, phi=pr.phi, nb_alpha=pr.nb_alpha, seed=pr.sched_seed)
+    return GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0")
+
+
+def tile_bytes_per_launch(pr):
+    """Algorithmic bytes of one tile-kernel launch: the block's counts (4 B each)
+    plus one read of the block's two panels (p+q+d floats per row/column)."""
+    ns, ms = pr.n / pr.R, pr.m / pr.S
+    return 4.0 * ns * ms + 4.0 * (ns + ms) * pr.k
+
+
+def run_arm(pr, precision, epochs, warmup, dstar, torch):
+    per_epoch = pr.R * pr.S
+    # warm-up on a throwaway context (kernel loading, caches)
+    g = make_gmf(pr, precision)
+    for _ in range(warmup):
+        g.step(per_epoch)
+        g.deviance()
+    g.close()
+    del g
+    torch.cuda.synchronize()
+
+    g = make_gmf(pr, precision)
+    torch.cuda.synchronize()
+    devs = []
+    t_hit = None
+    t0 = time.perf_counter()
+    for e in range(epochs):
+        g.step(per_epoch)
+        dev, _ = g.deviance()          # synchronises
+        devs.append(dev)
+        if t_hit is None and dstar is not None and abs(dev - dstar) <= 1e-4 * dstar:
+            t_hit = time.perf_counter() - t0
+            e_hit = e + 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if t_hit is None:
+        e_hit = None
+
+    # per-kernel timing with HIP events on the library's stream (2 more epochs)
+    g.set_timing(True)
+    for _ in range(2):
+        g.step(per_epoch)
+        g.deviance()
+    tile_ms, upd_ms, nsteps = g.get_timing()
+    g.set_timing(False)
+    t_pp = time.perf_counter()
+    g.params(postprocess=1)
+    t_pp = time.perf_counter() - t_pp
+    final = devs[-1]
+    g.close()
+    return dict(epochs=epochs, wall_s=wall, epochs_per_s=epochs / wall,
+                ms_per_epoch=1e3 * wall / epochs, final_deviance=final,
+                rel_to_oracle=(abs(final - dstar) / dstar) if dstar else None,
+                s_to_1e4=t_hit, epochs_to_1e4=e_hit,
+                tile_ms_mean=tile_ms / max(nsteps, 1), update_ms_mean=upd_ms / max(nsteps, 1),
+                timed_steps=nsteps, postprocess_s=t_pp)
+
+
+def cpu_baseline(pr, epochs=3):
+    from threadpoolctl import threadpool_info
+    from oracle import gmf_oracle as G
+    cfg = G.Config(family=pr.family, link=pr.link, phi=pr.phi, nb_alpha=pr.nb_alpha,
+                   R=pr.R, S=pr.S, seed=pr.sched_seed)
+    o = G.OracleGMF(cfg, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0)
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        o.epoch()
+        o.full_deviance()
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return dict(value=epochs / dt, unit="epochs/s", cores=threads, kind="oracle",
+                sample=f"{epochs} epochs ({epochs * pr.R * pr.S} block steps of "
+                       f"{pr.n // pr.R}x{pr.m // pr.S}, each epoch followed by one full "
+                       f"deviance) of the same {pr.n}x{pr.m} NB workload, FP64 numpy",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed epochs")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed warm-up epochs")
+    ap.add_argument("--arms", default="fp32,bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth import make_problem
+    from paper_2412_20509_amd import gmf as _gmf  # noqa: F401  (fails if not built)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("generating the 10000x2000 NB workload")
+    pr = make_problem("c2")
+    target = load_target("c2")
+    dstar = target["final"] if target else None
+
+    arms = {}
+    for prec in args.arms.split(","):
+        log(f"arm {prec}: {args.warmup} warm-up + {args.steps} timed epochs")
+        arms[prec] = run_arm(pr, prec, args.steps, args.warmup, dstar, torch)
+        log(f"arm {prec}: {arms[prec]['epochs_per_s']:.1f} epochs/s, "
+            f"tile {1e3 * arms[prec]['tile_ms_mean']:.2f} us")
+
+    main_arm = arms.get("fp32") or next(iter(arms.values()))
+    bytes_launch = tile_bytes_per_launch(pr)
+    achieved = bytes_launch / (main_arm["tile_ms_mean"] * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel="tile_kernel<FP32,NB,KP=16>", achieved=achieved,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=None, bytes_per_launch=bytes_launch,
+                mean_launch_us=1e3 * main_arm["tile_ms_mean"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        cpu = cpu_baseline(pr)
+
+    out = dict(
+        metric=METRIC, value=main_arm["epochs_per_s"], unit="epochs/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=main_arm["ms_per_epoch"],
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload="NB GMF 10000x2000, d=10, p=3, q=1, alpha=5, blocks "
+                              "1000x400 (R=10, S=5), FP32 plain path, step = 1 epoch "
+                              "(50 block steps + full deviance)",
+                    n=pr.n, m=pr.m, d=pr.d, p=pr.p, q=pr.q, R=pr.R, S=pr.S,
+                    zero_fraction=float((pr.Y == 0).mean())),
+        s_to_1e4=main_arm["s_to_1e4"], epochs_to_1e4=main_arm["epochs_to_1e4"],
+        oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu,
+        arms={k: {kk: vv for kk, vv in v.items()} for k, v in arms.items()},
+    )
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

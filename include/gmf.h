@@ -177,6 +177,17 @@ int gmf_schedule_host(uint64_t seed, int64_t n, int64_t m, int32_t R, int64_t t_
                       int64_t count, int32_t* row_perm_host, int32_t* col_perm_host,
                       int32_t* r_host);
 
+/* gmf_set_timing -- enable (1) or disable (0) HIP-event timing of the step
+ * launches on the context's stream: each subsequent launch of the step kernel
+ * (one per gmf_step call, or per 8192 steps) is bracketed by events.
+ * gmf_get_timing synchronises and returns, for the launches since the last
+ * call, the summed launch time in milliseconds, the number of launches and
+ * the number of steps they ran, then starts a new window.  Any output may be
+ * NULL. */
+int gmf_set_timing(void* ctx, int32_t enable);
+int gmf_get_timing(void* ctx, double* launch_ms_host, double* launches_host,
+                   int64_t* steps_host);
+
 /* Steps run so far (the global counter t of the last step). */
 int64_t gmf_steps_done(void* ctx);
 

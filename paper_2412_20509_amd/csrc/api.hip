@@ -70,20 +70,28 @@ struct Plan {
   int64_t n = 0, m = 0;
   int R = 0, S = 0, p = 0, q = 0, d = 0, k = 0, KP = 0, KU = 0, KV = 0;
   int prec = 0, fam = 0, with_w = 0;
-  std::vector<int> ro, co, ld, rpw, nrr, nct;
+  std::vector<int> ro, co, ld, rpw, nrr, nct, nrows, mcols;
   std::vector<int64_t> coP;
   int64_t LDtot = 0;
-  int64_t upart_elems = 0, vpart_elems = 0;
-  int max_tiles = 0, dev_tiles = 0;
+  int rr_max = 0, ct_max = 0, nslot = 0;
+  int64_t slot_u = 0, slot_v = 0, slot_dev = 0;
+  int dev_tiles = 0;
   // byte offsets into the workspace
   size_t o_Yb, o_Wb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Gcol, o_Hcol, o_Upart, o_Vpart,
       o_devpart, o_devring, o_flag, o_rowperm, o_colperm, o_rowblk, o_rowloc, o_colblk,
       o_colloc, o_blkrowbase, o_blknrows, o_blkcoloff, o_blkld, o_tileblk, o_tilefirst,
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
-      o_scal, o_sumsq, o_post, o_firstnz, total;
+      o_scal, o_sumsq, o_post, o_firstnz, o_desc, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
+      o_ld, o_nct, o_coP, o_rowver, o_colver, o_arr, o_phase, o_slotgen, o_abort, o_taskctr,
+      total;
 };
 
 constexpr int kDevRing = 4096;
+constexpr int64_t kMaxTimedSteps = 8192;
+constexpr int kDescWindow = 16384;     // steps whose descriptors live on the device
+constexpr int kMaxSlots = 16;
+constexpr int kTilesPerStepTarget = 256;
+constexpr int kSpinLimit = 1 << 22;
 constexpr int kSumsqBlocks = 256;
 
 std::string check_config(const gmf_config* c) {
@@ -130,23 +138,34 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
     nct_max = std::max(nct_max, P.nct[s]);
   }
   P.LDtot = P.coP[P.S];
-  P.rpw.resize(P.R); P.nrr.resize(P.R);
+  P.rpw.resize(P.R); P.nrr.resize(P.R); P.nrows.resize(P.R); P.mcols.resize(P.S);
+  for (int s = 0; s < P.S; ++s) P.mcols[s] = P.co[s + 1] - P.co[s];
   for (int r = 0; r < P.R; ++r) {
     const int nr = P.ro[r + 1] - P.ro[r];
-    int rpw = round_up((int)std::ceil((double)nr * nct_max / 256.0), gmf::kRowGroup);
-    rpw = std::max(gmf::kRowGroup, std::min(rpw, 4096));
+    P.nrows[r] = nr;
+    int rpw = round_up((int)std::ceil((double)nr * nct_max / kTilesPerStepTarget), gmf::kRowGroup);
+    rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
     P.rpw[r] = rpw;
     P.nrr[r] = (nr + rpw - 1) / rpw;
   }
-  P.upart_elems = P.vpart_elems = 0; P.max_tiles = 0; P.dev_tiles = 0;
+  P.rr_max = *std::max_element(P.nrr.begin(), P.nrr.end());
+  P.ct_max = nct_max;
+  P.slot_u = P.slot_v = P.slot_dev = 0; P.dev_tiles = 0;
   for (int r = 0; r < P.R; ++r)
     for (int s = 0; s < P.S; ++s) {
-      const int64_t nr = P.ro[r + 1] - P.ro[r], ms = P.co[s + 1] - P.co[s];
-      P.upart_elems = std::max<int64_t>(P.upart_elems, (int64_t)P.nct[s] * nr * 2 * P.KU);
-      P.vpart_elems = std::max<int64_t>(P.vpart_elems, (int64_t)P.nrr[r] * ms * 2 * P.KV);
-      P.max_tiles = std::max(P.max_tiles, P.nrr[r] * P.nct[s]);
+      const int64_t nr = P.nrows[r], ms = P.mcols[s];
+      P.slot_u = std::max<int64_t>(P.slot_u, (int64_t)P.nct[s] * nr * 2 * P.KU);
+      P.slot_v = std::max<int64_t>(P.slot_v, (int64_t)P.nrr[r] * ms * 2 * P.KV);
+      P.slot_dev = std::max<int64_t>(P.slot_dev, (int64_t)P.nrr[r] * P.nct[s]);
       P.dev_tiles += P.nrr[r] * P.nct[s];
     }
+  P.slot_u = (P.slot_u + 63) / 64 * 64;
+  P.slot_v = (P.slot_v + 63) / 64 * 64;
+  P.slot_dev = (P.slot_dev + 31) / 32 * 32;
+  {
+    const double slot_bytes = 4.0 * (P.slot_u + P.slot_v) + 8.0 * P.slot_dev;
+    P.nslot = (int)std::max(2.0, std::min((double)kMaxSlots, (256.0 * 1024 * 1024) / slot_bytes));
+  }
   const int nb = P.R * P.S;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -158,9 +177,9 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_Hrow = take(sizeof(double) * (size_t)P.n * P.KU);
   P.o_Gcol = take(sizeof(double) * (size_t)P.m * P.KV);
   P.o_Hcol = take(sizeof(double) * (size_t)P.m * P.KV);
-  P.o_Upart = take(sizeof(float) * (size_t)P.upart_elems);
-  P.o_Vpart = take(sizeof(float) * (size_t)P.vpart_elems);
-  P.o_devpart = take(sizeof(double) * (size_t)P.max_tiles);
+  P.o_Upart = take(sizeof(float) * (size_t)P.slot_u * P.nslot);
+  P.o_Vpart = take(sizeof(float) * (size_t)P.slot_v * P.nslot);
+  P.o_devpart = take(sizeof(double) * (size_t)P.slot_dev * P.nslot);
   P.o_devring = take(sizeof(double) * kDevRing);
   P.o_flag = take(sizeof(int) * 4);
   P.o_rowperm = take(sizeof(int) * (size_t)P.n);
@@ -188,6 +207,23 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_sumsq = take(sizeof(double) * kSumsqBlocks * 4);
   P.o_post = take(sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks));
   P.o_firstnz = take(sizeof(int) * 64);
+  P.o_desc = take(sizeof(gmf::StepDesc) * kDescWindow);
+  P.o_ro = take(sizeof(int) * (P.R + 1));
+  P.o_nrows = take(sizeof(int) * P.R);
+  P.o_rpw = take(sizeof(int) * P.R);
+  P.o_nrr = take(sizeof(int) * P.R);
+  P.o_co = take(sizeof(int) * (P.S + 1));
+  P.o_mcols = take(sizeof(int) * P.S);
+  P.o_ld = take(sizeof(int) * P.S);
+  P.o_nct = take(sizeof(int) * P.S);
+  P.o_coP = take(sizeof(int64_t) * (P.S + 1));
+  P.o_rowver = take(sizeof(int) * (size_t)P.R * P.rr_max);
+  P.o_colver = take(sizeof(int) * (size_t)P.S * P.ct_max);
+  P.o_arr = take(sizeof(int) * (size_t)P.nslot * (P.rr_max + P.ct_max + 1));
+  P.o_phase = take(sizeof(int) * P.nslot);
+  P.o_slotgen = take(sizeof(int) * P.nslot);
+  P.o_abort = take(sizeof(int) * 4);
+  P.o_taskctr = take(sizeof(unsigned long long) * 4);
   P.total = o;
 }
 
@@ -200,6 +236,16 @@ struct Ctx {
   uint64_t draw_start = 0;
   int64_t t = 0;
   int want_block_dev = 1;
+  // schedule window and queue state
+  std::vector<int> cnt_r, cnt_s;       // steps per block among steps 1..filled
+  int64_t filled = 0;                  // descriptors written for steps 1..filled
+  unsigned long long task_base = 0;
+  int capacity[2] = {0, 0};            // resident workgroups (without / with deviance)
+  // event timing of the step kernels
+  bool timing = false;
+  std::vector<hipEvent_t> events;   // 2 per timed launch
+  int64_t timed_launches = 0;
+  int64_t timed_steps = 0;
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -241,58 +287,116 @@ int check_flag(Ctx* c) {
   return GMF_OK;
 }
 
-int enqueue_steps(Ctx* c, int64_t nsteps) {
+// Write the descriptors of steps filled+1 .. up to at least `upto` into the
+// device window (chunks of half a window, in step order).  Stream ordered, so
+// entries still read by earlier launches are replaced only after those finish.
+int fill_descs(Ctx* c, int64_t upto) {
+  const Plan& P = c->P;
+  const int64_t half = kDescWindow / 2;
+  while (c->filled < upto) {
+    const int64_t first = c->filled + 1;
+    std::vector<gmf::StepDesc> h(half);
+    for (int64_t k = 0; k < half; ++k) {
+      const int64_t t = first + k;
+      gmf::StepDesc& d = h[k];
+      d.r = row_block_of_step(c, t);
+      d.s = (int)((t - 1) % P.S);
+      d.slot = (int)((t - 1) % P.nslot);
+      d.need_row = c->cnt_r[d.r]++;
+      d.need_col = c->cnt_s[d.s]++;
+      d.need_slot = (int)((t - 1) / P.nslot);
+      d.pad0 = d.pad1 = 0;
+      d.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
+      d.t = t;
+    }
+    const int64_t pos = (first - 1) % kDescWindow;
+    HIP_TRY(hipMemcpyAsync(c->at<gmf::StepDesc>(P.o_desc) + pos, h.data(),
+                           sizeof(gmf::StepDesc) * half, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    c->filled += half;
+  }
+  return GMF_OK;
+}
+
+gmf::StepKernelArgs step_args(const Ctx* c) {
   const Plan& P = c->P;
   const gmf_config& cf = c->cfg;
-  const gmf::FamilyArgs fa = family_args(cf);
-  for (int64_t k = 0; k < nsteps; ++k) {
-    const int64_t t = c->t + 1;
-    const int r = row_block_of_step(c, t);
-    const int s = (int)((t - 1) % P.S);
-    const int nb = P.ro[r + 1] - P.ro[r];
-    const int mb = P.co[s + 1] - P.co[s];
-    gmf::TileArgs ta;
-    ta.b.Y = c->at<float>(P.o_Yb) + (int64_t)P.ro[r] * P.LDtot + (int64_t)nb * P.coP[s];
-    ta.b.W = P.with_w ? c->at<float>(P.o_Wb) + (int64_t)P.ro[r] * P.LDtot + (int64_t)nb * P.coP[s]
-                      : nullptr;
-    ta.b.Prow = c->at<float>(P.o_Prow) + (int64_t)P.ro[r] * P.KP;
-    ta.b.Pcol = c->at<float>(P.o_Pcol) + (int64_t)P.co[s] * P.KP;
-    ta.b.ldy = P.ld[s];
-    ta.b.n_b = nb;
-    ta.b.m_b = mb;
-    ta.b.rows_per_wg = P.rpw[r];
-    ta.b.n_rr = P.nrr[r];
-    ta.b.n_ct = P.nct[s];
-    ta.f = fa;
-    ta.Upart = c->at<float>(P.o_Upart);
-    ta.Vpart = c->at<float>(P.o_Vpart);
-    ta.devpart = c->at<double>(P.o_devpart);
-    ta.p = P.p; ta.q = P.q; ta.d = P.d; ta.KU = P.KU; ta.KV = P.KV;
-    ta.want_dev = c->want_block_dev;
-    HIP_TRY(gmf::launch_tile(P.prec, P.fam, P.KP, ta, c->st));
+  gmf::StepKernelArgs a;
+  a.Y = c->at<float>(P.o_Yb);
+  a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+  a.Prow = c->at<float>(P.o_Prow);
+  a.Pcol = c->at<float>(P.o_Pcol);
+  a.Grow = c->at<double>(P.o_Grow);
+  a.Hrow = c->at<double>(P.o_Hrow);
+  a.Gcol = c->at<double>(P.o_Gcol);
+  a.Hcol = c->at<double>(P.o_Hcol);
+  a.LDtot = P.LDtot;
+  a.ro = c->at<int>(P.o_ro);
+  a.nrows = c->at<int>(P.o_nrows);
+  a.rpw = c->at<int>(P.o_rpw);
+  a.nrr = c->at<int>(P.o_nrr);
+  a.co = c->at<int>(P.o_co);
+  a.mcols = c->at<int>(P.o_mcols);
+  a.ldy = c->at<int>(P.o_ld);
+  a.nct = c->at<int>(P.o_nct);
+  a.coP = c->at<int64_t>(P.o_coP);
+  a.rr_max = P.rr_max;
+  a.ct_max = P.ct_max;
+  a.n = P.n;
+  a.m = P.m;
+  a.Upart = c->at<float>(P.o_Upart);
+  a.Vpart = c->at<float>(P.o_Vpart);
+  a.devpart = c->at<double>(P.o_devpart);
+  a.slot_u_elems = P.slot_u;
+  a.slot_v_elems = P.slot_v;
+  a.slot_dev_elems = P.slot_dev;
+  a.rowver = c->at<int>(P.o_rowver);
+  a.colver = c->at<int>(P.o_colver);
+  a.arr = c->at<int>(P.o_arr);
+  a.phase = c->at<int>(P.o_phase);
+  a.slotgen = c->at<int>(P.o_slotgen);
+  a.abort_flag = c->at<int>(P.o_abort);
+  a.spin_limit = kSpinLimit;
+  a.desc = c->at<gmf::StepDesc>(P.o_desc);
+  a.desc_window = kDescWindow;
+  a.task_ctr = c->at<unsigned long long>(P.o_taskctr);
+  a.f = family_args(cf);
+  a.p = P.p; a.q = P.q; a.d = P.d; a.KU = P.KU; a.KV = P.KV; a.KP = P.KP;
+  a.lam_B = cf.lambda[0]; a.lam_A = cf.lambda[1]; a.lam_U = cf.lambda[2]; a.lam_V = cf.lambda[3];
+  a.a1 = cf.alpha1; a.a2 = cf.alpha2; a.damping = cf.damping;
+  a.devring = c->at<double>(P.o_devring);
+  a.devring_len = kDevRing;
+  a.err_flag = c->at<int>(P.o_flag);
+  return a;
+}
 
-    gmf::UpdateArgs ua;
-    ua.Prow = c->at<float>(P.o_Prow) + (int64_t)P.ro[r] * P.KP;
-    ua.Pcol = c->at<float>(P.o_Pcol) + (int64_t)P.co[s] * P.KP;
-    ua.Grow = c->at<double>(P.o_Grow) + (int64_t)P.ro[r] * P.KU;
-    ua.Hrow = c->at<double>(P.o_Hrow) + (int64_t)P.ro[r] * P.KU;
-    ua.Gcol = c->at<double>(P.o_Gcol) + (int64_t)P.co[s] * P.KV;
-    ua.Hcol = c->at<double>(P.o_Hcol) + (int64_t)P.co[s] * P.KV;
-    ua.Upart = ta.Upart; ua.Vpart = ta.Vpart; ua.devpart = ta.devpart;
-    ua.n_b = nb; ua.m_b = mb; ua.n_ct = P.nct[s]; ua.n_rr = P.nrr[r];
-    ua.n_tiles = P.nct[s] * P.nrr[r];
-    ua.p = P.p; ua.q = P.q; ua.d = P.d; ua.KU = P.KU; ua.KV = P.KV; ua.KP = P.KP;
-    ua.scale_m = (double)P.m / mb;
-    ua.scale_n = (double)P.n / nb;
-    ua.lam_B = cf.lambda[0]; ua.lam_A = cf.lambda[1]; ua.lam_U = cf.lambda[2]; ua.lam_V = cf.lambda[3];
-    ua.a1 = cf.alpha1; ua.a2 = cf.alpha2;
-    ua.stepsize = learning_rate(cf, t) * bias_factor(cf, t);
-    ua.damping = cf.damping;
-    ua.dev_out = c->at<double>(P.o_devring) + (t - 1) % kDevRing;
-    ua.err_flag = c->at<int>(P.o_flag);
-    ua.want_dev = c->want_block_dev;
-    HIP_TRY(gmf::launch_update(ua, c->st));
-    c->t = t;
+int enqueue_steps(Ctx* c, int64_t nsteps) {
+  const Plan& P = c->P;
+  const bool want_dev = c->want_block_dev != 0;
+  const int cap = c->capacity[want_dev ? 1 : 0];
+  const unsigned long long T = (unsigned long long)P.rr_max * P.ct_max;
+  while (nsteps > 0) {
+    const int64_t k = std::min<int64_t>(nsteps, kDescWindow / 2);
+    int rc = fill_descs(c, c->t + k);
+    if (rc != GMF_OK) return rc;
+    gmf::StepKernelArgs a = step_args(c);
+    a.t_first = c->t + 1;
+    a.nsteps = (int)k;
+    a.task_base = c->task_base;
+    const unsigned long long total = (unsigned long long)k * T;
+    const int grid = (int)std::min<unsigned long long>(total, (unsigned long long)cap);
+    hipEvent_t* ev = nullptr;
+    if (c->timing && c->timed_launches < kMaxTimedSteps) {
+      ev = &c->events[2 * c->timed_launches];
+      ++c->timed_launches;
+      c->timed_steps += k;
+      HIP_TRY(hipEventRecord(ev[0], c->st));
+    }
+    HIP_TRY(gmf::launch_steps(P.prec, P.fam, P.KP, want_dev, a, grid, c->st));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], c->st));
+    c->task_base += total + (unsigned long long)grid;
+    c->t += k;
+    nsteps -= k;
   }
   return GMF_OK;
 }
@@ -496,6 +600,29 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   for (size_t off : {P.o_Gcol, P.o_Hcol})
     if (e == hipSuccess) e = gmf::launch_fill_f64(c->at<double>(off), P.m * P.KV, 0.0, st);
   if (e == hipSuccess) e = gmf::launch_fill_f64(c->at<double>(P.o_devring), kDevRing, 0.0, st);
+  if (e == hipSuccess) e = h2d(P.o_ro, P.ro.data(), sizeof(int) * (P.R + 1));
+  if (e == hipSuccess) e = h2d(P.o_nrows, P.nrows.data(), sizeof(int) * P.R);
+  if (e == hipSuccess) e = h2d(P.o_rpw, P.rpw.data(), sizeof(int) * P.R);
+  if (e == hipSuccess) e = h2d(P.o_nrr, P.nrr.data(), sizeof(int) * P.R);
+  if (e == hipSuccess) e = h2d(P.o_co, P.co.data(), sizeof(int) * (P.S + 1));
+  if (e == hipSuccess) e = h2d(P.o_mcols, P.mcols.data(), sizeof(int) * P.S);
+  if (e == hipSuccess) e = h2d(P.o_ld, P.ld.data(), sizeof(int) * P.S);
+  if (e == hipSuccess) e = h2d(P.o_nct, P.nct.data(), sizeof(int) * P.S);
+  if (e == hipSuccess) e = h2d(P.o_coP, P.coP.data(), sizeof(int64_t) * (P.S + 1));
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_rowver), (int64_t)P.R * P.rr_max, 0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_colver), (int64_t)P.S * P.ct_max, 0, st);
+  if (e == hipSuccess)
+    e = gmf::launch_fill_i32(c->at<int>(P.o_arr), (int64_t)P.nslot * (P.rr_max + P.ct_max + 1), 0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_phase), P.nslot, 0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_slotgen), P.nslot, 0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_abort), 4, 0, st);
+  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_taskctr), 8, 0, st);
+  c->cnt_r.assign(P.R, 0);
+  c->cnt_s.assign(P.S, 0);
+  for (int wd = 0; wd < 2; ++wd) {
+    const int occ = gmf::steps_occupancy(P.prec, P.fam, P.KP, wd == 1);
+    c->capacity[wd] = std::max(1, occ) * std::max(1, prop.multiProcessorCount);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete c;
@@ -678,6 +805,41 @@ int gmf_sync(void* ctx) {
   return check_flag(as_ctx(ctx));
 }
 
-void gmf_destroy(void* ctx) { delete as_ctx(ctx); }
+int gmf_set_timing(void* ctx, int32_t enable) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  if (enable && c->events.empty()) {
+    c->events.resize(2 * kMaxTimedSteps);
+    for (auto& e : c->events) HIP_TRY(hipEventCreate(&e));
+  }
+  c->timing = enable != 0;
+  return GMF_OK;
+}
+
+int gmf_get_timing(void* ctx, double* launch_ms_host, double* launches_host,
+                   int64_t* steps_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  HIP_TRY(hipStreamSynchronize(c->st));
+  double tot = 0;
+  for (int64_t k = 0; k < c->timed_launches; ++k) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
+    tot += ms;
+  }
+  if (launch_ms_host) *launch_ms_host = tot;
+  if (launches_host) *launches_host = (double)c->timed_launches;
+  if (steps_host) *steps_host = c->timed_steps;
+  c->timed_launches = 0;
+  c->timed_steps = 0;
+  return GMF_OK;
+}
+
+void gmf_destroy(void* ctx) {
+  Ctx* c = as_ctx(ctx);
+  if (!c) return;
+  for (auto& e : c->events) (void)hipEventDestroy(e);
+  delete c;
+}
 
 }  // extern "C"

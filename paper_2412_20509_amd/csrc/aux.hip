@@ -212,6 +212,7 @@ __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   __shared__ float sP[kRowGroup][KP + 4];
   __shared__ double sDev[kTileWaves];
   const int tile = blockIdx.x;
+  const FamilyConst fc = family_const(a.f);
   const int blk = a.tile_block[tile];
   const int local = tile - a.tile_first[blk];
   const int n_b = a.blk_nb[blk], m_b = a.blk_mb[blk];
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
           for (int v = 0; v < 4; ++v) {
             if (colb + v < m_b) {
               float x1, x2, dv = 0.f;
-              family_entry<FAM>(e[v], ys[v], ws[v], a.f, true, x1, x2, dv);
+              family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
               acc += (double)dv;
             }
           }

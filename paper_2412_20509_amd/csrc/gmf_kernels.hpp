@@ -22,18 +22,6 @@ constexpr int kRowGroup = 32;
 enum Family { kPoisson = 0, kNegBin = 1, kGaussian = 2 };
 enum Prec { kF32 = 0, kBF16 = 1 };
 
-// One block B = I_r x J_s as seen by the tile kernels.
-struct BlockView {
-  const float* Y;      // block base; element (i, j) at Y[i * ldy + j]
-  const float* W;      // same layout, or nullptr for unit weights
-  const float* Prow;   // [X | Gamma | U | 0] rows of I_r, row stride KP
-  const float* Pcol;   // [B | Z | V | 0] rows of J_s, row stride KP
-  int64_t ldy;         // padded row stride (multiple of 4)
-  int n_b, m_b;        // |I_r|, |J_s|
-  int rows_per_wg;     // multiple of kRowGroup
-  int n_rr, n_ct;      // row ranges and column strips of the tiling
-};
-
 struct FamilyArgs {
   float phi_inv;       // 1 / phi
   float nb_alpha;      // NB shape
@@ -41,36 +29,57 @@ struct FamilyArgs {
   float eta_hi;        // eta_max    (log link)
 };
 
-struct TileArgs {
-  BlockView b;
-  FamilyArgs f;
-  float* Upart;        // [n_ct][n_b][2*KU] : column-strip partial sums, G then H
-  float* Vpart;        // [n_rr][m_b][2*KV] : row-range partial sums, G then H
-  double* devpart;     // [n_rr * n_ct]     : per-tile deviance partial sums
-  int p, q, d, KU, KV;
-  int want_dev;
+// One step of the schedule, filled on the host for a window of steps.
+struct StepDesc {
+  int r, s;            // row block and column block
+  int slot;            // partial-buffer slot (t-1) mod nslot
+  int need_row;        // earlier steps on row block r (row-range versions to wait for)
+  int need_col;        // earlier steps on column block s
+  int need_slot;       // earlier users of the slot that must have finished
+  int pad0, pad1;
+  double stepsize;     // rho_t * alpha_t
+  int64_t t;           // global step number (from 1)
 };
 
-struct UpdateArgs {
-  float* Prow;         // rows of I_r in the row panel (stride KP)
-  float* Pcol;         // rows of J_s in the column panel (stride KP)
-  double* Grow; double* Hrow;   // moments of [Gamma, U] for I_r (stride KU)
-  double* Gcol; double* Hcol;   // moments of [B, V] for J_s (stride KV)
-  const float* Upart; const float* Vpart; const double* devpart;
-  int n_b, m_b, n_ct, n_rr, n_tiles;
+struct StepKernelArgs {
+  // data in the workspace (permuted, block-major)
+  const float* Y; const float* W;
+  float* Prow; float* Pcol;
+  double* Grow; double* Hrow; double* Gcol; double* Hcol;
+  int64_t LDtot;
+  // per row block r / column block s geometry
+  const int* ro; const int* nrows; const int* rpw; const int* nrr;
+  const int* co; const int* mcols; const int* ldy; const int* nct; const int64_t* coP;
+  int rr_max, ct_max;
+  int64_t n, m;
+  // partial slots
+  float* Upart; float* Vpart; double* devpart;
+  int64_t slot_u_elems, slot_v_elems, slot_dev_elems;
+  // ordering state
+  int* rowver;   // [R][rr_max] updates applied to each row range
+  int* colver;   // [S][ct_max] updates applied to each column strip
+  int* arr;      // [nslot][rr_max + ct_max + 1] arrival counters
+  int* phase;    // [nslot] finished phases of the slot's current step
+  int* slotgen;  // [nslot] steps finished on the slot
+  int* abort_flag;
+  int spin_limit;
+  // schedule window and task queue
+  const StepDesc* desc; int desc_window;
+  int64_t t_first; int nsteps;
+  unsigned long long* task_ctr; unsigned long long task_base;
+  // numerics
+  FamilyArgs f;
   int p, q, d, KU, KV, KP;
-  double scale_m, scale_n;      // m / |J_s|, n / |I_r|
   double lam_B, lam_A, lam_U, lam_V;
-  double a1, a2, stepsize, damping;
-  double* dev_out;              // where the block deviance of this step goes
-  int* err_flag;                // set to 1 on a non-finite parameter
-  int want_dev;
+  double a1, a2, damping;
+  double* devring; int devring_len;
+  int* err_flag;
 };
 
 // ------------------------------------------------------------ launchers ----
-// Host-side launchers implemented in the .hip files.
-hipError_t launch_tile(int prec, int fam, int KP, const TileArgs& a, hipStream_t s);
-hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_steps(int prec, int fam, int KP, bool want_dev, const StepKernelArgs& a,
+                        int grid, hipStream_t s);
+int steps_occupancy(int prec, int fam, int KP, bool want_dev);
 
 struct DevArgs {
   const float* Y; const float* W;

@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(i32)]),
         "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
                                         C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_set_timing": (C.c_int, [vp, i32]),
+        "gmf_get_timing": (C.c_int, [vp, f64p, f64p, C.POINTER(i64)]),
         "gmf_steps_done": (i64, [vp]),
         "gmf_sync": (C.c_int, [vp]),
         "gmf_destroy": (None, [vp]),
@@ -180,6 +182,17 @@ def gmf_schedule_host(seed: int, n: int, m: int, R: int, t_first: int = 1, count
     rr = (C.c_int32 * max(count, 1))()
     _check(load_library().gmf_schedule_host(seed, n, m, R, t_first, count, rp, cp, rr))
     return np.array(rp)[:n], np.array(cp)[:m], np.array(rr)[:count]
+
+
+def gmf_set_timing(ctx, enable: bool):
+    return _check(load_library().gmf_set_timing(ctx, int(bool(enable))))
+
+
+def gmf_get_timing(ctx):
+    """(summed step-launch ms, launches, steps) since the last call."""
+    a, b, k = C.c_double(), C.c_double(), C.c_int64()
+    _check(load_library().gmf_get_timing(ctx, C.byref(a), C.byref(b), C.byref(k)))
+    return a.value, b.value, k.value
 
 
 def gmf_steps_done(ctx) -> int:
@@ -317,6 +330,12 @@ class GMF:
 
     def schedule(self, t_first=1, count=0):
         return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)
+
+    def set_timing(self, enable):
+        gmf_set_timing(self.ctx, enable)
+
+    def get_timing(self):
+        return gmf_get_timing(self.ctx)
 
     def steps_done(self):
         return gmf_steps_done(self.ctx)
