@@ -77,12 +77,14 @@ typedef struct gmf_config {
   double eps;         /* mu floor: eta is clamped to >= log(eps) (log link)   */
   double eta_max;     /* eta ceiling for the log link                         */
   uint64_t seed;      /* schedule seed: partitions and row-block draws        */
+  int32_t tile_rows;  /* rows per step tile (multiple of 32), 0 = automatic   */
+  int32_t reserved;   /* must be 0                                            */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
- * bias_mode=0, seed=0. */
+ * bias_mode=0, seed=0, tile_rows=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -187,6 +189,15 @@ int gmf_schedule_host(uint64_t seed, int64_t n, int64_t m, int32_t R, int64_t t_
 int gmf_set_timing(void* ctx, int32_t enable);
 int gmf_get_timing(void* ctx, double* launch_ms_host, double* launches_host,
                    int64_t* steps_host);
+
+/* gmf_set_trace -- record a timeline of the step tasks into a caller device
+ * buffer of `records` x 8 uint64 (NULL disables): per task of the following
+ * launches, in claim order across launches: [0] step t, [1] (workgroup << 32)
+ * | tile, [2..6] s_memrealtime stamps (100 MHz) at claim, dependencies met,
+ * tile computed, arrival counted, done, [7] bit 0/1/2 = this task ran the
+ * row-range update / column-strip update / block-deviance sum.  Records past
+ * the capacity are dropped.  For profiling only. */
+int gmf_set_trace(void* ctx, void* buffer, int64_t records);
 
 /* Steps run so far (the global counter t of the last step). */
 int64_t gmf_steps_done(void* ctx);

@@ -66,6 +66,9 @@ std::vector<int> shuffle(uint64_t seed, uint64_t stream, int64_t n) {
 int round_up(int x, int a) { return (x + a - 1) / a * a; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Rows per workgroup of the full-deviance kernel (multiple of 32).
+int dev_rows_per_wg(int nr) { return std::min(256, (nr + 31) / 32 * 32); }
+
 struct Plan {
   int64_t n = 0, m = 0;
   int R = 0, S = 0, p = 0, q = 0, d = 0, k = 0, KP = 0, KU = 0, KV = 0;
@@ -81,17 +84,15 @@ struct Plan {
       o_devpart, o_devring, o_flag, o_rowperm, o_colperm, o_rowblk, o_rowloc, o_colblk,
       o_colloc, o_blkrowbase, o_blknrows, o_blkcoloff, o_blkld, o_tileblk, o_tilefirst,
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
-      o_scal, o_sumsq, o_post, o_firstnz, o_desc, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
-      o_ld, o_nct, o_coP, o_rowver, o_colver, o_arr, o_phase, o_slotgen, o_abort, o_taskctr,
-      total;
+      o_scal, o_sumsq, o_post, o_firstnz, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
+      o_ld, o_nct, o_coP, total;
+  int row_chunk = 1, col_chunk = 1, upd_per_step = 1;
 };
 
 constexpr int kDevRing = 4096;
 constexpr int64_t kMaxTimedSteps = 8192;
-constexpr int kDescWindow = 16384;     // steps whose descriptors live on the device
 constexpr int kMaxSlots = 16;
 constexpr int kTilesPerStepTarget = 256;
-constexpr int kSpinLimit = 1 << 22;
 constexpr int kSumsqBlocks = 256;
 
 std::string check_config(const gmf_config* c) {
@@ -116,6 +117,8 @@ std::string check_config(const gmf_config* c) {
   if (!(c->damping >= 0) || !(c->eps > 0) || !std::isfinite(c->eta_max)) return "bad damping/eps/eta_max";
   for (int i = 0; i < 4; ++i)
     if (!(c->lambda[i] >= 0)) return "lambda must be >= 0";
+  if (c->tile_rows < 0 || c->tile_rows % 32 != 0 || c->tile_rows > 4096)
+    return "tile_rows must be 0 or a multiple of 32 up to 4096";
   return "";
 }
 
@@ -145,6 +148,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
     P.nrows[r] = nr;
     int rpw = round_up((int)std::ceil((double)nr * nct_max / kTilesPerStepTarget), gmf::kRowGroup);
     rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
+    if (c->tile_rows > 0) rpw = c->tile_rows;
     P.rpw[r] = rpw;
     P.nrr[r] = (nr + rpw - 1) / rpw;
   }
@@ -157,7 +161,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
       P.slot_u = std::max<int64_t>(P.slot_u, (int64_t)P.nct[s] * nr * 2 * P.KU);
       P.slot_v = std::max<int64_t>(P.slot_v, (int64_t)P.nrr[r] * ms * 2 * P.KV);
       P.slot_dev = std::max<int64_t>(P.slot_dev, (int64_t)P.nrr[r] * P.nct[s]);
-      P.dev_tiles += P.nrr[r] * P.nct[s];
+      P.dev_tiles += ((nr + dev_rows_per_wg((int)nr) - 1) / dev_rows_per_wg((int)nr)) * P.nct[s];
     }
   P.slot_u = (P.slot_u + 63) / 64 * 64;
   P.slot_v = (P.slot_v + 63) / 64 * 64;
@@ -207,7 +211,6 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_sumsq = take(sizeof(double) * kSumsqBlocks * 4);
   P.o_post = take(sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks));
   P.o_firstnz = take(sizeof(int) * 64);
-  P.o_desc = take(sizeof(gmf::StepDesc) * kDescWindow);
   P.o_ro = take(sizeof(int) * (P.R + 1));
   P.o_nrows = take(sizeof(int) * P.R);
   P.o_rpw = take(sizeof(int) * P.R);
@@ -217,13 +220,13 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_ld = take(sizeof(int) * P.S);
   P.o_nct = take(sizeof(int) * P.S);
   P.o_coP = take(sizeof(int64_t) * (P.S + 1));
-  P.o_rowver = take(sizeof(int) * (size_t)P.R * P.rr_max);
-  P.o_colver = take(sizeof(int) * (size_t)P.S * P.ct_max);
-  P.o_arr = take(sizeof(int) * (size_t)P.nslot * (P.rr_max + P.ct_max + 1));
-  P.o_phase = take(sizeof(int) * P.nslot);
-  P.o_slotgen = take(sizeof(int) * P.nslot);
-  P.o_abort = take(sizeof(int) * 4);
-  P.o_taskctr = take(sizeof(unsigned long long) * 4);
+  P.row_chunk = std::max(1, gmf::kTileThreads / (2 * P.KU));
+  P.col_chunk = std::max(1, gmf::kTileThreads / (2 * P.KV));
+  P.upd_per_step = 1;
+  for (int r = 0; r < P.R; ++r)
+    for (int s = 0; s < P.S; ++s)
+      P.upd_per_step = std::max(P.upd_per_step, (P.nrows[r] + P.row_chunk - 1) / P.row_chunk +
+                                                    (P.mcols[s] + P.col_chunk - 1) / P.col_chunk + 1);
   P.total = o;
 }
 
@@ -236,11 +239,11 @@ struct Ctx {
   uint64_t draw_start = 0;
   int64_t t = 0;
   int want_block_dev = 1;
-  // schedule window and queue state
-  std::vector<int> cnt_r, cnt_s;       // steps per block among steps 1..filled
-  int64_t filled = 0;                  // descriptors written for steps 1..filled
-  unsigned long long task_base = 0;
-  int capacity[2] = {0, 0};            // resident workgroups (without / with deviance)
+  unsigned long long launches = 0;
+  // optional per-task trace (caller's device buffer)
+  unsigned long long* trace = nullptr;
+  long long trace_cap = 0;
+  unsigned long long trace_used = 0;
   // event timing of the step kernels
   bool timing = false;
   std::vector<hipEvent_t> events;   // 2 per timed launch
@@ -287,41 +290,10 @@ int check_flag(Ctx* c) {
   return GMF_OK;
 }
 
-// Write the descriptors of steps filled+1 .. up to at least `upto` into the
-// device window (chunks of half a window, in step order).  Stream ordered, so
-// entries still read by earlier launches are replaced only after those finish.
-int fill_descs(Ctx* c, int64_t upto) {
-  const Plan& P = c->P;
-  const int64_t half = kDescWindow / 2;
-  while (c->filled < upto) {
-    const int64_t first = c->filled + 1;
-    std::vector<gmf::StepDesc> h(half);
-    for (int64_t k = 0; k < half; ++k) {
-      const int64_t t = first + k;
-      gmf::StepDesc& d = h[k];
-      d.r = row_block_of_step(c, t);
-      d.s = (int)((t - 1) % P.S);
-      d.slot = (int)((t - 1) % P.nslot);
-      d.need_row = c->cnt_r[d.r]++;
-      d.need_col = c->cnt_s[d.s]++;
-      d.need_slot = (int)((t - 1) / P.nslot);
-      d.pad0 = d.pad1 = 0;
-      d.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
-      d.t = t;
-    }
-    const int64_t pos = (first - 1) % kDescWindow;
-    HIP_TRY(hipMemcpyAsync(c->at<gmf::StepDesc>(P.o_desc) + pos, h.data(),
-                           sizeof(gmf::StepDesc) * half, hipMemcpyHostToDevice, c->st));
-    HIP_TRY(hipStreamSynchronize(c->st));
-    c->filled += half;
-  }
-  return GMF_OK;
-}
-
-gmf::StepKernelArgs step_args(const Ctx* c) {
+gmf::LevelArgs level_args(const Ctx* c) {
   const Plan& P = c->P;
   const gmf_config& cf = c->cfg;
-  gmf::StepKernelArgs a;
+  gmf::LevelArgs a;
   a.Y = c->at<float>(P.o_Yb);
   a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
   a.Prow = c->at<float>(P.o_Prow);
@@ -350,16 +322,9 @@ gmf::StepKernelArgs step_args(const Ctx* c) {
   a.slot_u_elems = P.slot_u;
   a.slot_v_elems = P.slot_v;
   a.slot_dev_elems = P.slot_dev;
-  a.rowver = c->at<int>(P.o_rowver);
-  a.colver = c->at<int>(P.o_colver);
-  a.arr = c->at<int>(P.o_arr);
-  a.phase = c->at<int>(P.o_phase);
-  a.slotgen = c->at<int>(P.o_slotgen);
-  a.abort_flag = c->at<int>(P.o_abort);
-  a.spin_limit = kSpinLimit;
-  a.desc = c->at<gmf::StepDesc>(P.o_desc);
-  a.desc_window = kDescWindow;
-  a.task_ctr = c->at<unsigned long long>(P.o_taskctr);
+  a.row_chunk = P.row_chunk;
+  a.col_chunk = P.col_chunk;
+  a.upd_per_step = P.upd_per_step;
   a.f = family_args(cf);
   a.p = P.p; a.q = P.q; a.d = P.d; a.KU = P.KU; a.KV = P.KV; a.KP = P.KP;
   a.lam_B = cf.lambda[0]; a.lam_A = cf.lambda[1]; a.lam_U = cf.lambda[2]; a.lam_V = cf.lambda[3];
@@ -367,37 +332,88 @@ gmf::StepKernelArgs step_args(const Ctx* c) {
   a.devring = c->at<double>(P.o_devring);
   a.devring_len = kDevRing;
   a.err_flag = c->at<int>(P.o_flag);
+  a.trace = c->trace;
+  a.trace_cap = c->trace_cap;
+  a.trace_base = 0;
+  a.launch_id = 0;
+  a.n_tile_steps = a.n_upd_steps = 0;
   return a;
 }
 
+// Run steps c->t+1 .. c->t+nsteps.  Step t is placed at level
+// T(t) = max over its predecessors (previous step on the same row block, on the
+// same column block, and on the same partial slot) of T + 2, or 0.  Launch k
+// runs the tiles of level k and the updates of level k-1; oversized levels are
+// split over several launches (tiles of level k never need updates of level k-1).
 int enqueue_steps(Ctx* c, int64_t nsteps) {
   const Plan& P = c->P;
+  const gmf_config& cf = c->cfg;
   const bool want_dev = c->want_block_dev != 0;
-  const int cap = c->capacity[want_dev ? 1 : 0];
-  const unsigned long long T = (unsigned long long)P.rr_max * P.ct_max;
-  while (nsteps > 0) {
-    const int64_t k = std::min<int64_t>(nsteps, kDescWindow / 2);
-    int rc = fill_descs(c, c->t + k);
-    if (rc != GMF_OK) return rc;
-    gmf::StepKernelArgs a = step_args(c);
-    a.t_first = c->t + 1;
-    a.nsteps = (int)k;
-    a.task_base = c->task_base;
-    const unsigned long long total = (unsigned long long)k * T;
-    const int grid = (int)std::min<unsigned long long>(total, (unsigned long long)cap);
-    hipEvent_t* ev = nullptr;
-    if (c->timing && c->timed_launches < kMaxTimedSteps) {
-      ev = &c->events[2 * c->timed_launches];
-      ++c->timed_launches;
-      c->timed_steps += k;
-      HIP_TRY(hipEventRecord(ev[0], c->st));
-    }
-    HIP_TRY(gmf::launch_steps(P.prec, P.fam, P.KP, want_dev, a, grid, c->st));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], c->st));
-    c->task_base += total + (unsigned long long)grid;
-    c->t += k;
-    nsteps -= k;
+  if (nsteps <= 0) return GMF_OK;
+  std::vector<gmf::LevelStep> steps(nsteps);
+  std::vector<int> level(nsteps);
+  std::vector<int> lr(P.R, -1), ls(P.S, -1), lslot(P.nslot, -1);
+  int max_level = 0;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t t = c->t + 1 + k;
+    gmf::LevelStep& st = steps[k];
+    st.r = row_block_of_step(c, t);
+    st.s = (int)((t - 1) % P.S);
+    st.slot = (int)((t - 1) % P.nslot);
+    st.n_b = P.nrows[st.r];
+    st.m_b = P.mcols[st.s];
+    st.n_rr = P.nrr[st.r];
+    st.n_ct = P.nct[st.s];
+    st.rpw = P.rpw[st.r];
+    st.ldy = P.ld[st.s];
+    st.ro = P.ro[st.r];
+    st.co = P.co[st.s];
+    st.pad = 0;
+    st.yoff = (int64_t)P.ro[st.r] * P.LDtot + (int64_t)st.n_b * P.coP[st.s];
+    st.stepsize = learning_rate(cf, t) * bias_factor(cf, t);
+    st.t = t;
+    int lv = 0;
+    if (lr[st.r] >= 0) lv = std::max(lv, lr[st.r] + 2);
+    if (ls[st.s] >= 0) lv = std::max(lv, ls[st.s] + 2);
+    if (lslot[st.slot] >= 0) lv = std::max(lv, lslot[st.slot] + 2);
+    lr[st.r] = ls[st.s] = lslot[st.slot] = lv;
+    level[k] = lv;
+    max_level = std::max(max_level, lv);
   }
+  std::vector<std::vector<int>> by_level(max_level + 1);
+  for (int64_t k = 0; k < nsteps; ++k) by_level[level[k]].push_back((int)k);
+  const int T = P.rr_max * P.ct_max;
+  gmf::LevelArgs a = level_args(c);
+  for (int lv = 0; lv <= max_level + 1; ++lv) {
+    const std::vector<int> none;
+    const std::vector<int>& tiles = lv <= max_level ? by_level[lv] : none;
+    const std::vector<int>& upds = lv >= 1 ? by_level[lv - 1] : none;
+    size_t it = 0, iu = 0;
+    while (it < tiles.size() || iu < upds.size()) {
+      int nt = (int)std::min<size_t>(tiles.size() - it, gmf::kMaxLevelSteps);
+      int nu = (int)std::min<size_t>(upds.size() - iu, gmf::kMaxLevelSteps - nt);
+      a.n_tile_steps = nt;
+      a.n_upd_steps = nu;
+      for (int i = 0; i < nt; ++i) a.steps[i] = steps[tiles[it + i]];
+      for (int i = 0; i < nu; ++i) a.steps[nt + i] = steps[upds[iu + i]];
+      it += nt;
+      iu += nu;
+      const int grid = nt * T + nu * P.upd_per_step;
+      a.launch_id = c->launches++;
+      a.trace_base = c->trace_used;
+      c->trace_used += grid;
+      hipEvent_t* ev = nullptr;
+      if (c->timing && c->timed_launches < kMaxTimedSteps) {
+        ev = &c->events[2 * c->timed_launches];
+        ++c->timed_launches;
+        HIP_TRY(hipEventRecord(ev[0], c->st));
+      }
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, a, grid, c->st));
+      if (ev) HIP_TRY(hipEventRecord(ev[1], c->st));
+    }
+  }
+  if (c->timing) c->timed_steps += nsteps;
+  c->t += nsteps;
   return GMF_OK;
 }
 
@@ -425,24 +441,12 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
   // precision, so its panel stride must be a float32 case (16, 32, 48, 64).
   HIP_TRY(gmf::launch_deviance(P.fam, P.KP, a, c->st));
   double* scal = c->at<double>(P.o_scal);
-  HIP_TRY(gmf::launch_sum_partials(a.partial, P.dev_tiles, scal + 0, c->st));
   double* sq = c->at<double>(P.o_sumsq);
-  const int cols[4][3] = {{1, 0, P.p},           // B: column panel, cols [0, p)
-                          {0, P.p, P.q},         // Gamma: row panel, [p, p+q)
-                          {0, P.p + P.q, P.d},   // U: row panel
-                          {1, P.p + P.q, P.d}};  // V: column panel
-  for (int i = 0; i < 4; ++i) {
-    const bool colside = cols[i][0] == 1;
-    const float* Pn = colside ? c->at<float>(P.o_Pcol) : c->at<float>(P.o_Prow);
-    const int64_t rows = colside ? P.m : P.n;
-    if (cols[i][2] > 0) {
-      HIP_TRY(gmf::launch_sumsq(Pn, P.KP, rows, cols[i][1], cols[i][2], sq + i * kSumsqBlocks,
-                                kSumsqBlocks, c->st));
-    } else {
-      HIP_TRY(gmf::launch_fill_f64(sq + i * kSumsqBlocks, kSumsqBlocks, 0.0, c->st));
-    }
-    HIP_TRY(gmf::launch_sum_partials(sq + i * kSumsqBlocks, kSumsqBlocks, scal + 1 + i, c->st));
-  }
+  if (pen)
+    HIP_TRY(gmf::launch_norms(c->at<float>(P.o_Prow), c->at<float>(P.o_Pcol), P.KP, P.n, P.m, P.p,
+                              P.q, P.d, sq, kSumsqBlocks, c->st));
+  HIP_TRY(gmf::launch_finalize(a.partial, P.dev_tiles, pen ? sq : nullptr, kSumsqBlocks, scal,
+                               c->st));
   double h[5];
   HIP_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
@@ -545,6 +549,8 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   const int nb = P.R * P.S;
   std::vector<int> tileblk(P.dev_tiles), tilefirst(nb), brow0(nb), bcol0(nb), bnb(nb), bmb(nb),
       bldy(nb), brpw(nb), bnct(nb);
+  // the full-deviance kernel walks kDevRows rows per workgroup (fewer, longer
+  // workgroups than the step tiling); dev_tiles counts them
   std::vector<int64_t> byoff(nb);
   int tcount = 0;
   for (int r = 0; r < P.R; ++r)
@@ -558,9 +564,10 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
       bnb[b] = nr;
       bmb[b] = P.co[s + 1] - P.co[s];
       bldy[b] = P.ld[s];
-      brpw[b] = P.rpw[r];
+      const int drpw = dev_rows_per_wg(nr);
+      brpw[b] = drpw;
       bnct[b] = P.nct[s];
-      for (int k = 0; k < P.nrr[r] * P.nct[s]; ++k) tileblk[tcount++] = b;
+      for (int k = 0; k < ((nr + drpw - 1) / drpw) * P.nct[s]; ++k) tileblk[tcount++] = b;
     }
 
   hipStream_t st = c->st;
@@ -609,20 +616,6 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   if (e == hipSuccess) e = h2d(P.o_ld, P.ld.data(), sizeof(int) * P.S);
   if (e == hipSuccess) e = h2d(P.o_nct, P.nct.data(), sizeof(int) * P.S);
   if (e == hipSuccess) e = h2d(P.o_coP, P.coP.data(), sizeof(int64_t) * (P.S + 1));
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_rowver), (int64_t)P.R * P.rr_max, 0, st);
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_colver), (int64_t)P.S * P.ct_max, 0, st);
-  if (e == hipSuccess)
-    e = gmf::launch_fill_i32(c->at<int>(P.o_arr), (int64_t)P.nslot * (P.rr_max + P.ct_max + 1), 0, st);
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_phase), P.nslot, 0, st);
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_slotgen), P.nslot, 0, st);
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_abort), 4, 0, st);
-  if (e == hipSuccess) e = gmf::launch_fill_i32(c->at<int>(P.o_taskctr), 8, 0, st);
-  c->cnt_r.assign(P.R, 0);
-  c->cnt_s.assign(P.S, 0);
-  for (int wd = 0; wd < 2; ++wd) {
-    const int occ = gmf::steps_occupancy(P.prec, P.fam, P.KP, wd == 1);
-    c->capacity[wd] = std::max(1, occ) * std::max(1, prop.multiProcessorCount);
-  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete c;
@@ -803,6 +796,15 @@ int64_t gmf_steps_done(void* ctx) { return ctx ? as_ctx(ctx)->t : -1; }
 int gmf_sync(void* ctx) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   return check_flag(as_ctx(ctx));
+}
+
+int gmf_set_trace(void* ctx, void* buffer, int64_t records) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  c->trace = static_cast<unsigned long long*>(buffer);
+  c->trace_cap = buffer ? records : 0;
+  c->trace_used = 0;
+  return GMF_OK;
 }
 
 int gmf_set_timing(void* ctx, int32_t enable) {

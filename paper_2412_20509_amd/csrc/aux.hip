@@ -184,6 +184,68 @@ hipError_t launch_sumsq(const float* P, int KP, int64_t rows, int col0, int ncol
   return hipGetLastError();
 }
 
+// Squared Frobenius norms of B, Gamma, U, V (eq. 6 penalty) in one pass:
+// partial[k * gridDim.x + block] for k = 0..3 (fixed assignment and tree).
+__global__ void norms_kernel(const float* Prow, const float* Pcol, int KP, int64_t n, int64_t m,
+                             int p, int q, int d, double* partial) {
+  __shared__ double red[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t idx = start; idx < n * (q + d); idx += stride) {   // Gamma, U
+    const int64_t r = idx / (q + d);
+    const int c = (int)(idx % (q + d));
+    const double x = (double)Prow[r * KP + p + c];
+    acc[c < q ? 1 : 2] += x * x;
+  }
+  for (int64_t idx = start; idx < m * (p + d); idx += stride) {   // B, V
+    const int64_t r = idx / (p + d);
+    const int c = (int)(idx % (p + d));
+    const double x = (double)Pcol[r * KP + (c < p ? c : c + q)];
+    acc[c < p ? 0 : 3] += x * x;
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_norms(const float* Prow, const float* Pcol, int KP, int64_t n, int64_t m,
+                        int p, int q, int d, double* partial, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(norms_kernel, dim3(nblocks), dim3(256), 0, s, Prow, Pcol, KP, n, m, p, q, d,
+                     partial);
+  return hipGetLastError();
+}
+
+// out[0] = sum of dev[0..ndev), out[1+k] = sum of norm[k*nnorm .. (k+1)*nnorm).
+__global__ void finalize_kernel(const double* dev, int ndev, const double* norm, int nnorm,
+                                double* out) {
+  __shared__ double red[5][256];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < ndev; i += 256) acc[0] += dev[i];
+  if (norm)
+    for (int k = 0; k < 4; ++k)
+      for (int i = threadIdx.x; i < nnorm; i += 256) acc[1 + k] += norm[k * nnorm + i];
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm, double* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, dev, ndev, norm, nnorm, out);
+  return hipGetLastError();
+}
+
 // Ordered sum of `count` doubles by one workgroup (fixed assignment and tree).
 __global__ void sum_partials_kernel(const double* partial, int count, double* out) {
   __shared__ double red[256];
@@ -205,8 +267,10 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
 }
 
 // --------------------------------------------------------------- deviance --
-// One workgroup per (block, row range, column strip) of the step tiling; the
-// same 32x32 pieces and MFMA operand layout as the step kernel, float32 only.
+// One workgroup per (block, range of up to 256 rows, strip of 128 columns);
+// each wavefront owns 32 columns and walks the rows in groups of 32 with the
+// next group's counts and panel rows prefetched.  Same 32x32 pieces and MFMA
+// operand layout as the step kernel (float32 products).
 template <int FAM, int KP>
 __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   __shared__ float sP[kRowGroup][KP + 4];
@@ -229,6 +293,30 @@ __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
   const int colw = ct * kTileCols + wave * kWaveCols;
 
+  constexpr int PF = (kRowGroup * (KP / 4) + kTileThreads - 1) / kTileThreads;
+  auto load_p = [&](int rg, float4 (&pf)[PF]) {
+    for (int u = 0; u < PF; ++u) {
+      const int idx = tid + u * kTileThreads;
+      pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < kRowGroup * (KP / 4)) {
+        const int r = idx / (KP / 4), c4 = idx % (KP / 4);
+        if (rg + r < row_end) pf[u] = reinterpret_cast<const float4*>(Prow + (int64_t)(rg + r) * KP)[c4];
+      }
+    }
+  };
+  auto load_y = [&](int rg, float4 (&y)[2][2]) {
+    for (int R = 0; R < 2; ++R)
+      for (int C = 0; C < 2; ++C) {
+        const int row = rg + 2 * l16 + R;
+        const int colb = colw + 16 * C + 4 * g;
+        y[R][C] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < row_end && colb < ldy)
+          y[R][C] = *reinterpret_cast<const float4*>(Y + (int64_t)row * ldy + colb);
+      }
+  };
+  float4 pnext[PF], ynext[2][2];
+  load_p(row0, pnext);
+  load_y(row0, ynext);
   float pa[2][KP / 4];
   for (int c = 0; c < 2; ++c) {
     const int col = colw + 16 * c + l16;
@@ -237,40 +325,43 @@ __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   }
   double acc = 0.0;
   for (int rg = row0; rg < row_end; rg += kRowGroup) {
+    float4 ycur[2][2];
+    for (int R = 0; R < 2; ++R)
+      for (int C = 0; C < 2; ++C) ycur[R][C] = ynext[R][C];
     __syncthreads();
-    for (int idx = tid; idx < kRowGroup * (KP / 4); idx += kTileThreads) {
-      const int r = idx / (KP / 4), c4 = idx % (KP / 4);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (rg + r < n_b) v = reinterpret_cast<const float4*>(Prow + (int64_t)(rg + r) * KP)[c4];
-      sP[r][4 * c4 + 0] = v.x; sP[r][4 * c4 + 1] = v.y;
-      sP[r][4 * c4 + 2] = v.z; sP[r][4 * c4 + 3] = v.w;
+    for (int u = 0; u < PF; ++u) {
+      const int idx = tid + u * kTileThreads;
+      if (idx < kRowGroup * (KP / 4))
+        *reinterpret_cast<float4*>(&sP[idx / (KP / 4)][4 * (idx % (KP / 4))]) = pnext[u];
+    }
+    if (rg + kRowGroup < row_end) {
+      load_p(rg + kRowGroup, pnext);
+      load_y(rg + kRowGroup, ynext);
     }
     __syncthreads();
+    float grp = 0.f;
     for (int R = 0; R < 2; ++R) {
-      const int row = rg + 16 * R + l16;
+      const int lrow = 2 * l16 + R;
+      const int row = rg + lrow;
       for (int C = 0; C < 2; ++C) {
         // every lane takes part in the MFMA; masking happens afterwards
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
         for (int kk = 0; kk < KP / 4; ++kk)
-          e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], sP[16 * R + l16][4 * kk + g],
-                                                   e, 0, 0, 0);
+          e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], sP[lrow][4 * kk + g], e, 0, 0, 0);
         const int colb = colw + 16 * C + 4 * g;
-        if (row < n_b && colb < ldy) {
-          const float4 y4 = *reinterpret_cast<const float4*>(Y + (int64_t)row * ldy + colb);
-          float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
-          if (W) w4 = *reinterpret_cast<const float4*>(W + (int64_t)row * ldy + colb);
-          const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
-          const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
-          for (int v = 0; v < 4; ++v) {
-            if (colb + v < m_b) {
-              float x1, x2, dv = 0.f;
-              family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
-              acc += (double)dv;
-            }
-          }
+        float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
+        if (W && row < row_end && colb < ldy)
+          w4 = *reinterpret_cast<const float4*>(W + (int64_t)row * ldy + colb);
+        const float ys[4] = {ycur[R][C].x, ycur[R][C].y, ycur[R][C].z, ycur[R][C].w};
+        const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        for (int v = 0; v < 4; ++v) {
+          float x1, x2, dv = 0.f;
+          family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+          grp += (row < row_end && colb + v < m_b) ? dv : 0.f;
         }
       }
     }
+    acc += (double)grp;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) sDev[wave] = acc;

@@ -15,10 +15,12 @@
 //   Unit deviances (Supplementary Table 1 times 2; NB form of Appendix A):
 //   Poisson 2[y log(y/mu) - (y - mu)], NB 2[y log(y/mu) - (y+a) log((y+a)/(mu+a))],
 //   Gaussian (y - mu)^2.  For the log link log(mu) is the clamped eta itself;
-//   at y = 0 the NB term is 2 a log(1 + mu/a), formed without cancellation.
+//   the NB term uses (y+a)/(mu+a) = 1 + (y-mu)/(mu+a) and a log1p that keeps
+//   full relative accuracy when y is close to mu (and at y = 0).
 //
-// Arithmetic: hardware exp2/log2/reciprocal (1-ulp class), float32 per entry;
-// the callers accumulate deviances in float64.
+// Arithmetic: the hardware exp2 / log2 / reciprocal instructions (1-ulp
+// class, no denormal range reduction: every argument here is a normal number),
+// float32 per entry; the callers accumulate deviances in float64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,9 +29,16 @@
 
 namespace gmf {
 
-// log(1 + x) for x >= 0: series below 1/8 (truncation < 1e-8 relative),
-// the logarithm of 1 + x above.  Branch free.
-__device__ __forceinline__ float log1p_nonneg(float x) {
+__device__ __forceinline__ float fast_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+__device__ __forceinline__ float fast_log(float x) {
+  return __builtin_amdgcn_logf(x) * 0.6931471805599453f;
+}
+
+// log(1 + x) for x > -1: series for |x| < 1/8 (truncation below 1e-8
+// relative), the logarithm of 1 + x otherwise.  Branch free.
+__device__ __forceinline__ float log1p_small(float x) {
   float p = fmaf(x, -0.125f, 0.14285714f);
   p = fmaf(x, p, -0.16666667f);
   p = fmaf(x, p, 0.2f);
@@ -38,8 +47,8 @@ __device__ __forceinline__ float log1p_nonneg(float x) {
   p = fmaf(x, p, -0.5f);
   p = fmaf(x, p, 1.0f);
   const float series = x * p;
-  const float direct = __logf(1.0f + x);
-  return (x < 0.125f) ? series : direct;
+  const float direct = fast_log(1.0f + x);
+  return (fabsf(x) < 0.125f) ? series : direct;
 }
 
 // Per-launch constants of the epilogue.
@@ -70,13 +79,13 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
     if constexpr (WANT_DEV) dev = w * r * r;
   } else {
     const float ec = fminf(fmaxf(eta, c.lo), c.hi);
-    const float mu = __expf(ec);
+    const float mu = fast_exp(ec);
     if constexpr (FAM == kPoisson) {
       const float wp = w * c.phi_inv;
       d1 = wp * (mu - y);
       d2 = wp * mu;
       if constexpr (WANT_DEV) {
-        const float ly = __logf(fmaxf(y, 1.0f));
+        const float ly = fast_log(fmaxf(y, 1.0f));
         const float t = (y > 0.f) ? fmaf(y, ly - ec, mu - y) : mu;
         dev = 2.f * w * t;
       }
@@ -87,10 +96,11 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
       d1 = wa * (mu - y);
       d2 = wa * mu;
       if constexpr (WANT_DEV) {
-        const float ly = __logf(fmaxf(y, 1.0f));
-        const float pos = y * (ly - ec) - (y + c.a) * (__logf(y + c.a) - __logf(s));
-        const float zero = c.a * log1p_nonneg(mu * c.inv_a);
-        dev = 2.f * w * ((y > 0.f) ? pos : zero);
+        // y log(y/mu) - (y+a) log((y+a)/(mu+a)) with log(mu) = ec and
+        // (y+a)/(mu+a) = 1 + (y - mu)/(mu + a)
+        const float ylogy = (y > 0.f) ? y * fast_log(y) : 0.f;
+        const float t = ylogy - y * ec - (y + c.a) * log1p_small((y - mu) * inv);
+        dev = 2.f * w * t;
       }
     }
   }

@@ -29,19 +29,23 @@ struct FamilyArgs {
   float eta_hi;        // eta_max    (log link)
 };
 
-// One step of the schedule, filled on the host for a window of steps.
-struct StepDesc {
+// One step handed to a level launch, with its block geometry.
+struct LevelStep {
   int r, s;            // row block and column block
-  int slot;            // partial-buffer slot (t-1) mod nslot
-  int need_row;        // earlier steps on row block r (row-range versions to wait for)
-  int need_col;        // earlier steps on column block s
-  int need_slot;       // earlier users of the slot that must have finished
-  int pad0, pad1;
+  int slot;            // partial-buffer slot
+  int n_b, m_b;        // |I_r|, |J_s|
+  int n_rr, n_ct, rpw; // tiling: row ranges, column strips, rows per range
+  int ldy;             // padded row stride of the block
+  int ro, co;          // first permuted row / column of the block
+  int pad;
+  int64_t yoff;        // offset of the block in the block-major Y
   double stepsize;     // rho_t * alpha_t
   int64_t t;           // global step number (from 1)
 };
 
-struct StepKernelArgs {
+constexpr int kMaxLevelSteps = 32;   // tile steps + update steps per launch
+
+struct LevelArgs {
   // data in the workspace (permuted, block-major)
   const float* Y; const float* W;
   float* Prow; float* Pcol;
@@ -55,18 +59,8 @@ struct StepKernelArgs {
   // partial slots
   float* Upart; float* Vpart; double* devpart;
   int64_t slot_u_elems, slot_v_elems, slot_dev_elems;
-  // ordering state
-  int* rowver;   // [R][rr_max] updates applied to each row range
-  int* colver;   // [S][ct_max] updates applied to each column strip
-  int* arr;      // [nslot][rr_max + ct_max + 1] arrival counters
-  int* phase;    // [nslot] finished phases of the slot's current step
-  int* slotgen;  // [nslot] steps finished on the slot
-  int* abort_flag;
-  int spin_limit;
-  // schedule window and task queue
-  const StepDesc* desc; int desc_window;
-  int64_t t_first; int nsteps;
-  unsigned long long* task_ctr; unsigned long long task_base;
+  // update work split
+  int row_chunk, col_chunk, upd_per_step;
   // numerics
   FamilyArgs f;
   int p, q, d, KU, KV, KP;
@@ -74,12 +68,17 @@ struct StepKernelArgs {
   double a1, a2, damping;
   double* devring; int devring_len;
   int* err_flag;
+  // optional per-workgroup trace: 8 x u64 per workgroup (see gmf_set_trace)
+  unsigned long long* trace; long long trace_cap; unsigned long long trace_base;
+  unsigned long long launch_id;
+  // the steps of this launch: [0, n_tile_steps) run tiles, the next
+  // n_upd_steps run their updates
+  int n_tile_steps, n_upd_steps;
+  LevelStep steps[kMaxLevelSteps];
 };
 
-// ------------------------------------------------------------ launchers ----
-hipError_t launch_steps(int prec, int fam, int KP, bool want_dev, const StepKernelArgs& a,
-                        int grid, hipStream_t s);
-int steps_occupancy(int prec, int fam, int KP, bool want_dev);
+hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
+                        hipStream_t s);
 
 struct DevArgs {
   const float* Y; const float* W;
@@ -97,6 +96,10 @@ struct DevArgs {
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int count, double* out,
                                hipStream_t s);
+hipError_t launch_norms(const float* Prow, const float* Pcol, int KP, int64_t n, int64_t m,
+                        int p, int q, int d, double* partial, int nblocks, hipStream_t s);
+hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm, double* out,
+                           hipStream_t s);
 
 // Init / copy-out kernels.
 hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t n,

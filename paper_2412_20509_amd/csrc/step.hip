@@ -1,13 +1,11 @@
 // Block steps of the adaptive SGD for GMF (Algorithm 1, steps 2-4, with the
-// covariate extension of Appendix A) on gfx950, as one persistent launch.
+// covariate extension of Appendix A) on gfx950.
 //
-// Work decomposition.  Step t uses the block I_r x J_s.  The block is cut into
-// tiles: a range of `rpw` rows x a strip of 128 columns.  Tasks are the
-// (step, tile) pairs in increasing step order; workgroups claim them from an
-// atomic queue.  For every 32 x 32 piece of its tile a workgroup
+// Tiles.  Step t uses the block I_r x J_s, cut into tiles of `rpw` rows x 128
+// columns.  For every 32 x 32 piece of its tile a workgroup
 //   1. forms eta^T = [B|Z|V]_J [X|Gamma|U]_I^T on the matrix cores (MFMA
 //      16x16, K = padded p+q+d); sub-tile R of a 32-row group holds the rows
-//      2j + R, so that a lane's two sub-tiles cover adjacent rows;
+//      2j + R;
 //   2. applies the fused epilogue: clamp, inverse link, D1, D2, deviance;
 //   3. U side: D1 [Z,V]_J and D2 [Z^2,V^2]_J summed over its columns with MFMA
 //      (A = D1 straight from the eta accumulators);
@@ -15,23 +13,23 @@
 //      (A = D1^T after a transpose through LDS).
 // Nothing of the block (eta, mu, D1, D2) is written to memory; the tile writes
 // column-strip partial sums for its rows and row-range partial sums for its
-// columns into a slot of partial buffers.
+// columns into the step's slot of partial buffers.
 //
-// Updates.  The last tile to finish a row range sums that range's partials over
-// the column strips in a fixed order, scales by m/|J| (eq. 15), adds the ridge
-// term, updates the float64 EMAs (eq. 12) and takes the step
-// theta -= rho_t alpha_t Gbar/(Hbar + damping) (eq. 13-14) for [Gamma,U] of those
-// rows; the last tile of a column strip does the same for [B,V] of its
-// columns (scale n/|I|).  Both read only partials computed from the pre-step
-// parameters, so the two halves of a step see the same iterate.
+// Updates.  Row-chunk workgroups sum a chunk's partials over the column strips
+// in a fixed order, scale by m/|J| (eq. 15), add the ridge term, update the
+// float64 EMAs (eq. 12) and take theta -= rho_t alpha_t Gbar/(Hbar + damping)
+// (eq. 13-14) for [Gamma,U]; column-chunk workgroups do the same for [B,V]
+// (scale n/|I|); one workgroup sums the block deviance.  Both halves read only
+// partials computed from the pre-step parameters.
 //
-// Ordering.  A tile of step t waits until (a) every earlier step on row block r
-// has updated the tile's row range, (b) every earlier step on column block s has
-// updated its column strip, and (c) the previous user of its partial slot has
-// finished.  All three are counters published by earlier steps only, so the
-// lowest unfinished task can always run: the launch cannot deadlock, and steps
-// on disjoint blocks overlap while the result equals sequential execution.
-// Every wait is bounded; on expiry the launch aborts and reports an error.
+// Levels.  One launch runs the tiles of a set of steps ("level k") and the
+// updates of the steps of level k-1.  The host places step t at level
+// T(t) = 2 + max(T of the previous step on row block r, T of the previous step
+// on column block s, T of the previous user of its partial slot), so every
+// tile runs after the updates it depends on (earlier launch) and before any
+// later update of its rows or columns: the launches reproduce sequential
+// execution exactly while steps on disjoint blocks run side by side.  Kernel
+// boundaries are the only synchronisation.
 #include <hip/hip_runtime.h>
 
 #include "family.hpp"
@@ -80,6 +78,7 @@ struct TileView {
   int col0;                        // first column of the strip
   float* Upart;                    // this strip's partial rows: [n_b][2KU]
   float* Vpart;                    // this range's partial cols: [m_b][2KV]
+  unsigned long long* stamps;      // optional: 3 timestamps (profiling), or null
 };
 
 template <int PREC, int FAM, int KP, bool WANT_DEV>
@@ -163,23 +162,47 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       }
     }
   };
+  // row-panel rows of a group, float4 granules spread over the workgroup
+  constexpr int PF = (kRowGroup * (KP / 4) + kTileThreads - 1) / kTileThreads;
+  auto load_p = [&](int rg, float4 (&pf)[PF]) {
+    for (int u = 0; u < PF; ++u) {
+      const int idx = tid + u * kTileThreads;
+      pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < kRowGroup * (KP / 4)) {
+        const int r = idx / (KP / 4), c4 = idx % (KP / 4);
+        if (rg + r < tv.row_end)
+          pf[u] = reinterpret_cast<const float4*>(tv.Prow + (int64_t)(rg + r) * KP)[c4];
+      }
+    }
+  };
   float4 ynext[2][2];
+  float4 pnext[PF];
+  load_p(tv.row0, pnext);
   load_y(tv.row0, ynext);
+  if (tv.stamps && tid == 0) {
+    // operands in registers: force the loads to complete before stamping
+    float acc0 = 0.f;
+    if constexpr (PREC == kF32) acc0 = pa32[0][0] + ub32[0][0][0];
+    acc0 += ynext[0][0].x + pnext[0].x;
+    tv.stamps[0] = wall_clock64() + (acc0 == 12345.678f ? 1 : 0);
+  }
 
   for (int rg = tv.row0; rg < tv.row_end; rg += kRowGroup) {
     float4 ycur[2][2];
     for (int R = 0; R < 2; ++R)
       for (int C = 0; C < 2; ++C) ycur[R][C] = ynext[R][C];
     __syncthreads();   // previous group's readers of sP and of the wave buffers are done
-    for (int idx = tid; idx < kRowGroup * (KP / 4); idx += kTileThreads) {
-      const int r = idx / (KP / 4);
-      const int c4 = idx % (KP / 4);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (rg + r < tv.row_end) v = reinterpret_cast<const float4*>(tv.Prow + (int64_t)(rg + r) * KP)[c4];
-      *reinterpret_cast<float4*>(&L.sP[r][4 * c4]) = v;
+    for (int u = 0; u < PF; ++u) {
+      const int idx = tid + u * kTileThreads;
+      if (idx < kRowGroup * (KP / 4))
+        *reinterpret_cast<float4*>(&L.sP[idx / (KP / 4)][4 * (idx % (KP / 4))]) = pnext[u];
     }
-    if (rg + kRowGroup < tv.row_end) load_y(rg + kRowGroup, ynext);   // prefetch
+    if (rg + kRowGroup < tv.row_end) {   // prefetch the next group
+      load_p(rg + kRowGroup, pnext);
+      load_y(rg + kRowGroup, ynext);
+    }
     __syncthreads();
+    float dev_grp = 0.f;
 
     // ---- per 16-row sub-tile R: eta, epilogue, transpose store, U-side sums
     floatx4 ug[2][NB], uh[2][NB];
@@ -211,7 +234,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           const bool ok = row_ok && (colb + v < tv.m_b);
           d1[C][v] = ok ? x1 : 0.f;
           d2[C][v] = ok ? x2 : 0.f;
-          if constexpr (WANT_DEV) dev_acc += ok ? (double)dv : 0.0;
+          if constexpr (WANT_DEV) dev_grp += ok ? dv : 0.f;
         }
       }
       // transposed copies for the V side: sT[h][col][row]
@@ -246,6 +269,8 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
     __syncthreads();
 
+    if constexpr (WANT_DEV) dev_acc += (double)dev_grp;
+    if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
     for (int C = 0; C < 2; ++C) {
       if constexpr (PREC == kF32) {
@@ -297,6 +322,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
   }
 
+  if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
   // ---- V-side partial of this row range
   for (int C = 0; C < 2; ++C)
     for (int v = 0; v < 4; ++v) {
@@ -330,235 +356,185 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
 // ------------------------------------------------------------- updates ----
 // EMA + step for one parameter; returns false if the result is not finite.
 __device__ __forceinline__ bool ema_step(float* th, double* gm, double* hm, double G, double H,
-                                         const StepKernelArgs& a, double stepsize) {
-  const double gbar = (1.0 - a.a1) * (*gm) + a.a1 * G;
-  const double hbar = (1.0 - a.a2) * (*hm) + a.a2 * H;
+                                         double a1, double a2, double damping, double stepsize) {
+  const double gbar = (1.0 - a1) * (*gm) + a1 * G;
+  const double hbar = (1.0 - a2) * (*hm) + a2 * H;
   *gm = gbar;
   *hm = hbar;
-  const float nv = (float)((double)*th - stepsize * gbar / (hbar + a.damping));
+  const float nv = (float)((double)*th - stepsize * gbar / (hbar + damping));
   *th = nv;
   return isfinite(nv);
 }
 
-// Row range [row0, row_end) of block r: sum the n_ct strip partials.
-__device__ void update_rows(const StepKernelArgs& a, int row_first, int row0, int row_end,
-                            int n_b, int n_ct, const float* Ubase, double scale_m,
-                            double stepsize) {
+// Sum `nparts` partial segments (stride `part_stride` floats) element-wise in a
+// fixed order into sums[0..seg), seg <= blockDim.x; float64 accumulation.
+__device__ __forceinline__ void sum_segments(const float* base, int64_t part_stride, int nparts,
+                                             int seg, double* sums) {
+  const int i = threadIdx.x;
+  if (i < seg) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 8 <= nparts; k += 8) {
+      float v[8];
+      for (int u = 0; u < 8; ++u) v[u] = base[(int64_t)(k + u) * part_stride + i];
+      for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; k < nparts; ++k) acc += (double)base[(int64_t)k * part_stride + i];
+    sums[i] = acc;
+  }
+}
+
+template <int KP>
+struct UpdLds {
+  double sums[kTileThreads];
+};
+
+// Rows [row0, row1) of block r (block-local indices).
+__device__ void update_rows(const LevelArgs& a, const LevelStep& st, int row0, int row1,
+                            double* sums) {
+  const int n_b = st.n_b, m_b = st.m_b;
+  const int n_ct = st.n_ct;
   const int KU = a.KU;
-  const int items = (row_end - row0) * KU;
+  const float* U = a.Upart + (int64_t)st.slot * a.slot_u_elems;
+  const int seg = (row1 - row0) * 2 * KU;
+  sum_segments(U + (int64_t)row0 * 2 * KU, (int64_t)n_b * 2 * KU, n_ct, seg, sums);
+  __syncthreads();
+  const double scale_m = (double)a.m / m_b;
   bool ok = true;
-  for (int idx = threadIdx.x; idx < items; idx += blockDim.x) {
-    const int i = row0 + idx / KU;
-    const int o = idx % KU;
-    double sg = 0.0, sh = 0.0;
-    int c = 0;
-    for (; c + 4 <= n_ct; c += 4) {
-      float g4[4], h4[4];
-      for (int u = 0; u < 4; ++u) {
-        const float* src = Ubase + ((int64_t)(c + u) * n_b + i) * (2 * KU);
-        g4[u] = src[o];
-        h4[u] = src[KU + o];
-      }
-      for (int u = 0; u < 4; ++u) { sg += (double)g4[u]; sh += (double)h4[u]; }
-    }
-    for (; c < n_ct; ++c) {
-      const float* src = Ubase + ((int64_t)c * n_b + i) * (2 * KU);
-      sg += (double)src[o];
-      sh += (double)src[KU + o];
-    }
-    const int64_t grow = (int64_t)row_first + i;
+  for (int idx = threadIdx.x; idx < (row1 - row0) * KU; idx += blockDim.x) {
+    const int i = idx / KU, o = idx % KU;
+    const int64_t grow = (int64_t)st.ro + row0 + i;
     float* th = a.Prow + grow * a.KP + a.p + o;
     const double lam = (o < a.q) ? a.lam_A : a.lam_U;
     const double theta = (double)*th;
-    ok = ema_step(th, a.Grow + grow * KU + o, a.Hrow + grow * KU + o, scale_m * sg + lam * theta,
-                  scale_m * sh + lam, a, stepsize) && ok;
+    ok = ema_step(th, a.Grow + grow * KU + o, a.Hrow + grow * KU + o,
+                  scale_m * sums[i * 2 * KU + o] + lam * theta, scale_m * sums[i * 2 * KU + KU + o] + lam,
+                  a.a1, a.a2, a.damping, st.stepsize) && ok;
   }
   if (!ok) atomicOr(a.err_flag, 1);
 }
 
-// Column strip [col0, col_end) of block s: sum the n_rr range partials.
-__device__ void update_cols(const StepKernelArgs& a, int col_first, int col0, int col_end,
-                            int m_b, int n_rr, const float* Vbase, double scale_n,
-                            double stepsize) {
+// Columns [col0, col1) of block s (block-local indices).
+__device__ void update_cols(const LevelArgs& a, const LevelStep& st, int col0, int col1,
+                            double* sums) {
+  const int n_b = st.n_b, m_b = st.m_b;
+  const int n_rr = st.n_rr;
   const int KV = a.KV;
-  const int items = (col_end - col0) * KV;
+  const float* V = a.Vpart + (int64_t)st.slot * a.slot_v_elems;
+  const int seg = (col1 - col0) * 2 * KV;
+  sum_segments(V + (int64_t)col0 * 2 * KV, (int64_t)m_b * 2 * KV, n_rr, seg, sums);
+  __syncthreads();
+  const double scale_n = (double)a.n / n_b;
   bool ok = true;
-  for (int idx = threadIdx.x; idx < items; idx += blockDim.x) {
-    const int j = col0 + idx / KV;
-    const int o = idx % KV;
-    double sg = 0.0, sh = 0.0;
-    int rr = 0;
-    for (; rr + 8 <= n_rr; rr += 8) {
-      float g8[8], h8[8];
-      for (int u = 0; u < 8; ++u) {
-        const float* src = Vbase + ((int64_t)(rr + u) * m_b + j) * (2 * KV);
-        g8[u] = src[o];
-        h8[u] = src[KV + o];
-      }
-      for (int u = 0; u < 8; ++u) { sg += (double)g8[u]; sh += (double)h8[u]; }
-    }
-    for (; rr < n_rr; ++rr) {
-      const float* src = Vbase + ((int64_t)rr * m_b + j) * (2 * KV);
-      sg += (double)src[o];
-      sh += (double)src[KV + o];
-    }
-    const int64_t gcol = (int64_t)col_first + j;
+  for (int idx = threadIdx.x; idx < (col1 - col0) * KV; idx += blockDim.x) {
+    const int j = idx / KV, o = idx % KV;
+    const int64_t gcol = (int64_t)st.co + col0 + j;
     const int pc = (o < a.p) ? o : (o + a.q);
     float* th = a.Pcol + gcol * a.KP + pc;
     const double lam = (o < a.p) ? a.lam_B : a.lam_V;
     const double theta = (double)*th;
-    ok = ema_step(th, a.Gcol + gcol * KV + o, a.Hcol + gcol * KV + o, scale_n * sg + lam * theta,
-                  scale_n * sh + lam, a, stepsize) && ok;
+    ok = ema_step(th, a.Gcol + gcol * KV + o, a.Hcol + gcol * KV + o,
+                  scale_n * sums[j * 2 * KV + o] + lam * theta, scale_n * sums[j * 2 * KV + KV + o] + lam,
+                  a.a1, a.a2, a.damping, st.stepsize) && ok;
   }
   if (!ok) atomicOr(a.err_flag, 1);
 }
 
-// --------------------------------------------------------------- waits ----
-__device__ __forceinline__ int ld_agent(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Spin until *p >= need (thread 0 only).  Returns false on abort / expiry.
-__device__ bool wait_ge(const int* p, int need, const StepKernelArgs& a) {
-  for (int it = 0;; ++it) {
-    if (ld_agent(p) >= need) return true;
-    if (ld_agent(a.abort_flag) != 0) return false;
-    if (it >= a.spin_limit) {
-      atomicOr(a.err_flag, 8);
-      atomicExch(a.abort_flag, 1);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
+// Block deviance of the step: fixed-order tree over the tile partials.
+__device__ void sum_block_deviance(const LevelArgs& a, const LevelStep& st, double* sums) {
+  const int ntiles = st.n_rr * st.n_ct;
+  const double* D = a.devpart + (int64_t)st.slot * a.slot_dev_elems;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) acc += D[i];
+  sums[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sums[threadIdx.x] += sums[threadIdx.x + off];
+    __syncthreads();
   }
-}
-
-// Count one finished phase of the step in `slot`; the last phase opens the slot.
-__device__ void phase_done(const StepKernelArgs& a, int slot, int phases) {
-  if (threadIdx.x == 0) {
-    const int old = atomicAdd(a.phase + slot, 1);
-    if (old == phases - 1) {
-      atomicExch(a.phase + slot, 0);
-      __threadfence();
-      atomicAdd(a.slotgen + slot, 1);
-    }
-  }
+  if (threadIdx.x == 0) a.devring[(st.t - 1) % a.devring_len] = sums[0];
 }
 
 // ------------------------------------------------------------- kernel -----
 template <int PREC, int FAM, int KP, bool WANT_DEV>
-__global__ __launch_bounds__(kTileThreads, 2) void steps_kernel(StepKernelArgs a) {
-  __shared__ TileLds<PREC, KP> L;
-  const FamilyConst fc = family_const(a.f);
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
+  __shared__ union {
+    TileLds<PREC, KP> tile;
+    double sums[kTileThreads];
+  } L;
+  const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
+  __shared__ unsigned long long stamps[3];
   const int T = a.rr_max * a.ct_max;
-  const unsigned long long total = (unsigned long long)a.nsteps * T;
-
-  for (;;) {
-    if (tid == 0) L.task = atomicAdd(a.task_ctr, 1ull) - a.task_base;
-    __syncthreads();
-    const unsigned long long task = L.task;
-    __syncthreads();
-    if (task >= total) break;
-    const int k = (int)(task / T);
-    const int tile = (int)(task % T);
-    const int64_t t = a.t_first + k;
-    const StepDesc sd = a.desc[(t - 1) % a.desc_window];
-    const int r = sd.r, s = sd.s;
-    const int n_b = a.nrows[r], m_b = a.mcols[s];
-    const int n_rr = a.nrr[r], n_ct = a.nct[s], rpw = a.rpw[r];
+  const int ntile_blocks = a.n_tile_steps * T;
+  int b = blockIdx.x;
+  int kind = 0;
+  if (b < ntile_blocks) {
+    const LevelStep& st = a.steps[b / T];
+    const int tile = b % T;
+    const int n_b = st.n_b, m_b = st.m_b;
+    const int n_ct = st.n_ct, rpw = st.rpw;
     const int rr = tile / a.ct_max, ct = tile % a.ct_max;
-    if (rr >= n_rr || ct >= n_ct) continue;   // this block has fewer tiles
-
-    // ---- dependencies
-    if (tid == 0) {
-      bool ok = wait_ge(a.rowver + r * a.rr_max + rr, sd.need_row, a);
-      ok = ok && wait_ge(a.colver + s * a.ct_max + ct, sd.need_col, a);
-      ok = ok && wait_ge(a.slotgen + sd.slot, sd.need_slot, a);
-      L.flags[0] = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!L.flags[0]) continue;
-    __threadfence();
-
-    // ---- the tile
-    float* Uslot = a.Upart + (int64_t)sd.slot * a.slot_u_elems;
-    float* Vslot = a.Vpart + (int64_t)sd.slot * a.slot_v_elems;
-    double* Dslot = a.devpart + (int64_t)sd.slot * a.slot_dev_elems;
+    if (rr >= st.n_rr || ct >= n_ct) return;   // this block has fewer tiles
     TileView tv;
-    tv.ldy = a.ldy[s];
-    tv.Y = a.Y + (int64_t)a.ro[r] * a.LDtot + (int64_t)n_b * a.coP[s];
-    tv.W = a.W ? a.W + (int64_t)a.ro[r] * a.LDtot + (int64_t)n_b * a.coP[s] : nullptr;
-    tv.Prow = a.Prow + (int64_t)a.ro[r] * a.KP;
-    tv.Pcol = a.Pcol + (int64_t)a.co[s] * a.KP;
+    tv.ldy = st.ldy;
+    tv.Y = a.Y + st.yoff;
+    tv.W = a.W ? a.W + st.yoff : nullptr;
+    tv.Prow = a.Prow + (int64_t)st.ro * a.KP;
+    tv.Pcol = a.Pcol + (int64_t)st.co * a.KP;
     tv.n_b = n_b;
     tv.m_b = m_b;
     tv.row0 = rr * rpw;
     tv.row_end = min(n_b, (rr + 1) * rpw);
     tv.col0 = ct * kTileCols;
-    tv.Upart = Uslot + (int64_t)ct * n_b * (2 * a.KU);
-    tv.Vpart = Vslot + (int64_t)rr * m_b * (2 * a.KV);
-    const double dev = compute_tile<PREC, FAM, KP, WANT_DEV>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L);
-    if (tid == 0) Dslot[rr * n_ct + ct] = dev;
-
-    // ---- arrive
-    __threadfence();
-    __syncthreads();
-    int* arr = a.arr + (int64_t)sd.slot * (a.rr_max + a.ct_max + 1);
-    if (tid == 0) {
-      L.flags[1] = (atomicAdd(arr + rr, 1) == n_ct - 1);
-      L.flags[2] = (atomicAdd(arr + a.rr_max + ct, 1) == n_rr - 1);
-      L.flags[3] = (atomicAdd(arr + a.rr_max + a.ct_max, 1) == n_rr * n_ct - 1);
+    tv.Upart = a.Upart + (int64_t)st.slot * a.slot_u_elems + (int64_t)ct * n_b * (2 * a.KU);
+    tv.Vpart = a.Vpart + (int64_t)st.slot * a.slot_v_elems + (int64_t)rr * m_b * (2 * a.KV);
+    tv.stamps = a.trace ? stamps : nullptr;
+    const FamilyConst fc = family_const(a.f);
+    const double dev = compute_tile<PREC, FAM, KP, WANT_DEV>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
+    if (threadIdx.x == 0) a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
+  } else {
+    b -= ntile_blocks;
+    const int k = b / a.upd_per_step;
+    if (k >= a.n_upd_steps) return;
+    const LevelStep& st = a.steps[a.n_tile_steps + k];
+    int u = b % a.upd_per_step;
+    const int n_b = st.n_b, m_b = st.m_b;
+    const int nrc = (n_b + a.row_chunk - 1) / a.row_chunk;
+    const int ncc = (m_b + a.col_chunk - 1) / a.col_chunk;
+    if (u < nrc) {
+      kind = 1;
+      update_rows(a, st, u * a.row_chunk, min(n_b, (u + 1) * a.row_chunk), L.sums);
+    } else if ((u -= nrc) < ncc) {
+      kind = 2;
+      update_cols(a, st, u * a.col_chunk, min(m_b, (u + 1) * a.col_chunk), L.sums);
+    } else if (u == ncc) {
+      kind = 3;
+      if (WANT_DEV) sum_block_deviance(a, st, L.sums);
+    } else {
+      return;
     }
-    __syncthreads();
-    const int phases = n_rr + n_ct + 1;
-    if (L.flags[1]) {   // last tile of this row range: update [Gamma, U] of its rows
-      __threadfence();
-      update_rows(a, a.ro[r], tv.row0, tv.row_end, n_b, n_ct, Uslot, (double)a.m / m_b,
-                  sd.stepsize);
-      __threadfence();
-      __syncthreads();
-      if (tid == 0) {
-        atomicExch(arr + rr, 0);
-        __threadfence();
-        atomicAdd(a.rowver + r * a.rr_max + rr, 1);
-      }
-      phase_done(a, sd.slot, phases);
+  }
+  if (a.trace && threadIdx.x == 0) {
+    const long long gi = (long long)a.trace_base + blockIdx.x;
+    if (gi < a.trace_cap) {
+      unsigned long long* rec = a.trace + 8 * gi;
+      rec[0] = a.launch_id;
+      rec[1] = ((unsigned long long)blockIdx.x << 32) | (unsigned)kind;
+      rec[2] = tr0;
+      rec[3] = wall_clock64();
+      rec[4] = __smid();
+      rec[5] = kind == 0 ? stamps[0] : 0;
+      rec[6] = kind == 0 ? stamps[1] : 0;
+      rec[7] = kind == 0 ? stamps[2] : 0;
     }
-    if (L.flags[2]) {   // last tile of this column strip: update [B, V] of its columns
-      __threadfence();
-      update_cols(a, a.co[s], tv.col0, min(m_b, tv.col0 + kTileCols), m_b, n_rr, Vslot,
-                  (double)a.n / n_b, sd.stepsize);
-      __threadfence();
-      __syncthreads();
-      if (tid == 0) {
-        atomicExch(arr + a.rr_max + ct, 0);
-        __threadfence();
-        atomicAdd(a.colver + s * a.ct_max + ct, 1);
-      }
-      phase_done(a, sd.slot, phases);
-    }
-    if (L.flags[3]) {   // last tile of the step: block deviance in a fixed order
-      __threadfence();
-      if (tid == 0) {
-        if (WANT_DEV) {
-          double sum = 0.0;
-          for (int i = 0; i < n_rr * n_ct; ++i) sum += Dslot[i];
-          a.devring[(t - 1) % a.devring_len] = sum;
-        }
-        atomicExch(arr + a.rr_max + a.ct_max, 0);
-        __threadfence();
-      }
-      phase_done(a, sd.slot, phases);
-    }
-    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------ launchers ----
 template <int PREC, int FAM, int KP>
 static const void* kernel_ptr(bool want_dev) {
-  return want_dev ? reinterpret_cast<const void*>(&steps_kernel<PREC, FAM, KP, true>)
-                  : reinterpret_cast<const void*>(&steps_kernel<PREC, FAM, KP, false>);
+  return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true>)
+                  : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false>);
 }
 
 template <int PREC, int FAM>
@@ -572,7 +548,7 @@ static const void* kernel_ptr_kp(int KP, bool want_dev) {
   return nullptr;
 }
 
-const void* steps_kernel_for(int prec, int fam, int KP, bool want_dev) {
+static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev) {
   if (prec == kF32) {
     switch (fam) {
       case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev);
@@ -589,20 +565,13 @@ const void* steps_kernel_for(int prec, int fam, int KP, bool want_dev) {
   return nullptr;
 }
 
-hipError_t launch_steps(int prec, int fam, int KP, bool want_dev, const StepKernelArgs& a,
-                        int grid, hipStream_t s) {
-  const void* k = steps_kernel_for(prec, fam, KP, want_dev);
+hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
+                        hipStream_t s) {
+  const void* k = level_kernel_for(prec, fam, KP, want_dev);
   if (!k) return hipErrorInvalidValue;
-  void* args[] = {const_cast<StepKernelArgs*>(&a)};
+  if (grid <= 0) return hipSuccess;
+  void* args[] = {const_cast<LevelArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s);
-}
-
-int steps_occupancy(int prec, int fam, int KP, bool want_dev) {
-  const void* k = steps_kernel_for(prec, fam, KP, want_dev);
-  if (!k) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileThreads, 0) != hipSuccess) return 0;
-  return nb;
 }
 
 }  // namespace gmf

@@ -41,6 +41,7 @@ class gmf_config(C.Structure):
         ("alpha1", C.c_double), ("alpha2", C.c_double),
         ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
         ("seed", C.c_uint64),
+        ("tile_rows", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(i32)]),
         "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
                                         C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_set_trace": (C.c_int, [vp, vp, i64]),
         "gmf_set_timing": (C.c_int, [vp, i32]),
         "gmf_get_timing": (C.c_int, [vp, f64p, f64p, C.POINTER(i64)]),
         "gmf_steps_done": (i64, [vp]),
@@ -184,6 +186,10 @@ def gmf_schedule_host(seed: int, n: int, m: int, R: int, t_first: int = 1, count
     return np.array(rp)[:n], np.array(cp)[:m], np.array(rr)[:count]
 
 
+def gmf_set_trace(ctx, buffer, records: int):
+    return _check(load_library().gmf_set_trace(ctx, _ptr(buffer), int(records)))
+
+
 def gmf_set_timing(ctx, enable: bool):
     return _check(load_library().gmf_set_timing(ctx, int(bool(enable))))
 
@@ -230,6 +236,7 @@ class FitConfig:
     eta_max: float = 30.0
     bias_mode: int = 0
     seed: int = 0
+    tile_rows: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -246,6 +253,7 @@ class FitConfig:
         c.alpha1, c.alpha2 = self.alpha1, self.alpha2
         c.damping, c.eps, c.eta_max = self.damping, self.eps, self.eta_max
         c.seed = self.seed
+        c.tile_rows = self.tile_rows
         return c
 
 
@@ -330,6 +338,9 @@ class GMF:
 
     def schedule(self, t_first=1, count=0):
         return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)
+
+    def set_trace(self, buffer, records):
+        gmf_set_trace(self.ctx, buffer, records)
 
     def set_timing(self, enable):
         gmf_set_timing(self.ctx, enable)
