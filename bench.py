@@ -89,12 +89,12 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch):
     if t_hit is None:
         e_hit = None
 
-    # per-kernel timing with HIP events on the library's stream (2 more epochs)
+    # HIP events around every step launch on the library's stream (2 more epochs)
     g.set_timing(True)
     for _ in range(2):
         g.step(per_epoch)
         g.deviance()
-    tile_ms, upd_ms, nsteps = g.get_timing()
+    launch_ms, launches, nsteps = g.get_timing()
     g.set_timing(False)
     t_pp = time.perf_counter()
     g.params(postprocess=1)
@@ -105,8 +105,34 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch):
                 ms_per_epoch=1e3 * wall / epochs, final_deviance=final,
                 rel_to_oracle=(abs(final - dstar) / dstar) if dstar else None,
                 s_to_1e4=t_hit, epochs_to_1e4=e_hit,
-                tile_ms_mean=tile_ms / max(nsteps, 1), update_ms_mean=upd_ms / max(nsteps, 1),
-                timed_steps=nsteps, postprocess_s=t_pp)
+                launch_ms_total=launch_ms, launches=int(launches), timed_steps=nsteps,
+                postprocess_s=t_pp)
+
+
+def run_throughput(pr, precision, epochs, torch):
+    """Steps-only throughput of a large workload: epochs/s, launch roofline and
+    the time of one full-deviance evaluation."""
+    per_epoch = pr.R * pr.S
+    g = make_gmf(pr, precision)
+    g.step(per_epoch)                  # warm-up epoch
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    t0 = time.perf_counter()
+    g.step(epochs * per_epoch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms, launches, nsteps = g.get_timing()
+    g.set_timing(False)
+    t1 = time.perf_counter()
+    dev, _ = g.deviance()
+    t_dev = time.perf_counter() - t1
+    g.close()
+    bytes_step = tile_bytes_per_launch(pr)
+    achieved = nsteps * bytes_step / (launch_ms * 1e-3) / 1e9
+    return dict(epochs=epochs, epochs_per_s=epochs / wall, ms_per_epoch=1e3 * wall / epochs,
+                launches=int(launches), steps=nsteps, launch_ms_total=launch_ms,
+                bytes_per_step=bytes_step, achieved_GBs=achieved, hbm_frac=achieved / HBM_PEAK_GBS,
+                deviance_eval_s=t_dev, deviance=dev)
 
 
 def cpu_baseline(pr, epochs=3):
@@ -135,6 +161,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3, help="untimed warm-up epochs")
     ap.add_argument("--arms", default="fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 100000x5000 rank-20 throughput section")
+    ap.add_argument("--large-epochs", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -155,16 +184,31 @@ def main():
     for prec in args.arms.split(","):
         log(f"arm {prec}: {args.warmup} warm-up + {args.steps} timed epochs")
         arms[prec] = run_arm(pr, prec, args.steps, args.warmup, dstar, torch)
-        log(f"arm {prec}: {arms[prec]['epochs_per_s']:.1f} epochs/s, "
-            f"tile {1e3 * arms[prec]['tile_ms_mean']:.2f} us")
+        log(f"arm {prec}: {arms[prec]['epochs_per_s']:.1f} epochs/s")
 
     main_arm = arms.get("fp32") or next(iter(arms.values()))
-    bytes_launch = tile_bytes_per_launch(pr)
-    achieved = bytes_launch / (main_arm["tile_ms_mean"] * 1e-3) / 1e9
-    roof = dict(bound="hbm", kernel="tile_kernel<FP32,NB,KP=16>", achieved=achieved,
+    bytes_step = tile_bytes_per_launch(pr)
+    bytes_launch = bytes_step * main_arm["timed_steps"] / max(main_arm["launches"], 1)
+    mean_launch_s = main_arm["launch_ms_total"] * 1e-3 / max(main_arm["launches"], 1)
+    achieved = bytes_launch / mean_launch_s / 1e9
+    roof = dict(bound="hbm", kernel="level_kernel<FP32,NB,KP=16,dev>", achieved=achieved,
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                 traffic=None, bytes_per_launch=bytes_launch,
-                mean_launch_us=1e3 * main_arm["tile_ms_mean"])
+                mean_launch_us=1e6 * mean_launch_s, steps_per_launch=main_arm["timed_steps"] /
+                max(main_arm["launches"], 1))
+    large = None
+    if not args.no_large:
+        log("generating the 100000x5000 NB workload (rank 20)")
+        pr3 = make_problem("c3")
+        large = {}
+        for prec in ("bf16", "fp32"):
+            log(f"large workload, arm {prec}: 1 warm-up + {args.large_epochs} timed epochs")
+            large[prec] = run_throughput(pr3, prec, args.large_epochs, torch)
+            log(f"large {prec}: {large[prec]['epochs_per_s']:.1f} epochs/s, "
+                f"{large[prec]['achieved_GBs']:.0f} GB/s")
+        large["workload"] = ("NB GMF 100000x5000, d=20, p=3, q=1, alpha=5, blocks 10000x1000 "
+                             "(R=10, S=5); steps only, one full deviance timed separately")
+        del pr3
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
@@ -181,7 +225,7 @@ def main():
                     n=pr.n, m=pr.m, d=pr.d, p=pr.p, q=pr.q, R=pr.R, S=pr.S,
                     zero_fraction=float((pr.Y == 0).mean())),
         s_to_1e4=main_arm["s_to_1e4"], epochs_to_1e4=main_arm["epochs_to_1e4"],
-        oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu,
+        oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu, large=large,
         arms={k: {kk: vv for kk, vv in v.items()} for k, v in arms.items()},
     )
     print(json.dumps(out))

@@ -78,13 +78,13 @@ typedef struct gmf_config {
   double eta_max;     /* eta ceiling for the log link                         */
   uint64_t seed;      /* schedule seed: partitions and row-block draws        */
   int32_t tile_rows;  /* rows per step tile (multiple of 32), 0 = automatic   */
-  int32_t reserved;   /* must be 0                                            */
+  int32_t skip_block_deviance; /* 1: steps do not form the block deviance   */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
- * bias_mode=0, seed=0, tile_rows=0. */
+ * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -117,8 +117,9 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
  * derivatives D1 = -w(y-mu)/(phi nu g'), D2 = w/(phi nu g'^2) (Section 3),
  * the minibatch gradients of eq. 15 / Appendix A for [Gamma,U]_I and [B,V]_J
  * from the pre-step parameters, the EMAs of eq. 12 (float64) and the step
- * theta -= rho_t alpha_t Gbar / (Hbar + damping) (eq. 13-14).  It also records
- * the block deviance sum_B w D(y, mu) (float64).  Asynchronous.
+ * theta -= rho_t alpha_t Gbar / (Hbar + damping) (eq. 13-14).  Unless
+ * cfg.skip_block_deviance is set it also records the block deviance
+ * sum_B w D(y, mu) (float64, see gmf_block_deviance).  Asynchronous.
  * Errors: GMF_EINVAL (nsteps < 0), GMF_EDEVICE. */
 int gmf_step(void* ctx, int64_t nsteps);
 
@@ -189,6 +190,32 @@ int gmf_schedule_host(uint64_t seed, int64_t n, int64_t m, int32_t R, int64_t t_
 int gmf_set_timing(void* ctx, int32_t enable);
 int gmf_get_timing(void* ctx, double* launch_ms_host, double* launches_host,
                    int64_t* steps_host);
+
+/* gmf_project_workspace_bytes -- device bytes gmf_project needs for n_new
+ * new rows of the context's shape (0 on error). */
+size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new);
+
+/* gmf_project -- fit the row side [Gamma, U] of n_new new rows with the column
+ * side frozen (B, Z, V of the context), by the row half of Algorithm 1 (its
+ * step 4, with the covariate form of Appendix A): step t (from 1) uses every
+ * new row and column block J_{(t-1) mod S} of the context's partition,
+ * G = (m/|J|) D1 [Z,V]_J + lambda [0_A, U] style ridge terms as in gmf_step,
+ * float64 EMAs starting at zero, step rho_t alpha_t Gbar/(Hbar + damping).
+ * Rows are independent (the objective is convex in each row given V, eq. 7).
+ *   ws / ws_bytes: caller device workspace (gmf_project_workspace_bytes).
+ *   Ynew n_new x m (y_dtype as in gmf_init), Xnew n_new x p (NULL if p = 0).
+ *   A0 n_new x q, U0 n_new x d: starting values.
+ *   epochs: S steps each.  frozen = 0: the context's raw iterate; 1: its
+ *   Algorithm 2 (A + B1) projection, computed in float64.
+ *   A_out, U_out (device, may alias A0/U0): results.  dev_trace_host (may be
+ *   NULL): epochs + 1 values, the deviance of the new rows before the first
+ *   step and after every epoch.
+ * Enqueued on the context's stream; synchronises when dev_trace_host is set.
+ * The context's own iterate is not changed. */
+int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
+                int64_t n_new, const float* Xnew, const float* A0, const float* U0,
+                int32_t epochs, int32_t frozen, float* A_out, float* U_out,
+                double* dev_trace_host);
 
 /* gmf_set_trace -- record a timeline of the step tasks into a caller device
  * buffer of `records` x 8 uint64 (NULL disables): per task of the following

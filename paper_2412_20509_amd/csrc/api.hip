@@ -117,6 +117,8 @@ std::string check_config(const gmf_config* c) {
   if (!(c->damping >= 0) || !(c->eps > 0) || !std::isfinite(c->eta_max)) return "bad damping/eps/eta_max";
   for (int i = 0; i < 4; ++i)
     if (!(c->lambda[i] >= 0)) return "lambda must be >= 0";
+  if (c->skip_block_deviance != 0 && c->skip_block_deviance != 1)
+    return "skip_block_deviance must be 0 or 1";
   if (c->tile_rows < 0 || c->tile_rows % 32 != 0 || c->tile_rows > 4096)
     return "tile_rows must be 0 or a multiple of 32 up to 4096";
   return "";
@@ -294,6 +296,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   const Plan& P = c->P;
   const gmf_config& cf = c->cfg;
   gmf::LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
   a.Y = c->at<float>(P.o_Yb);
   a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
   a.Prow = c->at<float>(P.o_Prow);
@@ -336,6 +339,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   a.trace_cap = c->trace_cap;
   a.trace_base = 0;
   a.launch_id = 0;
+  a.row_only = 0;
   a.n_tile_steps = a.n_upd_steps = 0;
   return a;
 }
@@ -523,6 +527,7 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
                                     std::to_string(P.total) + " bytes");
   }
   c->ws = static_cast<char*>(workspace);
+  c->want_block_dev = cfg->skip_block_deviance ? 0 : 1;
   c->st = static_cast<hipStream_t>(stream);
   c->row_perm = shuffle(cfg->seed, 0, P.n);
   c->col_perm = shuffle(cfg->seed, 1, P.m);
@@ -682,6 +687,7 @@ int gmf_block_deviance(void* ctx, double* out_host, int64_t count) {
   if (!ctx || !out_host) return fail(GMF_EINVAL, "NULL argument");
   Ctx* c = as_ctx(ctx);
   if (count < 0 || count > c->t || count > kDevRing) return fail(GMF_EINVAL, "bad count");
+  if (!c->want_block_dev) return fail(GMF_EINVAL, "block deviance is off (skip_block_deviance)");
   std::vector<double> ring(kDevRing);
   HIP_TRY(hipMemcpyAsync(ring.data(), c->at<double>(c->P.o_devring), sizeof(double) * kDevRing,
                          hipMemcpyDeviceToHost, c->st));
@@ -796,6 +802,229 @@ int64_t gmf_steps_done(void* ctx) { return ctx ? as_ctx(ctx)->t : -1; }
 int gmf_sync(void* ctx) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   return check_flag(as_ctx(ctx));
+}
+
+// ------------------------------------------------------------ projection --
+namespace {
+
+struct ProjPlan {
+  int64_t n_new = 0;
+  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_per_step = 0;
+  int64_t slot_u = 0;
+  size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
+      o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
+      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, total;
+};
+
+bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
+  const Plan& P = c->P;
+  if (n_new < 1 || n_new > ((int64_t)1 << 31) - 1) return false;
+  Q.n_new = n_new;
+  int rpw = round_up((int)std::min<double>(2048.0, std::ceil((double)n_new * P.ct_max / kTilesPerStepTarget)),
+                     gmf::kRowGroup);
+  Q.rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
+  Q.nrr = (int)((n_new + Q.rpw - 1) / Q.rpw);
+  Q.dev_rpw = dev_rows_per_wg((int)std::min<int64_t>(n_new, 1 << 30));
+  Q.dev_tiles = 0;
+  for (int s = 0; s < P.S; ++s) Q.dev_tiles += (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];
+  Q.slot_u = ((int64_t)P.ct_max * n_new * 2 * P.KU + 63) / 64 * 64;
+  Q.upd_per_step = (int)((n_new + P.row_chunk - 1) / P.row_chunk) + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  Q.o_Yb = take(sizeof(float) * (size_t)n_new * P.LDtot);
+  Q.o_Prow = take(sizeof(float) * (size_t)n_new * P.KP);
+  Q.o_Pcol = take(sizeof(float) * (size_t)P.m * P.KP);
+  Q.o_Grow = take(sizeof(double) * (size_t)n_new * P.KU);
+  Q.o_Hrow = take(sizeof(double) * (size_t)n_new * P.KU);
+  Q.o_Upart = take(sizeof(float) * (size_t)Q.slot_u * 2);
+  Q.o_devpart = take(sizeof(double) * 64);
+  Q.o_iota = take(sizeof(int) * (size_t)n_new);
+  Q.o_zero = take(sizeof(int) * (size_t)n_new);
+  Q.o_rowbase = take(sizeof(int64_t));
+  Q.o_nrows = take(sizeof(int));
+  Q.o_tileblk = take(sizeof(int) * (size_t)Q.dev_tiles);
+  Q.o_tilefirst = take(sizeof(int) * P.S);
+  Q.o_byoff = take(sizeof(int64_t) * P.S);
+  Q.o_brow0 = take(sizeof(int) * P.S);
+  Q.o_bcol0 = take(sizeof(int) * P.S);
+  Q.o_bnb = take(sizeof(int) * P.S);
+  Q.o_bmb = take(sizeof(int) * P.S);
+  Q.o_bldy = take(sizeof(int) * P.S);
+  Q.o_brpw = take(sizeof(int) * P.S);
+  Q.o_bnct = take(sizeof(int) * P.S);
+  Q.o_devpartial = take(sizeof(double) * (size_t)Q.dev_tiles);
+  Q.o_scal = take(sizeof(double) * 16);
+  Q.o_tmpB = take(sizeof(float) * (size_t)P.m * std::max(P.p, 1));
+  Q.o_tmpZ = take(sizeof(float) * (size_t)P.m * std::max(P.q, 1));
+  Q.o_tmpV = take(sizeof(float) * (size_t)P.m * P.d);
+  Q.total = o;
+  return true;
+}
+
+}  // namespace
+
+extern "C" size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new) {
+  if (!ctx) return 0;
+  ProjPlan Q;
+  if (!make_proj_plan(as_ctx(ctx), n_new, Q)) return 0;
+  return Q.total;
+}
+
+extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
+                           int64_t n_new, const float* Xnew, const float* A0, const float* U0,
+                           int32_t epochs, int32_t frozen, float* A_out, float* U_out,
+                           double* dev_trace_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  ProjPlan Q;
+  if (!make_proj_plan(c, n_new, Q)) return fail(GMF_EINVAL, "bad n_new");
+  if (!Ynew || !U0 || !U_out || (P.p > 0 && !Xnew) || (P.q > 0 && (!A0 || !A_out)))
+    return fail(GMF_EINVAL, "missing array");
+  if (y_dtype != GMF_Y_INT32 && y_dtype != GMF_Y_FLOAT32) return fail(GMF_EINVAL, "bad y_dtype");
+  if (epochs < 0) return fail(GMF_EINVAL, "epochs < 0");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < Q.total)
+    return fail(GMF_EWORKSPACE, "projection workspace NULL, misaligned or smaller than " +
+                                    std::to_string(Q.total) + " bytes");
+  char* W = static_cast<char*>(ws);
+  auto at = [&](size_t off) { return W + off; };
+  hipStream_t st = c->st;
+  // ---- tables: one row block (all new rows), the context's column blocks
+  HIP_TRY(gmf::launch_iota(reinterpret_cast<int*>(at(Q.o_iota)), n_new, st));
+  HIP_TRY(gmf::launch_fill_i32(reinterpret_cast<int*>(at(Q.o_zero)), n_new, 0, st));
+  const int64_t rowbase = 0;
+  const int nrows = (int)n_new;
+  HIP_TRY(hipMemcpyAsync(at(Q.o_rowbase), &rowbase, sizeof(rowbase), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(at(Q.o_nrows), &nrows, sizeof(nrows), hipMemcpyHostToDevice, st));
+  std::vector<int> tileblk(Q.dev_tiles), tilefirst(P.S), brow0(P.S, 0), bcol0(P.S), bnb(P.S), bmb(P.S),
+      bldy(P.S), brpw(P.S, Q.dev_rpw), bnct(P.S);
+  std::vector<int64_t> byoff(P.S);
+  int tc = 0;
+  for (int s = 0; s < P.S; ++s) {
+    tilefirst[s] = tc;
+    byoff[s] = (int64_t)n_new * P.coP[s];
+    bcol0[s] = P.co[s];
+    bnb[s] = (int)n_new;
+    bmb[s] = P.mcols[s];
+    bldy[s] = P.ld[s];
+    bnct[s] = P.nct[s];
+    const int tiles = (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];
+    for (int k = 0; k < tiles; ++k) tileblk[tc++] = s;
+  }
+  HIP_TRY(hipMemcpyAsync(at(Q.o_tileblk), tileblk.data(), sizeof(int) * tileblk.size(), hipMemcpyHostToDevice, st));
+#define PH2D(off, vec) HIP_TRY(hipMemcpyAsync(at(Q.off), vec.data(), sizeof(vec[0]) * vec.size(), hipMemcpyHostToDevice, st))
+  PH2D(o_tilefirst, tilefirst); PH2D(o_byoff, byoff); PH2D(o_brow0, brow0); PH2D(o_bcol0, bcol0);
+  PH2D(o_bnb, bnb); PH2D(o_bmb, bmb); PH2D(o_bldy, bldy); PH2D(o_brpw, brpw); PH2D(o_bnct, bnct);
+#undef PH2D
+  // ---- data: Y in column-block-major order, the new row panel, the frozen column panel
+  float* Yb = reinterpret_cast<float*>(at(Q.o_Yb));
+  HIP_TRY(hipMemsetAsync(Yb, 0, sizeof(float) * (size_t)n_new * P.LDtot, st));
+  HIP_TRY(gmf::launch_permute_y(Ynew, y_dtype == GMF_Y_INT32, nullptr, n_new, P.m,
+                                reinterpret_cast<int*>(at(Q.o_zero)), reinterpret_cast<int*>(at(Q.o_iota)),
+                                c->at<int>(P.o_colblk), c->at<int>(P.o_colloc),
+                                reinterpret_cast<int64_t*>(at(Q.o_rowbase)), reinterpret_cast<int*>(at(Q.o_nrows)),
+                                c->at<int64_t>(P.o_blkcoloff), c->at<int>(P.o_blkld), Yb, nullptr,
+                                c->at<int>(P.o_flag), st));
+  float* Prow = reinterpret_cast<float*>(at(Q.o_Prow));
+  HIP_TRY(gmf::launch_pack_panel(Xnew, P.p, A0, P.q, U0, P.d, reinterpret_cast<int*>(at(Q.o_iota)), n_new,
+                                 P.KP, Prow, st));
+  float* Pcol = reinterpret_cast<float*>(at(Q.o_Pcol));
+  if (frozen) {
+    float* tB = reinterpret_cast<float*>(at(Q.o_tmpB));
+    float* tZ = reinterpret_cast<float*>(at(Q.o_tmpZ));
+    float* tV = reinterpret_cast<float*>(at(Q.o_tmpV));
+    gmf::PostArgs pa;
+    pa.Prow = c->at<float>(P.o_Prow);
+    pa.Pcol = c->at<float>(P.o_Pcol);
+    pa.n = P.n; pa.m = P.m; pa.p = P.p; pa.q = P.q; pa.d = P.d; pa.KP = P.KP;
+    pa.row_perm = c->at<int>(P.o_rowperm);
+    pa.col_perm = c->at<int>(P.o_colperm);
+    pa.gram_part = c->at<double>(P.o_post);
+    pa.small = nullptr;
+    pa.first_nz = c->at<int>(P.o_firstnz);
+    pa.err_flag = c->at<int>(P.o_flag);
+    pa.B = P.p > 0 ? tB : nullptr; pa.A = nullptr; pa.U = nullptr; pa.V = tV;
+    pa.nblocks_row = kSumsqBlocks; pa.nblocks_col = kSumsqBlocks;
+    HIP_TRY(gmf::launch_postprocess(pa, st));
+    HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, c->at<int>(P.o_colperm), P.m, P.p, P.q, tZ, st));
+    HIP_TRY(gmf::launch_pack_panel(tB, P.p, tZ, P.q, tV, P.d, c->at<int>(P.o_colperm), P.m, P.KP, Pcol, st));
+  } else {
+    HIP_TRY(hipMemcpyAsync(Pcol, c->at<float>(P.o_Pcol), sizeof(float) * (size_t)P.m * P.KP,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  double* Grow = reinterpret_cast<double*>(at(Q.o_Grow));
+  double* Hrow = reinterpret_cast<double*>(at(Q.o_Hrow));
+  HIP_TRY(gmf::launch_fill_f64(Grow, n_new * P.KU, 0.0, st));
+  HIP_TRY(gmf::launch_fill_f64(Hrow, n_new * P.KU, 0.0, st));
+
+  // ---- deviance of the new rows
+  gmf::DevArgs da;
+  da.Y = Yb; da.W = nullptr; da.Prow = Prow; da.Pcol = Pcol;
+  da.tile_block = reinterpret_cast<int*>(at(Q.o_tileblk));
+  da.tile_first = reinterpret_cast<int*>(at(Q.o_tilefirst));
+  da.blk_yoff = reinterpret_cast<int64_t*>(at(Q.o_byoff));
+  da.blk_row0 = reinterpret_cast<int*>(at(Q.o_brow0));
+  da.blk_col0 = reinterpret_cast<int*>(at(Q.o_bcol0));
+  da.blk_nb = reinterpret_cast<int*>(at(Q.o_bnb));
+  da.blk_mb = reinterpret_cast<int*>(at(Q.o_bmb));
+  da.blk_ldy = reinterpret_cast<int*>(at(Q.o_bldy));
+  da.blk_rpw = reinterpret_cast<int*>(at(Q.o_brpw));
+  da.blk_nct = reinterpret_cast<int*>(at(Q.o_bnct));
+  da.f = family_args(c->cfg);
+  da.partial = reinterpret_cast<double*>(at(Q.o_devpartial));
+  da.n_tiles = Q.dev_tiles;
+  double* scal = reinterpret_cast<double*>(at(Q.o_scal));
+  auto proj_dev = [&](double* out) -> int {
+    HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, st));
+    HIP_TRY(gmf::launch_finalize(da.partial, Q.dev_tiles, nullptr, 0, scal, st));
+    HIP_TRY(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GMF_OK;
+  };
+  if (dev_trace_host) {
+    const int rc = proj_dev(dev_trace_host);
+    if (rc != GMF_OK) return rc;
+  }
+
+  // ---- the row-side steps: tiles of step t, then its row updates
+  gmf::LevelArgs a = level_args(c);
+  a.Y = Yb; a.W = nullptr; a.Prow = Prow; a.Pcol = Pcol;
+  a.Grow = Grow; a.Hrow = Hrow; a.Gcol = nullptr; a.Hcol = nullptr;
+  a.Upart = reinterpret_cast<float*>(at(Q.o_Upart));
+  a.Vpart = nullptr;
+  a.devpart = reinterpret_cast<double*>(at(Q.o_devpart));
+  a.slot_u_elems = Q.slot_u; a.slot_v_elems = 0; a.slot_dev_elems = 0;
+  a.rr_max = Q.nrr;
+  a.upd_per_step = Q.upd_per_step;
+  a.row_only = 1;
+  a.trace = nullptr;
+  const int T = Q.nrr * P.ct_max;
+  for (int e = 0; e < epochs; ++e) {
+    for (int k = 0; k < P.S; ++k) {
+      const int64_t t = (int64_t)e * P.S + k + 1;
+      gmf::LevelStep stp;
+      stp.r = 0; stp.s = k; stp.slot = (int)(t & 1);
+      stp.n_b = (int)n_new; stp.m_b = P.mcols[k];
+      stp.n_rr = Q.nrr; stp.n_ct = P.nct[k]; stp.rpw = Q.rpw;
+      stp.ldy = P.ld[k]; stp.ro = 0; stp.co = P.co[k]; stp.pad = 0;
+      stp.yoff = (int64_t)n_new * P.coP[k];
+      stp.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
+      stp.t = t;
+      a.steps[0] = stp;
+      a.n_tile_steps = 1; a.n_upd_steps = 0;
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, a, T, st));
+      a.n_tile_steps = 0; a.n_upd_steps = 1;
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, a, Q.upd_per_step, st));
+    }
+    if (dev_trace_host) {
+      const int rc = proj_dev(dev_trace_host + e + 1);
+      if (rc != GMF_OK) return rc;
+    }
+  }
+  const int* iota = reinterpret_cast<int*>(at(Q.o_iota));
+  HIP_TRY(gmf::launch_unpack_panel(Prow, P.KP, iota, n_new, P.p, P.q, A_out, st));
+  HIP_TRY(gmf::launch_unpack_panel(Prow, P.KP, iota, n_new, P.p + P.q, P.d, U_out, st));
+  return check_flag(c);
 }
 
 int gmf_set_trace(void* ctx, void* buffer, int64_t records) {

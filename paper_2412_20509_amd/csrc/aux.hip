@@ -73,6 +73,16 @@ hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t
   return hipGetLastError();
 }
 
+__global__ void iota_kernel(int* p, int64_t count) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) p[idx] = (int)idx;
+}
+hipError_t launch_iota(int* p, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------- panels ---------
 __global__ void pack_panel_kernel(const float* M0, int c0, const float* M1, int c1,
                                   const float* M2, int c2, const int* perm,

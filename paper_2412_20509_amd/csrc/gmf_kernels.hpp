@@ -71,6 +71,7 @@ struct LevelArgs {
   // optional per-workgroup trace: 8 x u64 per workgroup (see gmf_set_trace)
   unsigned long long* trace; long long trace_cap; unsigned long long trace_base;
   unsigned long long launch_id;
+  int row_only;        // projection: no column-side sums or updates
   // the steps of this launch: [0, n_tile_steps) run tiles, the next
   // n_upd_steps run their updates
   int n_tile_steps, n_upd_steps;
@@ -117,6 +118,7 @@ hipError_t launch_unpack_moments(const double* M, int K, const int* perm,
                                  int64_t rows, double* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t s);
+hipError_t launch_iota(int* p, int64_t count, hipStream_t s);
 hipError_t launch_sumsq(const float* P, int KP, int64_t rows, int col0, int ncols,
                         double* partial, int nblocks, hipStream_t s);
 

@@ -79,6 +79,7 @@ struct TileView {
   float* Upart;                    // this strip's partial rows: [n_b][2KU]
   float* Vpart;                    // this range's partial cols: [m_b][2KV]
   unsigned long long* stamps;      // optional: 3 timestamps (profiling), or null
+  bool row_only;                   // skip the column-side (V) sums
 };
 
 template <int PREC, int FAM, int KP, bool WANT_DEV>
@@ -238,12 +239,13 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         }
       }
       // transposed copies for the V side: sT[h][col][row]
-      for (int C = 0; C < 2; ++C)
-        for (int v = 0; v < 4; ++v) {
-          const int cc = 16 * C + 4 * g + v;
-          sT[0][cc][lrow] = (TE)d1[C][v];
-          sT[1][cc][lrow] = (TE)d2[C][v];
-        }
+      if (!tv.row_only)
+        for (int C = 0; C < 2; ++C)
+          for (int v = 0; v < 4; ++v) {
+            const int cc = 16 * C + 4 * g + v;
+            sT[0][cc][lrow] = (TE)d1[C][v];
+            sT[1][cc][lrow] = (TE)d2[C][v];
+          }
       // U side: G_U[row][o] = sum over this wavefront's cols of D1[row][col] P[col][o]
       for (int ob = 0; ob < NB; ++ob) {
         ug[R][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -272,7 +274,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     if constexpr (WANT_DEV) dev_acc += (double)dev_grp;
     if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
-    for (int C = 0; C < 2; ++C) {
+    for (int C = 0; C < 2 && !tv.row_only; ++C) {
       if constexpr (PREC == kF32) {
         const float4 ta = *reinterpret_cast<const float4*>(&sT[0][16 * C + l16][8 * g]);
         const float4 tb = *reinterpret_cast<const float4*>(&sT[0][16 * C + l16][8 * g + 4]);
@@ -324,7 +326,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
 
   if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
   // ---- V-side partial of this row range
-  for (int C = 0; C < 2; ++C)
+  for (int C = 0; C < 2 && !tv.row_only; ++C)
     for (int v = 0; v < 4; ++v) {
       const int col = colw + 16 * C + 4 * g + v;
       if (col < tv.m_b) {
@@ -489,9 +491,11 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
     tv.Upart = a.Upart + (int64_t)st.slot * a.slot_u_elems + (int64_t)ct * n_b * (2 * a.KU);
     tv.Vpart = a.Vpart + (int64_t)st.slot * a.slot_v_elems + (int64_t)rr * m_b * (2 * a.KV);
     tv.stamps = a.trace ? stamps : nullptr;
+    tv.row_only = a.row_only != 0;
     const FamilyConst fc = family_const(a.f);
     const double dev = compute_tile<PREC, FAM, KP, WANT_DEV>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
-    if (threadIdx.x == 0) a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
+    if (WANT_DEV && threadIdx.x == 0)
+      a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
   } else {
     b -= ntile_blocks;
     const int k = b / a.upd_per_step;
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
     int u = b % a.upd_per_step;
     const int n_b = st.n_b, m_b = st.m_b;
     const int nrc = (n_b + a.row_chunk - 1) / a.row_chunk;
-    const int ncc = (m_b + a.col_chunk - 1) / a.col_chunk;
+    const int ncc = a.row_only ? 0 : (m_b + a.col_chunk - 1) / a.col_chunk;
     if (u < nrc) {
       kind = 1;
       update_rows(a, st, u * a.row_chunk, min(n_b, (u + 1) * a.row_chunk), L.sums);

@@ -41,7 +41,7 @@ class gmf_config(C.Structure):
         ("alpha1", C.c_double), ("alpha2", C.c_double),
         ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
         ("seed", C.c_uint64),
-        ("tile_rows", C.c_int32), ("reserved", C.c_int32),
+        ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
     ]
 
 
@@ -81,6 +81,9 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(i32)]),
         "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
                                         C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_project_workspace_bytes": (C.c_size_t, [vp, i64]),
+        "gmf_project": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, vp, i32, i32, vp, vp,
+                                  f64p]),
         "gmf_set_trace": (C.c_int, [vp, vp, i64]),
         "gmf_set_timing": (C.c_int, [vp, i32]),
         "gmf_get_timing": (C.c_int, [vp, f64p, f64p, C.POINTER(i64)]),
@@ -186,6 +189,20 @@ def gmf_schedule_host(seed: int, n: int, m: int, R: int, t_first: int = 1, count
     return np.array(rp)[:n], np.array(cp)[:m], np.array(rr)[:count]
 
 
+def gmf_project_workspace_bytes(ctx, n_new: int) -> int:
+    return load_library().gmf_project_workspace_bytes(ctx, int(n_new))
+
+
+def gmf_project(ctx, workspace, Ynew, y_dtype, n_new, Xnew, A0, U0, epochs, frozen, A_out,
+                U_out, trace: bool = False):
+    tr = (C.c_double * (epochs + 1))() if trace else None
+    _check(load_library().gmf_project(ctx, _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _ptr(Ynew),
+                                      y_dtype, int(n_new), _ptr(Xnew), _ptr(A0), _ptr(U0),
+                                      int(epochs), int(frozen), _ptr(A_out), _ptr(U_out), tr))
+    return None if tr is None else list(tr)
+
+
 def gmf_set_trace(ctx, buffer, records: int):
     return _check(load_library().gmf_set_trace(ctx, _ptr(buffer), int(records)))
 
@@ -237,6 +254,7 @@ class FitConfig:
     bias_mode: int = 0
     seed: int = 0
     tile_rows: int = 0
+    skip_block_deviance: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -254,6 +272,7 @@ class FitConfig:
         c.damping, c.eps, c.eta_max = self.damping, self.eps, self.eta_max
         c.seed = self.seed
         c.tile_rows = self.tile_rows
+        c.skip_block_deviance = self.skip_block_deviance
         return c
 
 
@@ -338,6 +357,36 @@ class GMF:
 
     def schedule(self, t_first=1, count=0):
         return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)
+
+    def project(self, Ynew, Xnew, A0, U0, epochs, frozen=0, trace=False):
+        """Row-side fit of new rows with the column side frozen (gmf_project)."""
+        t = self.torch
+        n_new = Ynew.shape[0]
+        nbytes = gmf_project_workspace_bytes(self.ctx, n_new)
+        if nbytes == 0:
+            raise GMFError(GMF_EINVAL, "bad n_new")
+        ws = t.empty(nbytes + 256, dtype=t.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        wsv = ws[off:off + nbytes]
+        if isinstance(Ynew, t.Tensor):
+            Yt = Ynew.to(self.device).contiguous()
+            ydt = GMF_Y_INT32 if Yt.dtype == t.int32 else GMF_Y_FLOAT32
+        elif np.issubdtype(np.asarray(Ynew).dtype, np.integer):
+            Yt = t.as_tensor(np.ascontiguousarray(Ynew, dtype=np.int32), device=self.device)
+            ydt = GMF_Y_INT32
+        else:
+            Yt = t.as_tensor(np.ascontiguousarray(Ynew, dtype=np.float32), device=self.device)
+            ydt = GMF_Y_FLOAT32
+        conv = lambda a, c: (None if c == 0 else
+                             (a.to(self.device).float().contiguous() if isinstance(a, t.Tensor) else
+                              t.as_tensor(np.ascontiguousarray(a, np.float32).reshape(n_new, c),
+                                          device=self.device)))
+        Xt, At, Ut = conv(Xnew, self.p), conv(A0, self.q), conv(U0, self.d)
+        Ao = t.empty((n_new, self.q), dtype=t.float32, device=self.device) if self.q else None
+        Uo = t.empty((n_new, self.d), dtype=t.float32, device=self.device)
+        tr = gmf_project(self.ctx, wsv, Yt, ydt, n_new, Xt, At, Ut, epochs, frozen, Ao, Uo, trace)
+        self.stream.synchronize()
+        return Ao, Uo, tr
 
     def set_trace(self, buffer, records):
         gmf_set_trace(self.ctx, buffer, records)

@@ -18,6 +18,7 @@ which are not available; shapes follow the paper's settings):
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -95,6 +96,22 @@ def gen_poisson_small(n=1000, m=500, d=5, R=10, S=5, seed=1001):
                    true=dict(B=beta0, A=gamma0, U=U, V=V))
 
 
+_PAR = {}
+_PAR_THRESHOLD = 100_000_000   # matrices with more entries are sampled in parallel
+
+
+def _sample_chunk(job):
+    """Counts of rows r0..r1 (chunk k): own PCG64 stream seeded with (seed, k)."""
+    r0, r1, k = job
+    d = _PAR
+    mu = np.exp(d["X"][r0:r1] @ d["B"].T + d["G"][r0:r1] @ d["Z"].T + d["U"][r0:r1] @ d["V"].T)
+    rng = np.random.Generator(np.random.PCG64([d["seed"], k]))
+    if d["family"] == "negbin":
+        a = d["alpha"]
+        return rng.negative_binomial(a, a / (a + mu)).astype(np.int32)
+    return rng.poisson(mu).astype(np.int32)
+
+
 def _nb_zero_frac(eta, alpha):
     mu = np.exp(eta)
     return float(np.mean((alpha / (alpha + mu)) ** alpha))
@@ -143,14 +160,28 @@ def gen_nb(n=10_000, m=2_000, d=10, R=10, S=5, alpha=5.0, zero_frac=0.85,
     B[:, 0] += c
 
     Y = np.empty((n, m), dtype=np.int32)
-    yr = _rng(seed + 11)
-    for r0 in range(0, n, chunk_rows):
-        r1 = min(n, r0 + chunk_rows)
-        mu = np.exp(X[r0:r1] @ B.T + gamma0[r0:r1] @ Z.T + U[r0:r1] @ V.T)
-        if family == "negbin":
-            Y[r0:r1] = yr.negative_binomial(alpha, alpha / (alpha + mu))
-        else:
-            Y[r0:r1] = yr.poisson(mu)
+    if n * m < _PAR_THRESHOLD:
+        yr = _rng(seed + 11)
+        for r0 in range(0, n, chunk_rows):
+            r1 = min(n, r0 + chunk_rows)
+            mu = np.exp(X[r0:r1] @ B.T + gamma0[r0:r1] @ Z.T + U[r0:r1] @ V.T)
+            if family == "negbin":
+                Y[r0:r1] = yr.negative_binomial(alpha, alpha / (alpha + mu))
+            else:
+                Y[r0:r1] = yr.poisson(mu)
+    else:
+        # large matrices: row chunks of `chunk_rows`, chunk k drawn from its own
+        # PCG64 stream seeded with (seed + 11, k), in a process pool
+        import multiprocessing as mp
+        _PAR.update(X=X, B=B, G=gamma0, Z=Z, U=U, V=V, seed=seed + 11, family=family,
+                    alpha=alpha)
+        jobs = [(r0, min(n, r0 + chunk_rows), k)
+                for k, r0 in enumerate(range(0, n, chunk_rows))]
+        workers = max(1, min(16, (os.cpu_count() or 1)))
+        with mp.get_context("fork").Pool(workers) as pool:
+            for (r0, r1, _), block in zip(jobs, pool.imap(_sample_chunk, jobs)):
+                Y[r0:r1] = block
+        _PAR.clear()
     B0, A0, U0, V0 = _start_values(_rng(seed + 2000), Y, X, Z, d, "poisson")
     return Problem(family, "log", n, m, d, 3, 1, R, S, Y, X, Z, B0, A0, U0, V0,
                    nb_alpha=alpha, sched_seed=seed + 1000,
