@@ -217,6 +217,59 @@ int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t 
                 int32_t epochs, int32_t frozen, float* A_out, float* U_out,
                 double* dev_trace_host);
 
+/* ---------------------------------------------------------------------------
+ * Warm-start encoder.  An MLP maps a row's counts to its latent scores:
+ * x = log(1 + y_i) (m values) -> Linear(m, H) -> GELU -> Linear(H, H) -> GELU
+ * -> Linear(H, d), GELU(z) = z Phi(z).  It is trained on (row, fitted u_i)
+ * pairs by minimising the mean squared error with Adam (bias-corrected
+ * moments, optional decoupled weight decay) in float32 on the matrix cores,
+ * and runs inference with bfloat16 operands (float32 accumulation) or float32.
+ * The weights live in the caller's workspace; the layout of each weight is
+ * row-major (out x in); biases are vectors.
+ * ------------------------------------------------------------------------- */
+typedef struct gmf_mlp_config {
+  int32_t m;          /* input width (columns of Y)                      */
+  int32_t hidden;     /* hidden width H                                   */
+  int32_t d;          /* output width (rank)                              */
+  int32_t batch;      /* minibatch rows per Adam step                     */
+  double lr, beta1, beta2, eps, weight_decay;
+} gmf_mlp_config;
+
+/* Defaults: m=1, hidden=256, d=1, batch=256, lr=1e-3, beta1=0.9,
+ * beta2=0.999, eps=1e-8, weight_decay=0. */
+void gmf_mlp_config_default(gmf_mlp_config* cfg);
+/* Device workspace bytes of an encoder (0 for an invalid cfg). */
+size_t gmf_encoder_workspace_bytes(const gmf_mlp_config* cfg);
+/* gmf_encoder_init -- copy the starting weights (device arrays: W1 H x m,
+ * b1 H, W2 H x H, b2 H, W3 d x H, b3 d) into the workspace and zero the Adam
+ * moments.  Synchronises.  Errors: GMF_EINVAL, GMF_EWORKSPACE, GMF_EDEVICE. */
+int gmf_encoder_init(void** enc_out, const gmf_mlp_config* cfg, void* ws, size_t ws_bytes,
+                     void* stream, const float* W1, const float* b1, const float* W2,
+                     const float* b2, const float* W3, const float* b3);
+/* gmf_encoder_train -- `epochs` passes over nrows (Y row-major nrows x m,
+ * y_dtype as in gmf_init; U nrows x d targets), minibatches of cfg.batch
+ * consecutive rows in the given order, one Adam step per minibatch.
+ * loss_trace_host (may be NULL): the mean training loss of every epoch
+ * (synchronises once per epoch when given). */
+int gmf_encoder_train(void* enc, const void* Y, int32_t y_dtype, const float* U, int64_t nrows,
+                      int32_t epochs, double* loss_trace_host);
+/* gmf_encoder_forward -- U_out (nrows x d, device) = encoder(Y); bf16 != 0
+ * uses bfloat16 operands.  Enqueued. */
+int gmf_encoder_forward(void* enc, const void* Y, int32_t y_dtype, int64_t nrows, float* U_out,
+                        int32_t bf16);
+/* gmf_encoder_loss_grad -- for one minibatch (nrows <= cfg.batch) compute the
+ * mean squared error and its gradient without updating: grad_out (device, may
+ * be NULL) receives the flat gradient [W1, b1, W2, b2, W3, b3] in the weight
+ * layouts above.  Synchronises. */
+int gmf_encoder_loss_grad(void* enc, const void* Y, int32_t y_dtype, const float* U, int64_t nrows,
+                          double* loss_host, float* grad_out);
+/* Copy the current weights out (device arrays, any may be NULL). */
+int gmf_encoder_get_weights(void* enc, float* W1, float* b1, float* W2, float* b2, float* W3,
+                            float* b3);
+void gmf_encoder_destroy(void* enc);
+/* Message for the last failing encoder call on this thread. */
+const char* gmf_encoder_last_error(void);
+
 /* gmf_set_trace -- record a timeline of the step tasks into a caller device
  * buffer of `records` x 8 uint64 (NULL disables): per task of the following
  * launches, in claim order across launches: [0] step t, [1] (workgroup << 32)

@@ -45,6 +45,12 @@ class gmf_config(C.Structure):
     ]
 
 
+class gmf_mlp_config(C.Structure):
+    _fields_ = [("m", C.c_int32), ("hidden", C.c_int32), ("d", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("weight_decay", C.c_double)]
+
+
 class GMFError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libgmf error {code}: {msg}")
@@ -84,6 +90,16 @@ def load_library(path: str = LIB_PATH):
         "gmf_project_workspace_bytes": (C.c_size_t, [vp, i64]),
         "gmf_project": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, vp, i32, i32, vp, vp,
                                   f64p]),
+        "gmf_mlp_config_default": (None, [C.POINTER(gmf_mlp_config)]),
+        "gmf_encoder_workspace_bytes": (C.c_size_t, [C.POINTER(gmf_mlp_config)]),
+        "gmf_encoder_init": (C.c_int, [C.POINTER(vp), C.POINTER(gmf_mlp_config), vp, C.c_size_t,
+                                       vp, vp, vp, vp, vp, vp, vp]),
+        "gmf_encoder_train": (C.c_int, [vp, vp, i32, vp, i64, i32, f64p]),
+        "gmf_encoder_forward": (C.c_int, [vp, vp, i32, i64, vp, i32]),
+        "gmf_encoder_loss_grad": (C.c_int, [vp, vp, i32, vp, i64, f64p, vp]),
+        "gmf_encoder_get_weights": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "gmf_encoder_destroy": (None, [vp]),
+        "gmf_encoder_last_error": (C.c_char_p, []),
         "gmf_set_trace": (C.c_int, [vp, vp, i64]),
         "gmf_set_timing": (C.c_int, [vp, i32]),
         "gmf_get_timing": (C.c_int, [vp, f64p, f64p, C.POINTER(i64)]),
@@ -407,6 +423,117 @@ class GMF:
         if getattr(self, "ctx", None) is not None:
             gmf_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ encoder ----
+
+def _echeck(rc):
+    if rc != GMF_OK:
+        raise GMFError(rc, load_library().gmf_encoder_last_error().decode())
+    return rc
+
+
+class Encoder:
+    """Warm-start MLP encoder (gmf_encoder_*): weights in a torch workspace."""
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, m, d, weights, hidden=256, batch=256, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, weight_decay=0.0, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        lib = load_library()
+        cfg = gmf_mlp_config()
+        lib.gmf_mlp_config_default(C.byref(cfg))
+        cfg.m, cfg.hidden, cfg.d, cfg.batch = m, hidden, d, batch
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay = lr, beta1, beta2, eps, weight_decay
+        self.cfg = cfg
+        self.m, self.d, self.hidden = m, d, hidden
+        nbytes = lib.gmf_encoder_workspace_bytes(C.byref(cfg))
+        if nbytes == 0:
+            raise GMFError(GMF_EINVAL, "invalid encoder configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        ws = self.workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        w = [torch.as_tensor(np.ascontiguousarray(weights[k], np.float32), device=self.device)
+             for k in self.NAMES]
+        self.enc = C.c_void_p()
+        _echeck(lib.gmf_encoder_init(C.byref(self.enc), C.byref(cfg), ws.data_ptr(), nbytes,
+                                     self.stream.cuda_stream, *[t.data_ptr() for t in w]))
+        self.nparam = (hidden * m + hidden + hidden * hidden + hidden + d * hidden + d)
+
+    def _y(self, Y):
+        t = self.torch
+        if isinstance(Y, t.Tensor):
+            Yt = Y.to(self.device).contiguous()
+            return Yt, (GMF_Y_INT32 if Yt.dtype == t.int32 else GMF_Y_FLOAT32)
+        if np.issubdtype(np.asarray(Y).dtype, np.integer):
+            return t.as_tensor(np.ascontiguousarray(Y, np.int32), device=self.device), GMF_Y_INT32
+        return t.as_tensor(np.ascontiguousarray(Y, np.float32), device=self.device), GMF_Y_FLOAT32
+
+    def _u(self, U):
+        t = self.torch
+        if isinstance(U, t.Tensor):
+            return U.to(self.device).float().contiguous()
+        return t.as_tensor(np.ascontiguousarray(U, np.float32), device=self.device)
+
+    def train(self, Y, U, epochs, trace=True):
+        Yt, ydt = self._y(Y)
+        Ut = self._u(U)
+        tr = (C.c_double * max(epochs, 1))() if trace else None
+        _echeck(load_library().gmf_encoder_train(self.enc, Yt.data_ptr(), ydt, Ut.data_ptr(),
+                                                 Yt.shape[0], int(epochs), tr))
+        self.stream.synchronize()
+        return list(tr)[:epochs] if trace else None
+
+    def forward(self, Y, bf16=True):
+        t = self.torch
+        Yt, ydt = self._y(Y)
+        out = t.empty((Yt.shape[0], self.d), dtype=t.float32, device=self.device)
+        _echeck(load_library().gmf_encoder_forward(self.enc, Yt.data_ptr(), ydt, Yt.shape[0],
+                                                   out.data_ptr(), int(bool(bf16))))
+        self.stream.synchronize()
+        return out
+
+    def loss_grad(self, Y, U):
+        t = self.torch
+        Yt, ydt = self._y(Y)
+        Ut = self._u(U)
+        g = t.empty(self.nparam, dtype=t.float32, device=self.device)
+        loss = C.c_double()
+        _echeck(load_library().gmf_encoder_loss_grad(self.enc, Yt.data_ptr(), ydt, Ut.data_ptr(),
+                                                     Yt.shape[0], C.byref(loss), g.data_ptr()))
+        gn = g.cpu().numpy().astype(np.float64)
+        H, m, d = self.hidden, self.m, self.d
+        out, o = {}, 0
+        for k, shp in (("W1", (H, m)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)),
+                       ("W3", (d, H)), ("b3", (d,))):
+            sz = int(np.prod(shp))
+            out[k] = gn[o:o + sz].reshape(shp)
+            o += sz
+        return loss.value, out
+
+    def weights(self):
+        t = self.torch
+        H, m, d = self.hidden, self.m, self.d
+        shapes = {"W1": (H, m), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (d, H), "b3": (d,)}
+        ts = {k: t.empty(s, dtype=t.float32, device=self.device) for k, s in shapes.items()}
+        _echeck(load_library().gmf_encoder_get_weights(self.enc, *[ts[k].data_ptr()
+                                                                   for k in self.NAMES]))
+        return {k: v.cpu().numpy().astype(np.float64) for k, v in ts.items()}
+
+    def close(self):
+        if getattr(self, "enc", None) is not None and self.enc.value:
+            load_library().gmf_encoder_destroy(self.enc)
+            self.enc = None
 
     def __del__(self):
         try:

@@ -96,20 +96,37 @@ def gen_poisson_small(n=1000, m=500, d=5, R=10, S=5, seed=1001):
                    true=dict(B=beta0, A=gamma0, U=U, V=V))
 
 
-_PAR = {}
 _PAR_THRESHOLD = 100_000_000   # matrices with more entries are sampled in parallel
 
 
-def _sample_chunk(job):
+def _sample_chunk(par, r0, r1, k):
     """Counts of rows r0..r1 (chunk k): own PCG64 stream seeded with (seed, k)."""
-    r0, r1, k = job
-    d = _PAR
-    mu = np.exp(d["X"][r0:r1] @ d["B"].T + d["G"][r0:r1] @ d["Z"].T + d["U"][r0:r1] @ d["V"].T)
-    rng = np.random.Generator(np.random.PCG64([d["seed"], k]))
-    if d["family"] == "negbin":
-        a = d["alpha"]
+    mu = np.exp(par["X"][r0:r1] @ par["B"].T + par["G"][r0:r1] @ par["Z"].T
+                + par["U"][r0:r1] @ par["V"].T)
+    rng = np.random.Generator(np.random.PCG64([par["seed"], k]))
+    if par["family"] == "negbin":
+        a = par["alpha"]
         return rng.negative_binomial(a, a / (a + mu)).astype(np.int32)
     return rng.poisson(mu).astype(np.int32)
+
+
+def _parallel_counts(Y, par, chunk_rows):
+    """Fill Y by row chunks of `chunk_rows` in a thread pool (numpy's samplers
+    release the GIL); chunk k always draws from the stream (seed, k), so the
+    result does not depend on the number of threads.  Threads rather than
+    processes: callers may already hold a GPU context, which must not be
+    duplicated into forked children."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = Y.shape[0]
+    jobs = [(r0, min(n, r0 + chunk_rows), k) for k, r0 in enumerate(range(0, n, chunk_rows))]
+
+    def run(job):
+        r0, r1, k = job
+        Y[r0:r1] = _sample_chunk(par, r0, r1, k)
+
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(run, jobs))
 
 
 def _nb_zero_frac(eta, alpha):
@@ -171,17 +188,9 @@ def gen_nb(n=10_000, m=2_000, d=10, R=10, S=5, alpha=5.0, zero_frac=0.85,
                 Y[r0:r1] = yr.poisson(mu)
     else:
         # large matrices: row chunks of `chunk_rows`, chunk k drawn from its own
-        # PCG64 stream seeded with (seed + 11, k), in a process pool
-        import multiprocessing as mp
-        _PAR.update(X=X, B=B, G=gamma0, Z=Z, U=U, V=V, seed=seed + 11, family=family,
-                    alpha=alpha)
-        jobs = [(r0, min(n, r0 + chunk_rows), k)
-                for k, r0 in enumerate(range(0, n, chunk_rows))]
-        workers = max(1, min(16, (os.cpu_count() or 1)))
-        with mp.get_context("fork").Pool(workers) as pool:
-            for (r0, r1, _), block in zip(jobs, pool.imap(_sample_chunk, jobs)):
-                Y[r0:r1] = block
-        _PAR.clear()
+        # PCG64 stream seeded with (seed + 11, k)
+        _parallel_counts(Y, dict(X=X, B=B, G=gamma0, Z=Z, U=U, V=V, seed=seed + 11,
+                                 family=family, alpha=alpha), chunk_rows)
     B0, A0, U0, V0 = _start_values(_rng(seed + 2000), Y, X, Z, d, "poisson")
     return Problem(family, "log", n, m, d, 3, 1, R, S, Y, X, Z, B0, A0, U0, V0,
                    nb_alpha=alpha, sched_seed=seed + 1000,
@@ -256,3 +265,42 @@ def make_problem(name: str, **over) -> Problem:
     if kind == "poisson":
         return gen_poisson_small(**cfg)
     return gen_nb(**cfg)
+
+
+def mlp_init(m, hidden, d, seed=4001):
+    """Starting weights of the warm-start encoder (m -> hidden -> hidden -> d):
+    each layer's weights and biases uniform on +-1/sqrt(fan_in), float32."""
+    rng = _rng(seed)
+    out = {}
+    for name, (fo, fi) in (("1", (hidden, m)), ("2", (hidden, hidden)), ("3", (d, hidden))):
+        lim = 1.0 / np.sqrt(fi)
+        out["W" + name] = _f32(rng.uniform(-lim, lim, size=(fo, fi)))
+        out["b" + name] = _f32(rng.uniform(-lim, lim, size=fo))
+    return out
+
+
+def gen_nb_rows(pr, n_new, seed=5005, chunk_rows=4096):
+    """New rows for a problem from gen_nb: the same column side (B, Z, V and
+    alpha of ``pr.true``) and fresh row draws (batch indicator, covariate,
+    row intercept N(0, 0.5^2), scores N(0, 0.5^2)).  Returns (Y, X, U_true,
+    gamma_true)."""
+    rng = _rng(seed)
+    d = pr.d
+    batch = np.zeros(n_new)
+    batch[rng.permutation(n_new)[: n_new // 2]] = 1.0
+    X = _f32(np.column_stack([np.ones(n_new), batch, rng.normal(0.0, 1.0, size=n_new)]))
+    gamma0 = rng.normal(0.0, 0.5, size=(n_new, 1))
+    U = rng.normal(0.0, 0.5, size=(n_new, d))
+    B, V = pr.true["B"], pr.true["V"]
+    Y = np.empty((n_new, pr.m), dtype=np.int32)
+    if n_new * pr.m < _PAR_THRESHOLD:
+        yr = _rng(seed + 11)
+        for r0 in range(0, n_new, chunk_rows):
+            r1 = min(n_new, r0 + chunk_rows)
+            mu = np.exp(X[r0:r1] @ B.T + gamma0[r0:r1] @ pr.Z.T + U[r0:r1] @ V.T)
+            a = pr.nb_alpha
+            Y[r0:r1] = yr.negative_binomial(a, a / (a + mu)) if pr.family == "negbin" else yr.poisson(mu)
+    else:
+        _parallel_counts(Y, dict(X=X, B=B, G=gamma0, Z=pr.Z, U=U, V=V, seed=seed + 11,
+                                 family=pr.family, alpha=pr.nb_alpha), chunk_rows)
+    return Y, X, U, gamma0
