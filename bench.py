@@ -17,8 +17,10 @@ Printed JSON line:
                     (relative) of D*, the FP64 oracle's deviance after 200
                     epochs of the same seeded schedule (tests/golden)
   roofline          dominant kernel (the fused tile kernel): algorithmic
-                    bytes per launch / mean launch time from HIP events on the
-                    library's stream, against the 8 TB/s HBM peak
+                    bytes per launch / mean launch time from HIP events stamped
+                    by the launches themselves on the library's stream, against
+                    the 8 TB/s HBM peak; traffic = measured HBM bytes per launch
+                    (rocprofv3 counters, summary under profiles/)
   cpu_baseline      the FP64 oracle on the host, bounded sample
   arms              the same measurements for the BF16 arm
 """
@@ -52,6 +54,25 @@ def make_gmf(pr, precision):
     fc = FitConfig(family=pr.family, link=pr.link, precision=precision, d=pr.d, R=pr.R,
                    S=pr.S, phi=pr.phi, nb_alpha=pr.nb_alpha, seed=pr.sched_seed)
     return GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the headline step kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
+    changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_level_kernel_nb10000x2000_nb100000x5000.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+) source: ([0-9a-f]+)", open(path).read())
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in ("step.hip", "family.hpp"):
+        with open(os.path.join(ROOT, "paper_2412_20509_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return float(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
 
 
 def tile_bytes_per_launch(pr):
@@ -164,6 +185,9 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 100000x5000 rank-20 throughput section")
     ap.add_argument("--large-epochs", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (a plain copy "
+                         "kernel of known size, to scale HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -171,6 +195,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {nbytes} bytes 3 times")
+        return
     from synth import make_problem
     from paper_2412_20509_amd import gmf as _gmf  # noqa: F401  (fails if not built)
 
@@ -193,7 +226,7 @@ def main():
     achieved = bytes_launch / mean_launch_s / 1e9
     roof = dict(bound="hbm", kernel="level_kernel<FP32,NB,KP=16,dev>", achieved=achieved,
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=None, bytes_per_launch=bytes_launch,
+                traffic=recorded_traffic(), bytes_per_launch=bytes_launch,
                 mean_launch_us=1e6 * mean_launch_s, steps_per_launch=main_arm["timed_steps"] /
                 max(main_arm["launches"], 1))
     large = None

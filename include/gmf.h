@@ -8,7 +8,7 @@
  * i.e. eta = X B' + Gamma Z' + U V' with X n x p, B m x p, Gamma n x q,
  * Z m x q, U n x d, V m x d.  The penalised negative log-likelihood of eq. 6
  * is minimised by the block-wise adaptive SGD of Algorithm 1, extended to the
- * covariate effects as in Appendix A.
+ * covariate effects as in Appendix B.
  *
  * Conventions for every call:
  *   - Array arguments are DEVICE pointers unless the name ends in _host.
@@ -70,7 +70,7 @@ typedef struct gmf_config {
   int32_t R, S;       /* number of row blocks and column blocks (Algorithm 1) */
   double phi;         /* dispersion (1 for Poisson and NB)                     */
   double nb_alpha;    /* NB shape alpha > 0: Var = mu + mu^2/alpha             */
-  double lambda[4];   /* ridge weights for B, Gamma, U, V (eq. 6, Appendix A) */
+  double lambda[4];   /* ridge weights for B, Gamma, U, V (eq. 6, Appendix B) */
   double rate0, decay, tau; /* rho_t = rate0 / (1 + rate0 decay t)^tau        */
   double alpha1, alpha2;    /* EMA weights of the new estimate (eq. 12)       */
   double damping;     /* delta added to the smoothed Hessian in the step      */
@@ -110,12 +110,12 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
              const float* A0, const float* U0, const float* V0);
 
 /* gmf_step -- run nsteps iterations of Algorithm 1 (steps 1-4) with the
- * covariate extension of Appendix A.  Iteration t (global counter, from 1):
+ * covariate extension of Appendix B.  Iteration t (global counter, from 1):
  * column block s_t = (t-1) mod S, row block r_t drawn uniformly with
  * replacement (SplitMix64 stream 2, draw t-1); on B = I_r x J_s it forms
  * eta = [X,Gamma,U]_I [B,Z,V]_J', mu = g^-1(clamp(eta)), the deviance
  * derivatives D1 = -w(y-mu)/(phi nu g'), D2 = w/(phi nu g'^2) (Section 3),
- * the minibatch gradients of eq. 15 / Appendix A for [Gamma,U]_I and [B,V]_J
+ * the minibatch gradients of eq. 15 / Appendix B for [Gamma,U]_I and [B,V]_J
  * from the pre-step parameters, the EMAs of eq. 12 (float64) and the step
  * theta -= rho_t alpha_t Gbar / (Hbar + damping) (eq. 13-14).  Unless
  * cfg.skip_block_deviance is set it also records the block deviance
@@ -134,7 +134,7 @@ int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
 
 /* gmf_deviance -- full deviance sum_ij w_ij D(y_ij, mu_ij) of the current
  * parameters (D as defined after eq. 2, Supplementary Table 1 times 2;
- * NB deviance of Appendix A), accumulated in float64 in a fixed order, and the
+ * NB deviance of Appendix B), accumulated in float64 in a fixed order, and the
  * penalised objective D/(2 phi) + sum_k lambda_k/2 ||theta_k||_F^2 (eq. 6).
  * Either host pointer may be NULL.  Synchronises. */
 int gmf_deviance(void* ctx, double* total_host, double* penalized_host);
@@ -197,7 +197,7 @@ size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new);
 
 /* gmf_project -- fit the row side [Gamma, U] of n_new new rows with the column
  * side frozen (B, Z, V of the context), by the row half of Algorithm 1 (its
- * step 4, with the covariate form of Appendix A): step t (from 1) uses every
+ * step 4, with the covariate form of Appendix B): step t (from 1) uses every
  * new row and column block J_{(t-1) mod S} of the context's partition,
  * G = (m/|J|) D1 [Z,V]_J + lambda [0_A, U] style ridge terms as in gmf_step,
  * float64 EMAs starting at zero, step rho_t alpha_t Gbar/(Hbar + damping).

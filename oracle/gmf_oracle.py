@@ -11,7 +11,7 @@ Model (Section 2, eq. 1-3): y_ij follows an exponential dispersion family with
 mean mu_ij, g(mu_ij) = eta_ij = x_i' beta_j + gamma_i' z_j + u_i' v_j, and the
 penalised negative log-likelihood of eq. 6 is minimised.
 
-Estimator (Section 3.2.2, eq. 11-15, Algorithm 1, Appendix A "stochastic
+Estimator (Section 3.2.2, eq. 11-15, Algorithm 1, Appendix B "stochastic
 gradient with non-zero covariate effects"): each step picks a block
 B = I x J, forms eta, mu and the first/second derivatives of the deviance on
 it, builds unbiased minibatch gradients for [Gamma, U]_I and [B, V]_J, smooths
@@ -22,7 +22,7 @@ Readings of points the paper leaves open (each is a parameter here):
   * D1 = dl/deta = -w (y - mu) / (phi nu(mu) g'(mu)), the derivative of the
     negative log-likelihood (the printed sign is that of the log-likelihood).
   * The ridge terms enter with a + sign (eq. 15), lambda ordered (B, Gamma, U, V).
-  * The Hessian of Gamma uses Z*Z (the minibatch form of Appendix A).
+  * The Hessian of Gamma uses Z*Z (the minibatch form of Appendix B).
   * Bias factor (eq. 11-12): bias_mode 0 uses (1-(1-a2)^t)/(1-(1-a1)^t), the
     Adam form for EMAs with weight a on the new value; bias_mode 1 uses the
     printed (1-a2^t)/(1-a1^t).  t is the global step counter starting at 1.
@@ -42,7 +42,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 # ---------------------------------------------------------------------------
-# Families (Section 2, eq. 1-2; Supplementary Table 1; Appendix A for NB)
+# Families (Section 2, eq. 1-2; Supplementary Table 1; Appendix B for NB)
 # ---------------------------------------------------------------------------
 
 FAMILIES = ("poisson", "negbin", "gaussian")
@@ -214,7 +214,7 @@ def bias_factor(cfg: Config, t: int) -> float:
 
 
 class OracleGMF:
-    """Plain FP64 replay of Algorithm 1 with covariates (Appendix A)."""
+    """Plain FP64 replay of Algorithm 1 with covariates (Appendix B)."""
 
     def __init__(self, cfg: Config, Y, X, Z, B0, A0, U0, V0, W=None):
         self.cfg = cfg
@@ -270,7 +270,7 @@ class OracleGMF:
         wB = None if self.W is None else self.W[np.ix_(I, J)]
         D1, D2 = deviance_derivatives(cfg.family, cfg.link, yB, mu, wB, cfg.phi,
                                       cfg.nb_alpha)
-        # minibatch gradients from the pre-step parameters (eq. 15, Appendix A)
+        # minibatch gradients from the pre-step parameters (eq. 15, Appendix B)
         Pc = np.hstack([self.Z[J], self.V[J]])            # [Z, V]_J
         Pr = np.hstack([self.X[I], self.U[I]])            # [X, U]_I
         row_par = np.hstack([self.A[I], self.U[I]])       # [Gamma, U]_I

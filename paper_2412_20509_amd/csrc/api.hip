@@ -410,10 +410,9 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
       if (c->timing && c->timed_launches < kMaxTimedSteps) {
         ev = &c->events[2 * c->timed_launches];
         ++c->timed_launches;
-        HIP_TRY(hipEventRecord(ev[0], c->st));
       }
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, a, grid, c->st));
-      if (ev) HIP_TRY(hipEventRecord(ev[1], c->st));
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, a, grid, c->st,
+                                ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
   }
   if (c->timing) c->timed_steps += nsteps;
@@ -449,9 +448,10 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
   if (pen)
     HIP_TRY(gmf::launch_norms(c->at<float>(P.o_Prow), c->at<float>(P.o_Pcol), P.KP, P.n, P.m, P.p,
                               P.q, P.d, sq, kSumsqBlocks, c->st));
-  HIP_TRY(gmf::launch_finalize(a.partial, P.dev_tiles, pen ? sq : nullptr, kSumsqBlocks, scal,
-                               c->st));
-  double h[5];
+  HIP_TRY(gmf::launch_finalize(a.partial, P.dev_tiles, pen ? sq : nullptr, kSumsqBlocks,
+                               c->at<int>(P.o_flag), scal, c->st));
+  // one read-back: the sums and the error flag
+  double h[6];
   HIP_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   if (total) *total = h[0];
@@ -460,7 +460,7 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
     *pen = h[0] / (2.0 * c->cfg.phi) +
            0.5 * (lam[0] * h[1] + lam[1] * h[2] + lam[2] * h[3] + lam[3] * h[4]);
   }
-  return check_flag(c);
+  return h[5] != 0.0 ? check_flag(c) : GMF_OK;
 }
 
 }  // namespace
@@ -976,7 +976,7 @@ extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Yne
   double* scal = reinterpret_cast<double*>(at(Q.o_scal));
   auto proj_dev = [&](double* out) -> int {
     HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, st));
-    HIP_TRY(gmf::launch_finalize(da.partial, Q.dev_tiles, nullptr, 0, scal, st));
+    HIP_TRY(gmf::launch_finalize(da.partial, Q.dev_tiles, nullptr, 0, nullptr, scal, st));
     HIP_TRY(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return GMF_OK;

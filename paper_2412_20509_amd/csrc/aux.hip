@@ -6,7 +6,7 @@
 //  * pack/unpack panel kernels: [X|Gamma|U] and [B|Z|V] panels in permuted
 //    order <-> caller arrays in original order.
 //  * deviance_kernel: full deviance sum_ij w D(y, mu) of the current iterate
-//    (definition after eq. 2; Supplementary Table 1; Appendix A for NB), eta on
+//    (definition after eq. 2; Supplementary Table 1; Appendix B for NB), eta on
 //    the float32 matrix cores, per-entry deviance in float32, float64
 //    accumulation in a fixed order (per-tile partials, then one ordered sum).
 #include <hip/hip_runtime.h>
@@ -233,7 +233,7 @@ hipError_t launch_norms(const float* Prow, const float* Pcol, int KP, int64_t n,
 
 // out[0] = sum of dev[0..ndev), out[1+k] = sum of norm[k*nnorm .. (k+1)*nnorm).
 __global__ void finalize_kernel(const double* dev, int ndev, const double* norm, int nnorm,
-                                double* out) {
+                                const int* flag, double* out) {
   __shared__ double red[5][256];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < ndev; i += 256) acc[0] += dev[i];
@@ -248,11 +248,12 @@ __global__ void finalize_kernel(const double* dev, int ndev, const double* norm,
     __syncthreads();
   }
   if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 5) out[5] = flag ? (double)*flag : 0.0;
 }
 
-hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm, double* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, dev, ndev, norm, nnorm, out);
+hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm,
+                           const int* flag, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, dev, ndev, norm, nnorm, flag, out);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@
 //                                                             D2 = w alpha mu/((alpha+mu) phi)
 //   Gaussian, identity:  nu = 1,                g' = 1     -> D1 = w (mu - y)/phi, D2 = w/phi
 //
-//   Unit deviances (Supplementary Table 1 times 2; NB form of Appendix A):
+//   Unit deviances (Supplementary Table 1 times 2; NB form of Appendix B):
 //   Poisson 2[y log(y/mu) - (y - mu)], NB 2[y log(y/mu) - (y+a) log((y+a)/(mu+a))],
 //   Gaussian (y - mu)^2.  For the log link log(mu) is the clamped eta itself;
 //   the NB term uses (y+a)/(mu+a) = 1 + (y-mu)/(mu+a) and a log1p that keeps

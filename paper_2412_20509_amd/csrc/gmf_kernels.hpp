@@ -78,8 +78,11 @@ struct LevelArgs {
   LevelStep steps[kMaxLevelSteps];
 };
 
+// ev_start / ev_stop (optional): HIP events stamped at the start and end of
+// this kernel's execution.
 hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_stop = nullptr);
 
 struct DevArgs {
   const float* Y; const float* W;
@@ -99,8 +102,10 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
                                hipStream_t s);
 hipError_t launch_norms(const float* Prow, const float* Pcol, int KP, int64_t n, int64_t m,
                         int p, int q, int d, double* partial, int nblocks, hipStream_t s);
-hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm, double* out,
-                           hipStream_t s);
+// out[0] = sum of dev, out[1..4] = the four norm sums (0 without norm),
+// out[5] = *flag (0 without flag).
+hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int nnorm,
+                           const int* flag, double* out, hipStream_t s);
 
 // Init / copy-out kernels.
 hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t n,

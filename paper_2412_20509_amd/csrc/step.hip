@@ -1,5 +1,5 @@
 // Block steps of the adaptive SGD for GMF (Algorithm 1, steps 2-4, with the
-// covariate extension of Appendix A) on gfx950.
+// covariate extension of Appendix B) on gfx950.
 //
 // Tiles.  Step t uses the block I_r x J_s, cut into tiles of `rpw` rows x 128
 // columns.  For every 32 x 32 piece of its tile a workgroup
@@ -30,6 +30,7 @@
 // later update of its rows or columns: the launches reproduce sequential
 // execution exactly while steps on disjoint blocks run side by side.  Kernel
 // boundaries are the only synchronisation.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "family.hpp"
@@ -570,11 +571,13 @@ static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev) {
 }
 
 hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const void* k = level_kernel_for(prec, fam, KP, want_dev);
   if (!k) return hipErrorInvalidValue;
   if (grid <= 0) return hipSuccess;
   void* args[] = {const_cast<LevelArgs*>(&a)};
+  if (ev_start || ev_stop)   // events stamped by the dispatch itself: kernel execution time only
+    return hipExtLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s, ev_start, ev_stop, 0);
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s);
 }
 
