@@ -217,6 +217,28 @@ int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t 
                 int32_t epochs, int32_t frozen, float* A_out, float* U_out,
                 double* dev_trace_host);
 
+/* gmf_project_warm -- gmf_project with its starting values built on the
+ * device, for a learned warm start of new rows (scores predicted from the
+ * counts, e.g. by the encoder below):
+ *   Gamma_0: the first column (Z's first column must be the intercept, z_j0 =
+ *     1) matches the row total given the frozen X B' part: log link
+ *     gamma_i0 = log(sum_j y_ij + 1/2) - log sum_j exp(x_i' beta_j); identity
+ *     link gamma_i0 = mean_j (y_ij - x_i' beta_j); other columns 0.
+ *   U_0: per row, U_cand's row when its row deviance sum_j D(y_ij, mu_ij)
+ *     (with Gamma_0) is below that of u_i = 0, else 0 (a fallback row).
+ *     U_cand NULL: U_0 = 0 for every row (the cold start).
+ * Then `epochs` epochs as in gmf_project.  Arguments as in gmf_project, and
+ *   U_cand (device, n_new x d, or NULL);
+ *   epoch_ms_host (may be NULL; needs dev_trace_host): epochs + 1 values, the
+ *     wall milliseconds since the call began at each deviance evaluation;
+ *   fallback_rows_host (may be NULL): the number of fallback rows.
+ * Same workspace as gmf_project.  With epochs = 0, A_out / U_out receive the
+ * starting values. */
+int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
+                     int64_t n_new, const float* Xnew, const float* U_cand, int32_t epochs,
+                     int32_t frozen, float* A_out, float* U_out, double* dev_trace_host,
+                     double* epoch_ms_host, int64_t* fallback_rows_host);
+
 /* ---------------------------------------------------------------------------
  * Warm-start encoder.  An MLP maps a row's counts to its latent scores:
  * x = log(1 + y_i) (m values) -> Linear(m, H) -> GELU -> Linear(H, H) -> GELU

@@ -437,3 +437,38 @@ def row_deviance(cfg: Config, Y, X, Z, B, A, U, V, W=None):
     if W is not None:
         dev = W * dev
     return dev.sum(axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Starting values of projected rows (learned warm start with per-row fallback)
+# ---------------------------------------------------------------------------
+
+
+def row_intercept_start(cfg: Config, Y, X, B, q: int):
+    """Gamma_0 of new rows given the frozen X B' part, with the first column of
+    Z the intercept: the row intercept that matches the row total when U = 0,
+    log link sum_j exp(x_i' beta_j + g) = sum_j y_ij + 1/2, identity link
+    sum_j (x_i' beta_j + g) = sum_j y_ij.  Other columns of Gamma are 0."""
+    Y = np.asarray(Y, np.float64)
+    n, m = Y.shape
+    eta_x = np.asarray(X, np.float64).reshape(n, -1) @ np.asarray(B, np.float64).reshape(m, -1).T
+    A0 = np.zeros((n, q))
+    if q == 0:
+        return A0
+    if cfg.link == "log":
+        mu_x = inverse_link("log", eta_x, cfg.eps, cfg.eta_max)
+        A0[:, 0] = np.log(Y.sum(axis=1) + 0.5) - np.log(mu_x.sum(axis=1))
+    else:
+        A0[:, 0] = (Y.sum(axis=1) - eta_x.sum(axis=1)) / m
+    return A0
+
+
+def warm_start_rows(cfg: Config, Y, X, Z, B, V, A0, U_cand):
+    """Per row, start from U_cand's row if its row deviance (with A0) is below
+    that of u_i = 0, else from 0.  Returns (U0, warm mask, dev_cand, dev_zero)."""
+    U_cand = np.asarray(U_cand, np.float64)
+    dev_c = row_deviance(cfg, Y, X, Z, B, A0, U_cand, V)
+    dev_0 = row_deviance(cfg, Y, X, Z, B, A0, np.zeros_like(U_cand), V)
+    warm = dev_c < dev_0
+    U0 = np.where(warm[:, None], U_cand, 0.0)
+    return U0, warm, dev_c, dev_0

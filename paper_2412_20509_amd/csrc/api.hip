@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -60,6 +61,10 @@ std::vector<int> shuffle(uint64_t seed, uint64_t stream, int64_t n) {
     std::swap(perm[i], perm[j]);
   }
   return perm;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---------------------------------------------------------------- planning --
@@ -813,7 +818,7 @@ struct ProjPlan {
   int64_t slot_u = 0;
   size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
-      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, total;
+      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, total;
 };
 
 bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
@@ -857,6 +862,7 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.o_tmpB = take(sizeof(float) * (size_t)P.m * std::max(P.p, 1));
   Q.o_tmpZ = take(sizeof(float) * (size_t)P.m * std::max(P.q, 1));
   Q.o_tmpV = take(sizeof(float) * (size_t)P.m * P.d);
+  Q.o_count = take(sizeof(unsigned long long) * 2);
   Q.total = o;
   return true;
 }
@@ -870,17 +876,27 @@ extern "C" size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new) {
   return Q.total;
 }
 
-extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
-                           int64_t n_new, const float* Xnew, const float* A0, const float* U0,
-                           int32_t epochs, int32_t frozen, float* A_out, float* U_out,
-                           double* dev_trace_host) {
-  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
-  Ctx* c = as_ctx(ctx);
+namespace {
+
+// Starting values of the projected rows: the caller's (A0, U0), or built on
+// the device (row intercept, then the candidate scores or 0 per row).
+enum ProjInit { kInitGiven = 0, kInitWarm = 1 };
+
+int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
+                 int64_t n_new, const float* Xnew, const float* A0, const float* U0,
+                 int init_mode, const float* Ucand, int32_t epochs, int32_t frozen,
+                 float* A_out, float* U_out, double* dev_trace_host, double* epoch_ms_host,
+                 int64_t* fallback_host) {
+  const auto t_start = std::chrono::steady_clock::now();
   const Plan& P = c->P;
   ProjPlan Q;
   if (!make_proj_plan(c, n_new, Q)) return fail(GMF_EINVAL, "bad n_new");
-  if (!Ynew || !U0 || !U_out || (P.p > 0 && !Xnew) || (P.q > 0 && (!A0 || !A_out)))
+  if (!Ynew || !U_out || (P.p > 0 && !Xnew) || (P.q > 0 && !A_out))
     return fail(GMF_EINVAL, "missing array");
+  if (init_mode == kInitGiven && (!U0 || (P.q > 0 && !A0)))
+    return fail(GMF_EINVAL, "missing starting values");
+  if (epoch_ms_host && !dev_trace_host)
+    return fail(GMF_EINVAL, "epoch_ms_host needs dev_trace_host");
   if (y_dtype != GMF_Y_INT32 && y_dtype != GMF_Y_FLOAT32) return fail(GMF_EINVAL, "bad y_dtype");
   if (epochs < 0) return fail(GMF_EINVAL, "epochs < 0");
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < Q.total)
@@ -926,8 +942,12 @@ extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Yne
                                 c->at<int64_t>(P.o_blkcoloff), c->at<int>(P.o_blkld), Yb, nullptr,
                                 c->at<int>(P.o_flag), st));
   float* Prow = reinterpret_cast<float*>(at(Q.o_Prow));
-  HIP_TRY(gmf::launch_pack_panel(Xnew, P.p, A0, P.q, U0, P.d, reinterpret_cast<int*>(at(Q.o_iota)), n_new,
-                                 P.KP, Prow, st));
+  if (init_mode == kInitGiven)
+    HIP_TRY(gmf::launch_pack_panel(Xnew, P.p, A0, P.q, U0, P.d, reinterpret_cast<int*>(at(Q.o_iota)),
+                                   n_new, P.KP, Prow, st));
+  else   // X only; Gamma and U are filled below
+    HIP_TRY(gmf::launch_pack_panel(Xnew, P.p, nullptr, 0, nullptr, 0, reinterpret_cast<int*>(at(Q.o_iota)),
+                                   n_new, P.KP, Prow, st));
   float* Pcol = reinterpret_cast<float*>(at(Q.o_Pcol));
   if (frozen) {
     float* tB = reinterpret_cast<float*>(at(Q.o_tmpB));
@@ -951,6 +971,29 @@ extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Yne
   } else {
     HIP_TRY(hipMemcpyAsync(Pcol, c->at<float>(P.o_Pcol), sizeof(float) * (size_t)P.m * P.KP,
                            hipMemcpyDeviceToDevice, st));
+  }
+  if (init_mode == kInitWarm) {
+    gmf::WarmArgs wa;
+    wa.Y = Ynew; wa.n = n_new; wa.m = (int)P.m; wa.p = P.p; wa.q = P.q; wa.d = P.d; wa.KP = P.KP;
+    wa.Prow = Prow; wa.Pcol = Pcol;
+    wa.colblk = c->at<int>(P.o_colblk); wa.colloc = c->at<int>(P.o_colloc); wa.co = c->at<int>(P.o_co);
+    wa.f = family_args(c->cfg);
+    wa.Ucand = Ucand; wa.dev_out = nullptr;
+    wa.fallback = reinterpret_cast<unsigned long long*>(at(Q.o_count));
+    const bool y_int = y_dtype == GMF_Y_INT32;
+    HIP_TRY(gmf::launch_row_intercept(wa, y_int, P.fam != GMF_GAUSSIAN, st));
+    if (Ucand) {
+      HIP_TRY(gmf::launch_fill_f64(reinterpret_cast<double*>(at(Q.o_count)), 1, 0.0, st));
+      HIP_TRY(gmf::launch_row_select(wa, P.fam, y_int, st));
+      if (fallback_host) {
+        unsigned long long cnt = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, at(Q.o_count), sizeof(cnt), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *fallback_host = (int64_t)cnt;
+      }
+    } else if (fallback_host) {
+      *fallback_host = 0;
+    }
   }
   double* Grow = reinterpret_cast<double*>(at(Q.o_Grow));
   double* Hrow = reinterpret_cast<double*>(at(Q.o_Hrow));
@@ -984,6 +1027,7 @@ extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Yne
   if (dev_trace_host) {
     const int rc = proj_dev(dev_trace_host);
     if (rc != GMF_OK) return rc;
+    if (epoch_ms_host) epoch_ms_host[0] = ms_since(t_start);
   }
 
   // ---- the row-side steps: tiles of step t, then its row updates
@@ -1019,12 +1063,35 @@ extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Yne
     if (dev_trace_host) {
       const int rc = proj_dev(dev_trace_host + e + 1);
       if (rc != GMF_OK) return rc;
+      if (epoch_ms_host) epoch_ms_host[e + 1] = ms_since(t_start);
     }
   }
   const int* iota = reinterpret_cast<int*>(at(Q.o_iota));
   HIP_TRY(gmf::launch_unpack_panel(Prow, P.KP, iota, n_new, P.p, P.q, A_out, st));
   HIP_TRY(gmf::launch_unpack_panel(Prow, P.KP, iota, n_new, P.p + P.q, P.d, U_out, st));
   return check_flag(c);
+}
+
+}  // namespace
+
+extern "C" int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
+                           int64_t n_new, const float* Xnew, const float* A0, const float* U0,
+                           int32_t epochs, int32_t frozen, float* A_out, float* U_out,
+                           double* dev_trace_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  return project_impl(as_ctx(ctx), ws, ws_bytes, Ynew, y_dtype, n_new, Xnew, A0, U0, kInitGiven,
+                      nullptr, epochs, frozen, A_out, U_out, dev_trace_host, nullptr, nullptr);
+}
+
+extern "C" int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void* Ynew,
+                                int32_t y_dtype, int64_t n_new, const float* Xnew,
+                                const float* U_cand, int32_t epochs, int32_t frozen, float* A_out,
+                                float* U_out, double* dev_trace_host, double* epoch_ms_host,
+                                int64_t* fallback_rows_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  return project_impl(as_ctx(ctx), ws, ws_bytes, Ynew, y_dtype, n_new, Xnew, nullptr, nullptr,
+                      kInitWarm, U_cand, epochs, frozen, A_out, U_out, dev_trace_host,
+                      epoch_ms_host, fallback_rows_host);
 }
 
 int gmf_set_trace(void* ctx, void* buffer, int64_t records) {

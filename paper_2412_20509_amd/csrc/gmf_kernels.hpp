@@ -29,6 +29,30 @@ struct FamilyArgs {
   float eta_hi;        // eta_max    (log link)
 };
 
+// Starting values of projected rows (warm.hip).  Y: the caller's new rows in
+// original order (n x m, int32 or float32); Prow: their panel (n x KP) with X
+// filled; Pcol: the frozen column panel in the fit's permuted order, column j
+// at row co[colblk[j]] + colloc[j]; Ucand: candidate scores (n x d) for
+// row_select; dev_out (optional): per row [deviance with Ucand, with 0];
+// fallback: count of rows that start from 0.
+struct WarmArgs {
+  const void* Y;
+  int64_t n;
+  int m, p, q, d, KP;
+  float* Prow;
+  const float* Pcol;
+  const int* colblk;
+  const int* colloc;
+  const int* co;
+  FamilyArgs f;
+  const float* Ucand;
+  double* dev_out;
+  unsigned long long* fallback;
+};
+
+hipError_t launch_row_intercept(const WarmArgs& a, bool y_int, bool log_link, hipStream_t s);
+hipError_t launch_row_select(const WarmArgs& a, int fam, bool y_int, hipStream_t s);
+
 // One step handed to a level launch, with its block geometry.
 struct LevelStep {
   int r, s;            // row block and column block

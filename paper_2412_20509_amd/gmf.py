@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
         "gmf_project_workspace_bytes": (C.c_size_t, [vp, i64]),
         "gmf_project": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, vp, i32, i32, vp, vp,
                                   f64p]),
+        "gmf_project_warm": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, i32, i32, vp,
+                                       vp, f64p, f64p, C.POINTER(i64)]),
         "gmf_mlp_config_default": (None, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_workspace_bytes": (C.c_size_t, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_init": (C.c_int, [C.POINTER(vp), C.POINTER(gmf_mlp_config), vp, C.c_size_t,
@@ -217,6 +219,20 @@ def gmf_project(ctx, workspace, Ynew, y_dtype, n_new, Xnew, A0, U0, epochs, froz
                                       y_dtype, int(n_new), _ptr(Xnew), _ptr(A0), _ptr(U0),
                                       int(epochs), int(frozen), _ptr(A_out), _ptr(U_out), tr))
     return None if tr is None else list(tr)
+
+
+def gmf_project_warm(ctx, workspace, Ynew, y_dtype, n_new, Xnew, U_cand, epochs, frozen, A_out,
+                     U_out, trace: bool = False):
+    """Returns (deviance trace or None, wall ms per trace point or None, fallback rows)."""
+    tr = (C.c_double * (epochs + 1))() if trace else None
+    ms = (C.c_double * (epochs + 1))() if trace else None
+    fb = C.c_int64(-1)
+    _check(load_library().gmf_project_warm(ctx, _ptr(workspace),
+                                           workspace.numel() * workspace.element_size(), _ptr(Ynew),
+                                           y_dtype, int(n_new), _ptr(Xnew), _ptr(U_cand),
+                                           int(epochs), int(frozen), _ptr(A_out), _ptr(U_out), tr,
+                                           ms, C.byref(fb)))
+    return (None if tr is None else list(tr)), (None if ms is None else list(ms)), fb.value
 
 
 def gmf_set_trace(ctx, buffer, records: int):
@@ -374,8 +390,7 @@ class GMF:
     def schedule(self, t_first=1, count=0):
         return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)
 
-    def project(self, Ynew, Xnew, A0, U0, epochs, frozen=0, trace=False):
-        """Row-side fit of new rows with the column side frozen (gmf_project)."""
+    def _project_inputs(self, Ynew):
         t = self.torch
         n_new = Ynew.shape[0]
         nbytes = gmf_project_workspace_bytes(self.ctx, n_new)
@@ -393,16 +408,43 @@ class GMF:
         else:
             Yt = t.as_tensor(np.ascontiguousarray(Ynew, dtype=np.float32), device=self.device)
             ydt = GMF_Y_FLOAT32
-        conv = lambda a, c: (None if c == 0 else
-                             (a.to(self.device).float().contiguous() if isinstance(a, t.Tensor) else
-                              t.as_tensor(np.ascontiguousarray(a, np.float32).reshape(n_new, c),
-                                          device=self.device)))
-        Xt, At, Ut = conv(Xnew, self.p), conv(A0, self.q), conv(U0, self.d)
+        return n_new, ws, wsv, Yt, ydt
+
+    def _dev_f32(self, a, n_new, c):
+        t = self.torch
+        if c == 0 or a is None:
+            return None
+        if isinstance(a, t.Tensor):
+            return a.to(self.device).float().contiguous()
+        return t.as_tensor(np.ascontiguousarray(a, np.float32).reshape(n_new, c), device=self.device)
+
+    def project(self, Ynew, Xnew, A0, U0, epochs, frozen=0, trace=False):
+        """Row-side fit of new rows with the column side frozen (gmf_project)."""
+        t = self.torch
+        n_new, ws, wsv, Yt, ydt = self._project_inputs(Ynew)
+        Xt = self._dev_f32(Xnew, n_new, self.p)
+        At = self._dev_f32(A0, n_new, self.q)
+        Ut = self._dev_f32(U0, n_new, self.d)
         Ao = t.empty((n_new, self.q), dtype=t.float32, device=self.device) if self.q else None
         Uo = t.empty((n_new, self.d), dtype=t.float32, device=self.device)
         tr = gmf_project(self.ctx, wsv, Yt, ydt, n_new, Xt, At, Ut, epochs, frozen, Ao, Uo, trace)
         self.stream.synchronize()
         return Ao, Uo, tr
+
+    def project_warm(self, Ynew, Xnew, U_cand, epochs, frozen=1, trace=False):
+        """gmf_project_warm: starting values built on the device (row intercept;
+        U_cand per row where it lowers the row deviance, else 0; U_cand None =
+        cold start).  Returns (A, U, deviance trace, wall ms trace, fallback rows)."""
+        t = self.torch
+        n_new, ws, wsv, Yt, ydt = self._project_inputs(Ynew)
+        Xt = self._dev_f32(Xnew, n_new, self.p)
+        Uc = self._dev_f32(U_cand, n_new, self.d)
+        Ao = t.empty((n_new, self.q), dtype=t.float32, device=self.device) if self.q else None
+        Uo = t.empty((n_new, self.d), dtype=t.float32, device=self.device)
+        tr, ms, fb = gmf_project_warm(self.ctx, wsv, Yt, ydt, n_new, Xt, Uc, epochs, frozen, Ao,
+                                      Uo, trace)
+        self.stream.synchronize()
+        return Ao, Uo, tr, ms, fb
 
     def set_trace(self, buffer, records):
         gmf_set_trace(self.ctx, buffer, records)

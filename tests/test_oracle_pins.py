@@ -401,3 +401,56 @@ def test_projection_rows_are_independent_and_reach_row_optimum():
 
     res = minimize(f, np.zeros(1 + pr.d), method="BFGS", options=dict(gtol=1e-10))
     np.testing.assert_allclose(np.concatenate([A[i], U[i]]), res.x, atol=1e-6)
+
+
+# ------------------------------------------------- projection start values --
+
+def test_row_intercept_start_matches_row_totals():
+    """With U = 0 the log-link intercept makes each row's fitted total equal
+    its count total + 1/2; the identity-link intercept makes the mean residual
+    zero (both by construction of the definition, checked from the mean)."""
+    rng = np.random.default_rng(11)
+    n, m, p = 9, 13, 2
+    X = np.column_stack([np.ones(n), rng.normal(size=n)])
+    B = rng.normal(0, 0.4, size=(m, p))
+    Y = rng.poisson(2.0, size=(n, m))
+    Y[3] = 0                                  # an all-zero row
+    cfg = G.Config(family="poisson")
+    A0 = G.row_intercept_start(cfg, Y, X, B, q=2)
+    mu = np.exp(X @ B.T + A0[:, :1])
+    np.testing.assert_allclose(mu.sum(axis=1), Y.sum(axis=1) + 0.5, rtol=1e-12)
+    assert np.all(A0[:, 1] == 0)
+    cfg_g = G.Config(family="gaussian", link="identity")
+    Yg = rng.normal(size=(n, m))
+    Ag = G.row_intercept_start(cfg_g, Yg, X, B, q=1)
+    np.testing.assert_allclose((Yg - X @ B.T - Ag).mean(axis=1), 0.0, atol=1e-12)
+
+
+def test_warm_start_rows_picks_lower_row_deviance():
+    """Brute force: per row, sum the unit deviances entry by entry for both
+    candidates and compare with the selection."""
+    rng = np.random.default_rng(12)
+    n, m, p, q, d = 8, 10, 1, 1, 2
+    X = np.ones((n, p))
+    Z = np.ones((m, q))
+    B = rng.normal(0, 0.3, size=(m, p))
+    V = rng.normal(0, 0.5, size=(m, d))
+    U_true = rng.normal(0, 0.8, size=(n, d))
+    Y = rng.poisson(np.exp(X @ B.T + U_true @ V.T))
+    cand = U_true.copy()
+    cand[::2] = -3.0 * U_true[::2]             # poor candidates on even rows
+    cfg = G.Config(family="poisson")
+    A0 = G.row_intercept_start(cfg, Y, X, B, q)
+    U0, warm, dc, d0 = G.warm_start_rows(cfg, Y, X, Z, B, V, A0, cand)
+    for i in range(n):
+        def dev(u):
+            tot = 0.0
+            for j in range(m):
+                eta = X[i] @ B[j] + A0[i] @ Z[j] + u @ V[j]
+                tot += float(G.unit_deviance("poisson", Y[i, j], np.exp(eta)))
+            return tot
+        a, b = dev(cand[i]), dev(np.zeros(d))
+        assert abs(a - dc[i]) <= 1e-10 * max(1.0, a) and abs(b - d0[i]) <= 1e-10 * max(1.0, b)
+        assert warm[i] == (a < b)
+        np.testing.assert_array_equal(U0[i], cand[i] if a < b else np.zeros(d))
+    assert warm.any() and (~warm).any()       # both outcomes occur
