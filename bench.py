@@ -23,6 +23,10 @@ Printed JSON line:
                     (rocprofv3 counters, summary under profiles/)
   cpu_baseline      the FP64 oracle on the host, bounded sample
   arms              the same measurements for the BF16 arm
+  large             the 100000 x 5000 rank-20 workload (steps only)
+  warm_start        learned warm start of 1,000,000 new rows: epochs and
+                    seconds to 1e-4 of the converged projection deviance for a
+                    cold start and for the encoder's bfloat16 predictions
 """
 import argparse
 import json
@@ -156,6 +160,82 @@ def run_throughput(pr, precision, epochs, torch):
                 deviance_eval_s=t_dev, deviance=dev)
 
 
+def first_hit(trace, ms, target, rel=1e-4):
+    """(epoch, wall ms) of the first deviance within rel of target, else (None, None)."""
+    for e, (dv, t) in enumerate(zip(trace, ms)):
+        if abs(dv - target) <= rel * target:
+            return e, t
+    return None, None
+
+
+def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
+    """Learned warm start of new rows: fit the workload, train the encoder on
+    (log1p counts, projected scores) of its rows (90/10 split), then project
+    n_new fresh rows from the same generator twice, cold (U0 = 0) and warm (U0 =
+    encoder output in bfloat16, per-row fallback to 0), both with the row
+    intercept start, and time each to 1e-4 of the converged projection deviance."""
+    import numpy as np
+    from paper_2412_20509_amd.gmf import Encoder
+    from synth import gen_nb_rows, mlp_init
+    per_epoch = pr.R * pr.S
+    g = make_gmf(pr, "fp32")
+    g.step(200 * per_epoch)
+    torch.cuda.synchronize()
+    n_tr = int(0.9 * pr.n)
+    Ytr = torch.as_tensor(pr.Y, device="cuda:0")
+    # encoder targets: the optimum of each fitted row's own projection problem on
+    # the frozen column side (the scores a projection converges to), so that the
+    # encoder learns the map the warm start is meant to shortcut
+    _, Uft, _, _, _ = g.project_warm(Ytr, pr.X, None, 3 * max_epochs, frozen=1)
+    enc = Encoder(pr.m, pr.d, mlp_init(pr.m, 256, pr.d), hidden=256, batch=256, lr=1e-3)
+    t0 = time.perf_counter()
+    losses = enc.train(Ytr[:n_tr], Uft[:n_tr], enc_epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val = enc.forward(Ytr[n_tr:], bf16=True)
+    val_mse = float(((val - Uft[n_tr:]) ** 2).mean())
+    val_var = float(((Uft[n_tr:] - Uft[n_tr:].mean(0)) ** 2).mean())
+    del Ytr, Uft
+    log(f"warm start: generating {n_new} new rows")
+    Ynew, Xnew, _, _ = gen_nb_rows(pr, n_new, seed=5005)
+    Yd = torch.as_tensor(Ynew, device="cuda:0")
+    Xd = torch.as_tensor(np.asarray(Xnew, np.float32), device="cuda:0")
+    del Ynew
+    # converged reference: a cold run to a relative change below 1e-9 (or the cap)
+    log("warm start: converged reference (cold)")
+    _, _, ref, _, _ = g.project_warm(Yd, Xd, None, 3 * max_epochs, frozen=1, trace=True)
+    ref_change = abs(ref[-1] - ref[-2]) / ref[-1]
+    dstar = ref[-1]
+    log("warm start: cold arm")
+    _, _, trc, msc, _ = g.project_warm(Yd, Xd, None, max_epochs, frozen=1, trace=True)
+    log("warm start: warm arm")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cand = enc.forward(Yd, bf16=True)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    _, _, trw, msw, fb = g.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
+    ec, tc = first_hit(trc, msc, dstar)
+    ew, tw = first_hit(trw, msw, dstar)
+    enc.close()
+    g.close()
+    return dict(
+        workload=(f"{n_new} new NB rows x {pr.m} (same column side, fresh rows), projected "
+                  f"on the frozen Algorithm 2 column side of the {pr.n}x{pr.m} fit"),
+        encoder=dict(train_rows=n_tr, val_rows=pr.n - n_tr, epochs=enc_epochs,
+                     train_loss_first=losses[0], train_loss_last=losses[-1],
+                     val_mse_bf16=val_mse, val_target_var=val_var, train_s=t_train,
+                     infer_s=t_inf, infer_rows_per_s=n_new / t_inf),
+        reference=dict(epochs=3 * max_epochs, deviance=dstar, last_rel_change=ref_change),
+        cold=dict(epochs_to_1e4=ec, s_to_1e4=None if tc is None else tc / 1e3,
+                  deviance_start=trc[0], ms_per_epoch=(msc[-1] - msc[0]) / max_epochs),
+        warm=dict(epochs_to_1e4=ew,
+                  s_to_1e4=None if tw is None else tw / 1e3 + t_inf,
+                  deviance_start=trw[0], fallback_rows=fb,
+                  ms_per_epoch=(msw[-1] - msw[0]) / max_epochs),
+    )
+
+
 def cpu_baseline(pr, epochs=3):
     from threadpoolctl import threadpool_info
     from oracle import gmf_oracle as G
@@ -185,6 +265,11 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 100000x5000 rank-20 throughput section")
     ap.add_argument("--large-epochs", type=int, default=5)
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start section")
+    ap.add_argument("--warm-rows", type=int, default=1_000_000)
+    ap.add_argument("--warm-epochs", type=int, default=60,
+                    help="projection epochs per arm (the reference runs 3x as many)")
+    ap.add_argument("--encoder-epochs", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known size, to scale HBM byte counters) and exit")
@@ -242,6 +327,12 @@ def main():
         large["workload"] = ("NB GMF 100000x5000, d=20, p=3, q=1, alpha=5, blocks 10000x1000 "
                              "(R=10, S=5); steps only, one full deviance timed separately")
         del pr3
+    warm = None
+    if not args.no_warm:
+        warm = run_warm_start(pr, args.warm_rows, args.warm_epochs, args.encoder_epochs, torch)
+        log(f"warm start: cold {warm['cold']['epochs_to_1e4']} epochs, "
+            f"warm {warm['warm']['epochs_to_1e4']} epochs, "
+            f"{warm['warm']['fallback_rows']} fallback rows")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
@@ -259,6 +350,7 @@ def main():
                     zero_fraction=float((pr.Y == 0).mean())),
         s_to_1e4=main_arm["s_to_1e4"], epochs_to_1e4=main_arm["epochs_to_1e4"],
         oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu, large=large,
+        warm_start=warm,
         arms={k: {kk: vv for kk, vv in v.items()} for k, v in arms.items()},
     )
     print(json.dumps(out))

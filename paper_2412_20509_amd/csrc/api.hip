@@ -818,7 +818,7 @@ struct ProjPlan {
   int64_t slot_u = 0;
   size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
-      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, total;
+      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, o_pcolorig, total;
 };
 
 bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
@@ -863,6 +863,7 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.o_tmpZ = take(sizeof(float) * (size_t)P.m * std::max(P.q, 1));
   Q.o_tmpV = take(sizeof(float) * (size_t)P.m * P.d);
   Q.o_count = take(sizeof(unsigned long long) * 2);
+  Q.o_pcolorig = take(sizeof(float) * (size_t)P.m * P.KP);
   Q.total = o;
   return true;
 }
@@ -975,8 +976,10 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
   if (init_mode == kInitWarm) {
     gmf::WarmArgs wa;
     wa.Y = Ynew; wa.n = n_new; wa.m = (int)P.m; wa.p = P.p; wa.q = P.q; wa.d = P.d; wa.KP = P.KP;
-    wa.Prow = Prow; wa.Pcol = Pcol;
-    wa.colblk = c->at<int>(P.o_colblk); wa.colloc = c->at<int>(P.o_colloc); wa.co = c->at<int>(P.o_co);
+    // the frozen column panel in the caller's column order
+    float* Pco = reinterpret_cast<float*>(at(Q.o_pcolorig));
+    HIP_TRY(gmf::launch_unpack_panel(Pcol, P.KP, c->at<int>(P.o_colperm), P.m, 0, P.KP, Pco, st));
+    wa.Prow = Prow; wa.Pcol_orig = Pco;
     wa.f = family_args(c->cfg);
     wa.Ucand = Ucand; wa.dev_out = nullptr;
     wa.fallback = reinterpret_cast<unsigned long long*>(at(Q.o_count));

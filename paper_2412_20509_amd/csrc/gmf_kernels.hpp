@@ -31,19 +31,16 @@ struct FamilyArgs {
 
 // Starting values of projected rows (warm.hip).  Y: the caller's new rows in
 // original order (n x m, int32 or float32); Prow: their panel (n x KP) with X
-// filled; Pcol: the frozen column panel in the fit's permuted order, column j
-// at row co[colblk[j]] + colloc[j]; Ucand: candidate scores (n x d) for
+// filled (and Gamma for row_select); Pcol_orig: the frozen column panel in the
+// caller's original column order (m x KP); Ucand: candidate scores (n x d) for
 // row_select; dev_out (optional): per row [deviance with Ucand, with 0];
-// fallback: count of rows that start from 0.
+// fallback: count of rows that start from 0.  Requires p + q + d <= 64.
 struct WarmArgs {
   const void* Y;
   int64_t n;
   int m, p, q, d, KP;
   float* Prow;
-  const float* Pcol;
-  const int* colblk;
-  const int* colloc;
-  const int* co;
+  const float* Pcol_orig;
   FamilyArgs f;
   const float* Ucand;
   double* dev_out;

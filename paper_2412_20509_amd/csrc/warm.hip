@@ -12,11 +12,12 @@
 //    candidate scores u_i (e.g. an encoder's output) and of u_i = 0, both with
 //    the row's covariate and Gamma terms; the row starts from the candidate when
 //    its deviance is lower, else from 0 (a fallback, counted).
-// One wavefront per row; each lane walks the columns j = lane, lane + 64, ...
-// in the caller's original column order (the frozen column panel is stored in
-// the fit's permuted order and is addressed through the column tables); the
-// per-lane sums are combined by a fixed butterfly, so results are
-// reproducible.
+// A workgroup takes 16 rows; thread t walks the columns j = t, t + 256, ... in
+// the caller's original column order (a copy of the frozen column panel in that
+// order), so the count loads of consecutive threads are consecutive and every
+// column's panel row is read once per 16 rows.  Per-row sums are combined in a
+// fixed order (butterfly within a wavefront, then the four wavefronts), so
+// results are reproducible.
 #include <hip/hip_runtime.h>
 
 #include "family.hpp"
@@ -26,12 +27,9 @@ namespace gmf {
 
 namespace {
 
-constexpr int kRowsPerWG = 4;   // one wavefront per row, 256 threads
-
-__device__ __forceinline__ double wave_sum(double x) {
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
+constexpr int kTileRows = 16;   // rows per workgroup
+constexpr int kThreads = 256;
+constexpr int kMaxK = 64;       // p + q + d <= 64
 
 template <bool Y_INT>
 __device__ __forceinline__ float y_at(const void* Y, int64_t idx) {
@@ -39,74 +37,145 @@ __device__ __forceinline__ float y_at(const void* Y, int64_t idx) {
   else return static_cast<const float*>(Y)[idx];
 }
 
-template <bool Y_INT, bool LOG_LINK>
-__global__ __launch_bounds__(256) void row_intercept_kernel(WarmArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * kRowsPerWG + (threadIdx.x >> 6);
-  if (i >= a.n) return;
-  float* prow = a.Prow + i * a.KP;
-  double sy = 0.0, s2 = 0.0;
-  for (int j = lane; j < a.m; j += 64) {
-    const int jp = a.co[a.colblk[j]] + a.colloc[j];
-    const float* pc = a.Pcol + (int64_t)jp * a.KP;
-    float ex = 0.f;
-    for (int k = 0; k < a.p; ++k) ex += prow[k] * pc[k];
-    const float y = y_at<Y_INT>(a.Y, i * a.m + j);
-    sy += (double)y;
-    if constexpr (LOG_LINK) s2 += (double)fast_exp(fminf(fmaxf(ex, a.f.eta_lo), a.f.eta_hi));
-    else s2 += (double)ex;
+// Sums of kTileRows per-thread values over the workgroup, in a fixed order:
+// a butterfly inside each wavefront, then the four wavefront totals in order;
+// the totals land in tot[] (LDS).
+__device__ __forceinline__ void tile_sums(const float (&v)[kTileRows], double (*red)[kTileRows],
+                                          double* tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = 0; r < kTileRows; ++r) {
+    double x = (double)v[r];
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave][r] = x;
   }
-  sy = wave_sum(sy);
-  s2 = wave_sum(s2);
-  if (lane < a.q) {
-    float g = 0.f;
-    if (lane == 0) {
-      if constexpr (LOG_LINK) g = (float)(log(sy + 0.5) - log(s2));
-      else g = (float)((sy - s2) / (double)a.m);
+  __syncthreads();
+  if (threadIdx.x < kTileRows) {
+    const int r = threadIdx.x;
+    tot[r] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+  }
+  __syncthreads();
+}
+
+// Stage the tile's panel rows (Prow, first `cols` values) into LDS.
+__device__ __forceinline__ void stage_rows(const WarmArgs& a, int64_t r0, int nr, int cols,
+                                           float (*sP)[kMaxK + 1]) {
+  for (int idx = threadIdx.x; idx < kTileRows * cols; idx += kThreads) {
+    const int r = idx / cols, k = idx % cols;
+    sP[r][k] = (r < nr) ? a.Prow[(r0 + r) * a.KP + k] : 0.f;
+  }
+}
+
+template <bool Y_INT, bool LOG_LINK>
+__global__ __launch_bounds__(kThreads) void row_intercept_kernel(WarmArgs a) {
+  __shared__ float sP[kTileRows][kMaxK + 1];
+  __shared__ double red[4][kTileRows];
+  const int64_t r0 = (int64_t)blockIdx.x * kTileRows;
+  const int nr = (int)min<int64_t>(kTileRows, a.n - r0);
+  stage_rows(a, r0, nr, a.p, sP);
+  __syncthreads();
+  float sy[kTileRows], s2[kTileRows];
+  for (int r = 0; r < kTileRows; ++r) sy[r] = s2[r] = 0.f;
+  for (int j = threadIdx.x; j < a.m; j += kThreads) {
+    const float* pc = a.Pcol_orig + (int64_t)j * a.KP;
+    float ex[kTileRows];
+    for (int r = 0; r < kTileRows; ++r) ex[r] = 0.f;
+    for (int k = 0; k < a.p; ++k) {
+      const float b = pc[k];
+      for (int r = 0; r < kTileRows; ++r) ex[r] = fmaf(sP[r][k], b, ex[r]);
     }
-    prow[a.p + lane] = g;
+    for (int r = 0; r < kTileRows; ++r) {
+      if (r < nr) {
+        sy[r] += y_at<Y_INT>(a.Y, (r0 + r) * a.m + j);
+        if constexpr (LOG_LINK) s2[r] += fast_exp(fminf(fmaxf(ex[r], a.f.eta_lo), a.f.eta_hi));
+        else s2[r] += ex[r];
+      }
+    }
+  }
+  __shared__ double ty[kTileRows], t2[kTileRows];
+  tile_sums(sy, red, ty);
+  tile_sums(s2, red, t2);
+  // index r * q + c: column c of Gamma for row r
+  for (int t = threadIdx.x; t < kTileRows * a.q; t += kThreads) {
+    const int r = t / a.q, c = t % a.q;
+    if (r < nr) {
+      float g = 0.f;
+      if (c == 0) {
+        const double yr = ty[r], xr = t2[r];
+        if constexpr (LOG_LINK) g = (float)(log(yr + 0.5) - log(xr));
+        else g = (float)((yr - xr) / (double)a.m);
+      }
+      a.Prow[(r0 + r) * a.KP + a.p + c] = g;
+    }
   }
 }
 
 template <bool Y_INT, int FAM>
-__global__ __launch_bounds__(256) void row_select_kernel(WarmArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * kRowsPerWG + (threadIdx.x >> 6);
-  if (i >= a.n) return;
-  const FamilyConst fc = family_const(a.f);
-  float* prow = a.Prow + i * a.KP;
-  const float* uw = a.Ucand + i * a.d;
+__global__ __launch_bounds__(kThreads) void row_select_kernel(WarmArgs a) {
+  __shared__ float sP[kTileRows][kMaxK + 1];
+  __shared__ double red[4][kTileRows];
+  const int64_t r0 = (int64_t)blockIdx.x * kTileRows;
+  const int nr = (int)min<int64_t>(kTileRows, a.n - r0);
   const int pq = a.p + a.q;
-  float dw = 0.f, dc = 0.f;
-  for (int j = lane; j < a.m; j += 64) {
-    const int jp = a.co[a.colblk[j]] + a.colloc[j];
-    const float* pc = a.Pcol + (int64_t)jp * a.KP;
-    float base = 0.f;
-    for (int k = 0; k < pq; ++k) base += prow[k] * pc[k];
-    float lat = 0.f;
-    for (int k = 0; k < a.d; ++k) lat += uw[k] * pc[pq + k];
-    const float y = y_at<Y_INT>(a.Y, i * a.m + j);
-    float x1, x2, dv;
-    family_entry<FAM, true>(base + lat, y, 1.f, fc, x1, x2, dv);
-    dw += dv;
-    family_entry<FAM, true>(base, y, 1.f, fc, x1, x2, dv);
-    dc += dv;
+  const int kk = pq + a.d;
+  // panel rows with the candidate scores in the U columns
+  for (int idx = threadIdx.x; idx < kTileRows * kk; idx += kThreads) {
+    const int r = idx / kk, k = idx % kk;
+    float v = 0.f;
+    if (r < nr) v = (k < pq) ? a.Prow[(r0 + r) * a.KP + k] : a.Ucand[(r0 + r) * a.d + (k - pq)];
+    sP[r][k] = v;
   }
-  const double sw = wave_sum((double)dw);
-  const double sc = wave_sum((double)dc);
-  const bool warm = sw < sc;
-  if (a.dev_out && lane == 0) {
-    a.dev_out[2 * i] = sw;
-    a.dev_out[2 * i + 1] = sc;
+  __syncthreads();
+  const FamilyConst fc = family_const(a.f);
+  float dw[kTileRows], dz[kTileRows];
+  for (int r = 0; r < kTileRows; ++r) dw[r] = dz[r] = 0.f;
+  for (int j = threadIdx.x; j < a.m; j += kThreads) {
+    const float* pc = a.Pcol_orig + (int64_t)j * a.KP;
+    float base[kTileRows], lat[kTileRows];
+    for (int r = 0; r < kTileRows; ++r) base[r] = lat[r] = 0.f;
+    for (int k = 0; k < pq; ++k) {
+      const float b = pc[k];
+      for (int r = 0; r < kTileRows; ++r) base[r] = fmaf(sP[r][k], b, base[r]);
+    }
+    for (int k = pq; k < kk; ++k) {
+      const float b = pc[k];
+      for (int r = 0; r < kTileRows; ++r) lat[r] = fmaf(sP[r][k], b, lat[r]);
+    }
+    for (int r = 0; r < kTileRows; ++r) {
+      if (r < nr) {
+        const float y = y_at<Y_INT>(a.Y, (r0 + r) * a.m + j);
+        float x1, x2, dv;
+        family_entry<FAM, true>(base[r] + lat[r], y, 1.f, fc, x1, x2, dv);
+        dw[r] += dv;
+        family_entry<FAM, true>(base[r], y, 1.f, fc, x1, x2, dv);
+        dz[r] += dv;
+      }
+    }
   }
-  if (lane < a.d) prow[pq + lane] = warm ? uw[lane] : 0.f;
-  if (!warm && lane == 0) atomicAdd(a.fallback, 1ULL);
+  __shared__ double tw[kTileRows], tz[kTileRows];
+  tile_sums(dw, red, tw);
+  tile_sums(dz, red, tz);
+  // index r * d + c: score c of row r
+  for (int t = threadIdx.x; t < kTileRows * a.d; t += kThreads) {
+    const int r = t / a.d, c = t % a.d;
+    if (r < nr) {
+      const double wr = tw[r], zr = tz[r];
+      const bool warm = wr < zr;
+      a.Prow[(r0 + r) * a.KP + pq + c] = warm ? sP[r][pq + c] : 0.f;
+      if (c == 0) {
+        if (a.dev_out) {
+          a.dev_out[2 * (r0 + r)] = wr;
+          a.dev_out[2 * (r0 + r) + 1] = zr;
+        }
+        if (!warm) atomicAdd(a.fallback, 1ULL);
+      }
+    }
+  }
 }
 
 template <int FAM>
 hipError_t select_fam(const WarmArgs& a, bool y_int, dim3 grid, hipStream_t s) {
-  if (y_int) hipLaunchKernelGGL((row_select_kernel<true, FAM>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((row_select_kernel<false, FAM>), grid, dim3(256), 0, s, a);
+  if (y_int) hipLaunchKernelGGL((row_select_kernel<true, FAM>), grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((row_select_kernel<false, FAM>), grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -114,20 +183,22 @@ hipError_t select_fam(const WarmArgs& a, bool y_int, dim3 grid, hipStream_t s) {
 
 hipError_t launch_row_intercept(const WarmArgs& a, bool y_int, bool log_link, hipStream_t s) {
   if (a.n <= 0 || a.q <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((a.n + kRowsPerWG - 1) / kRowsPerWG));
+  if (a.p + a.q + a.d > kMaxK) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.n + kTileRows - 1) / kTileRows));
   if (y_int) {
-    if (log_link) hipLaunchKernelGGL((row_intercept_kernel<true, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((row_intercept_kernel<true, false>), grid, dim3(256), 0, s, a);
+    if (log_link) hipLaunchKernelGGL((row_intercept_kernel<true, true>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((row_intercept_kernel<true, false>), grid, dim3(kThreads), 0, s, a);
   } else {
-    if (log_link) hipLaunchKernelGGL((row_intercept_kernel<false, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((row_intercept_kernel<false, false>), grid, dim3(256), 0, s, a);
+    if (log_link) hipLaunchKernelGGL((row_intercept_kernel<false, true>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((row_intercept_kernel<false, false>), grid, dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_row_select(const WarmArgs& a, int fam, bool y_int, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((a.n + kRowsPerWG - 1) / kRowsPerWG));
+  if (a.p + a.q + a.d > kMaxK) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.n + kTileRows - 1) / kTileRows));
   switch (fam) {
     case kPoisson: return select_fam<kPoisson>(a, y_int, grid, s);
     case kNegBin: return select_fam<kNegBin>(a, y_int, grid, s);
