@@ -79,12 +79,16 @@ typedef struct gmf_config {
   uint64_t seed;      /* schedule seed: partitions and row-block draws        */
   int32_t tile_rows;  /* rows per step tile (multiple of 32), 0 = automatic   */
   int32_t skip_block_deviance; /* 1: steps do not form the block deviance   */
+  int32_t panel_stride; /* floats per panel row: 0 = automatic (p+q+d rounded
+                           up to 16, or 32 for BF16); else 16, 32, 48 or 64
+                           (BF16: 32 or 64) and >= p+q+d.  Fits run together
+                           by gmf_batch_* must share it.                       */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
- * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0. */
+ * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -238,6 +242,39 @@ int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int
                      int64_t n_new, const float* Xnew, const float* U_cand, int32_t epochs,
                      int32_t frozen, float* A_out, float* U_out, double* dev_trace_host,
                      double* epoch_ms_host, int64_t* fallback_rows_host);
+
+/* ---------------------------------------------------------------------------
+ * Batched fits.  Many independent contexts (each from gmf_init, any shapes,
+ * Poisson / NB / Gaussian mixed) advance together: one epoch of the batch is
+ * a fixed sequence of launches -- for k = 0, 1, ..., the tiles of step k of
+ * every fit, then the updates of step k -- so each fit's steps run in order
+ * exactly as gmf_step runs them (same results, the block deviance of each
+ * step is not formed), while the fits share every launch.  The random row
+ * blocks and step sizes of the coming epochs are uploaded as a device table,
+ * so the launch sequence of an epoch is the same every epoch; with use_graph
+ * it is recorded once as a HIP graph and replayed.  All contexts must share
+ * the precision and the panel stride (gmf_config.panel_stride) and live on one
+ * device; they must stay alive, and must not be used on their own while a
+ * gmf_batch_run call is in progress.  The batch runs on a stream of its own,
+ * ordered after the work already queued on the contexts' streams, and their
+ * streams are ordered after it.
+ * ------------------------------------------------------------------------- */
+/* Device bytes of the batch workspace (0 on invalid arguments). */
+size_t gmf_batch_workspace_bytes(void* const* ctxs, int32_t nfits, int32_t table_epochs);
+/* gmf_batch_init -- set up a batch over ctxs[0..nfits) with a step table of
+ * table_epochs epochs (refilled from the host when used up: one stream
+ * synchronisation per refill).  use_graph != 0 records the epoch as a HIP
+ * graph.  Errors: GMF_EINVAL (mixed precision / panel stride, repeated or NULL
+ * contexts), GMF_EWORKSPACE, GMF_EDEVICE. */
+int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits, void* ws,
+                   size_t ws_bytes, int32_t table_epochs, int32_t use_graph);
+/* gmf_batch_run -- run `epochs` epochs of every fit (fit f: R_f * S_f steps
+ * each).  Every eval_every epochs, when dev_trace_host is not NULL, the full
+ * deviance of every fit is evaluated (float64, as gmf_deviance) into
+ * dev_trace_host[f * (epochs / eval_every) + i]; this synchronises.  Errors as
+ * gmf_step, GMF_ENUMERIC when a fit produced a non-finite parameter. */
+int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every, double* dev_trace_host);
+void gmf_batch_destroy(void* batch);
 
 /* ---------------------------------------------------------------------------
  * Warm-start encoder.  An MLP maps a row's counts to its latent scores:

@@ -126,6 +126,13 @@ std::string check_config(const gmf_config* c) {
     return "skip_block_deviance must be 0 or 1";
   if (c->tile_rows < 0 || c->tile_rows % 32 != 0 || c->tile_rows > 4096)
     return "tile_rows must be 0 or a multiple of 32 up to 4096";
+  if (c->panel_stride != 0) {
+    const int ps = c->panel_stride;
+    const bool ok = (c->precision == GMF_PREC_BF16) ? (ps == 32 || ps == 64)
+                                                    : (ps == 16 || ps == 32 || ps == 48 || ps == 64);
+    if (!ok) return "panel_stride must be 0, 16, 32, 48 or 64 (BF16: 32 or 64)";
+    if (ps < c->p + c->q + c->d) return "panel_stride must be >= p + q + d";
+  }
   return "";
 }
 
@@ -134,6 +141,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.p = c->p; P.q = c->q; P.d = c->d; P.k = c->p + c->q + c->d;
   P.prec = c->precision; P.fam = c->family; P.with_w = with_w ? 1 : 0;
   P.KP = (P.prec == GMF_PREC_BF16) ? round_up(P.k, 32) : round_up(P.k, 16);
+  if (c->panel_stride > 0) P.KP = c->panel_stride;
   P.KU = P.q + P.d; P.KV = P.p + P.d;
   P.ro.resize(P.R + 1); P.co.resize(P.S + 1);
   for (int r = 0; r <= P.R; ++r) P.ro[r] = (int)((int64_t)r * P.n / P.R);
@@ -334,6 +342,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   a.col_chunk = P.col_chunk;
   a.upd_per_step = P.upd_per_step;
   a.f = family_args(cf);
+  a.fam = P.fam;
   a.p = P.p; a.q = P.q; a.d = P.d; a.KU = P.KU; a.KV = P.KV; a.KP = P.KP;
   a.lam_B = cf.lambda[0]; a.lam_A = cf.lambda[1]; a.lam_U = cf.lambda[2]; a.lam_V = cf.lambda[3];
   a.a1 = cf.alpha1; a.a2 = cf.alpha2; a.damping = cf.damping;
@@ -349,6 +358,28 @@ gmf::LevelArgs level_args(const Ctx* c) {
   return a;
 }
 
+// Block geometry and step size of global step t.
+gmf::LevelStep make_step(const Ctx* c, int64_t t) {
+  const Plan& P = c->P;
+  gmf::LevelStep st;
+  st.r = row_block_of_step(c, t);
+  st.s = (int)((t - 1) % P.S);
+  st.slot = (int)((t - 1) % P.nslot);
+  st.n_b = P.nrows[st.r];
+  st.m_b = P.mcols[st.s];
+  st.n_rr = P.nrr[st.r];
+  st.n_ct = P.nct[st.s];
+  st.rpw = P.rpw[st.r];
+  st.ldy = P.ld[st.s];
+  st.ro = P.ro[st.r];
+  st.co = P.co[st.s];
+  st.pad = 0;
+  st.yoff = (int64_t)P.ro[st.r] * P.LDtot + (int64_t)st.n_b * P.coP[st.s];
+  st.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
+  st.t = t;
+  return st;
+}
+
 // Run steps c->t+1 .. c->t+nsteps.  Step t is placed at level
 // T(t) = max over its predecessors (previous step on the same row block, on the
 // same column block, and on the same partial slot) of T + 2, or 0.  Launch k
@@ -356,7 +387,6 @@ gmf::LevelArgs level_args(const Ctx* c) {
 // split over several launches (tiles of level k never need updates of level k-1).
 int enqueue_steps(Ctx* c, int64_t nsteps) {
   const Plan& P = c->P;
-  const gmf_config& cf = c->cfg;
   const bool want_dev = c->want_block_dev != 0;
   if (nsteps <= 0) return GMF_OK;
   std::vector<gmf::LevelStep> steps(nsteps);
@@ -366,21 +396,7 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int64_t t = c->t + 1 + k;
     gmf::LevelStep& st = steps[k];
-    st.r = row_block_of_step(c, t);
-    st.s = (int)((t - 1) % P.S);
-    st.slot = (int)((t - 1) % P.nslot);
-    st.n_b = P.nrows[st.r];
-    st.m_b = P.mcols[st.s];
-    st.n_rr = P.nrr[st.r];
-    st.n_ct = P.nct[st.s];
-    st.rpw = P.rpw[st.r];
-    st.ldy = P.ld[st.s];
-    st.ro = P.ro[st.r];
-    st.co = P.co[st.s];
-    st.pad = 0;
-    st.yoff = (int64_t)P.ro[st.r] * P.LDtot + (int64_t)st.n_b * P.coP[st.s];
-    st.stepsize = learning_rate(cf, t) * bias_factor(cf, t);
-    st.t = t;
+    st = make_step(c, t);
     int lv = 0;
     if (lr[st.r] >= 0) lv = std::max(lv, lr[st.r] + 2);
     if (ls[st.s] >= 0) lv = std::max(lv, ls[st.s] + 2);
@@ -425,7 +441,7 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
   return GMF_OK;
 }
 
-int compute_deviance(Ctx* c, double* total, double* pen) {
+gmf::DevArgs dev_args(Ctx* c) {
   const Plan& P = c->P;
   gmf::DevArgs a;
   a.Y = c->at<float>(P.o_Yb);
@@ -445,6 +461,12 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
   a.f = family_args(c->cfg);
   a.partial = c->at<double>(P.o_devpartial);
   a.n_tiles = P.dev_tiles;
+  return a;
+}
+
+int compute_deviance(Ctx* c, double* total, double* pen) {
+  const Plan& P = c->P;
+  gmf::DevArgs a = dev_args(c);
   // The deviance monitor uses float32 products regardless of the step
   // precision, so its panel stride must be a float32 case (16, 32, 48, 64).
   HIP_TRY(gmf::launch_deviance(P.fam, P.KP, a, c->st));
@@ -1144,3 +1166,271 @@ void gmf_destroy(void* ctx) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batched fits --
+// Many independent fits advanced together.  One epoch of the batch is a fixed
+// sequence of launches: for k = 0 .. L-1, the tiles of step k of every fit
+// that has one (one segment per fit), then the updates of step k, then one
+// workgroup that advances the epoch cursor.  Each fit's steps follow one
+// another exactly as in gmf_step (its tiles of step k run after the updates
+// of step k-1, in the previous launch); the fits run side by side.  The
+// launch sequence does not depend on the random row blocks: those (and the
+// step sizes) come from a device table of `table_epochs` epochs refilled from
+// the host, so one recorded sequence (a HIP graph when asked for) serves every
+// epoch.
+namespace {
+
+struct BatchLaunch {
+  int seg0, nsegs, grid;
+};
+
+struct Batch {
+  std::vector<Ctx*> fits;
+  int prec = 0, KP = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  int table_epochs = 1;
+  int64_t steps_per_epoch = 0;
+  std::vector<int64_t> step_off;     // per fit: offset of its steps inside an epoch
+  int L = 0;                         // most steps per epoch over the fits
+  gmf::LevelArgs* fits_dev = nullptr;
+  gmf::BatchSeg* segs_dev = nullptr;
+  gmf::LevelStep* steps_dev = nullptr;
+  int* cursor = nullptr;
+  double* scal = nullptr;            // 8 doubles per fit
+  std::vector<BatchLaunch> launches;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t used = 0, valid = 0;       // epochs of the current table consumed / available
+  std::vector<gmf::LevelStep> host_steps;
+};
+
+struct BatchSizes {
+  int L = 0;
+  int64_t steps_per_epoch = 0;
+  size_t o_fits = 0, o_segs = 0, o_steps = 0, o_cursor = 0, o_scal = 0, total = 0;
+};
+
+bool batch_sizes(void* const* ctxs, int nfits, int table_epochs, BatchSizes& z) {
+  if (!ctxs || nfits < 1 || table_epochs < 1) return false;
+  for (int f = 0; f < nfits; ++f) {
+    if (!ctxs[f]) return false;
+    const Plan& P = as_ctx(ctxs[f])->P;
+    z.L = std::max(z.L, P.R * P.S);
+    z.steps_per_epoch += (int64_t)P.R * P.S;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  z.o_fits = take(sizeof(gmf::LevelArgs) * (size_t)nfits);
+  z.o_segs = take(sizeof(gmf::BatchSeg) * 2 * (size_t)z.L * nfits);
+  z.o_steps = take(sizeof(gmf::LevelStep) * (size_t)table_epochs * z.steps_per_epoch);
+  z.o_cursor = take(sizeof(int) * 4);
+  z.o_scal = take(sizeof(double) * 8 * (size_t)nfits);
+  z.total = o;
+  return true;
+}
+
+int enqueue_batch_epoch(Batch* b) {
+  for (const BatchLaunch& l : b->launches) {
+    gmf::BatchArgs ba;
+    ba.fits = b->fits_dev;
+    ba.segs = b->segs_dev + l.seg0;
+    ba.nsegs = l.nsegs;
+    ba.steps = b->steps_dev;
+    ba.steps_per_epoch = b->steps_per_epoch;
+    ba.table_epochs = b->table_epochs;
+    ba.cursor = b->cursor;
+    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st));
+  }
+  HIP_TRY(gmf::launch_advance_cursor(b->cursor, b->st));
+  return GMF_OK;
+}
+
+// Refill the step table with the next `ne` epochs of every fit (from each
+// fit's current step counter) and reset the cursor.  Waits for the batch
+// stream first: the previous table may still be read.
+int refill_batch_table(Batch* b, int ne) {
+  HIP_TRY(hipStreamSynchronize(b->st));
+  b->host_steps.resize((size_t)b->table_epochs * b->steps_per_epoch);
+  for (int e = 0; e < ne; ++e)
+    for (size_t f = 0; f < b->fits.size(); ++f) {
+      const Ctx* c = b->fits[f];
+      const int rs = c->P.R * c->P.S;
+      for (int k = 0; k < rs; ++k)
+        b->host_steps[(size_t)e * b->steps_per_epoch + b->step_off[f] + k] =
+            make_step(c, c->t + (int64_t)e * rs + k + 1);
+    }
+  HIP_TRY(hipMemcpyAsync(b->steps_dev, b->host_steps.data(),
+                         sizeof(gmf::LevelStep) * (size_t)ne * b->steps_per_epoch,
+                         hipMemcpyHostToDevice, b->st));
+  HIP_TRY(gmf::launch_fill_i32(b->cursor, 1, 0, b->st));
+  HIP_TRY(hipStreamSynchronize(b->st));
+  b->used = 0;
+  b->valid = ne;
+  return GMF_OK;
+}
+
+void destroy_batch(Batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" size_t gmf_batch_workspace_bytes(void* const* ctxs, int32_t nfits, int32_t table_epochs) {
+  BatchSizes z;
+  return batch_sizes(ctxs, nfits, table_epochs, z) ? z.total : 0;
+}
+
+extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits, void* ws,
+                              size_t ws_bytes, int32_t table_epochs, int32_t use_graph) {
+  if (!batch_out) return fail(GMF_EINVAL, "batch_out is NULL");
+  *batch_out = nullptr;
+  BatchSizes z;
+  if (!batch_sizes(ctxs, nfits, table_epochs, z))
+    return fail(GMF_EINVAL, "need nfits >= 1 non-NULL contexts and table_epochs >= 1");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < z.total)
+    return fail(GMF_EWORKSPACE, "batch workspace NULL, misaligned or smaller than " +
+                                    std::to_string(z.total) + " bytes");
+  const Plan& P0 = as_ctx(ctxs[0])->P;
+  for (int f = 0; f < nfits; ++f) {
+    const Plan& P = as_ctx(ctxs[f])->P;
+    if (P.prec != P0.prec || P.KP != P0.KP)
+      return fail(GMF_EINVAL, "batched fits need one precision and one panel stride "
+                              "(set gmf_config.panel_stride)");
+    for (int g = 0; g < f; ++g)
+      if (ctxs[g] == ctxs[f]) return fail(GMF_EINVAL, "a context appears twice in the batch");
+  }
+  Batch* b = new Batch();
+  b->prec = P0.prec;
+  b->KP = P0.KP;
+  b->table_epochs = table_epochs;
+  b->steps_per_epoch = z.steps_per_epoch;
+  b->L = z.L;
+  char* W = static_cast<char*>(ws);
+  b->fits_dev = reinterpret_cast<gmf::LevelArgs*>(W + z.o_fits);
+  b->segs_dev = reinterpret_cast<gmf::BatchSeg*>(W + z.o_segs);
+  b->steps_dev = reinterpret_cast<gmf::LevelStep*>(W + z.o_steps);
+  b->cursor = reinterpret_cast<int*>(W + z.o_cursor);
+  b->scal = reinterpret_cast<double*>(W + z.o_scal);
+  auto bail = [&](int code, const std::string& msg) {
+    destroy_batch(b);
+    return fail(code, msg);
+  };
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess)
+    return bail(GMF_EDEVICE, "cannot create the batch stream");
+  // descriptors and the static segment lists
+  std::vector<gmf::LevelArgs> fa(nfits);
+  int64_t off = 0;
+  for (int f = 0; f < nfits; ++f) {
+    Ctx* c = as_ctx(ctxs[f]);
+    b->fits.push_back(c);
+    fa[f] = level_args(c);
+    fa[f].trace = nullptr;
+    fa[f].trace_cap = 0;
+    b->step_off.push_back(off);
+    off += (int64_t)c->P.R * c->P.S;
+  }
+  std::vector<gmf::BatchSeg> segs;
+  for (int k = 0; k < b->L; ++k)
+    for (int kind = 0; kind < 2; ++kind) {
+      BatchLaunch l{(int)segs.size(), 0, 0};
+      for (int f = 0; f < nfits; ++f) {
+        const Plan& P = b->fits[f]->P;
+        if (k >= P.R * P.S) continue;
+        const int wgs = kind == 0 ? P.rr_max * P.ct_max : P.upd_per_step;
+        segs.push_back(gmf::BatchSeg{l.grid, f, kind, (int)(b->step_off[f] + k)});
+        l.grid += wgs;
+        ++l.nsegs;
+      }
+      if (l.nsegs > 0) b->launches.push_back(l);
+    }
+  if (hipMemcpyAsync(b->fits_dev, fa.data(), sizeof(gmf::LevelArgs) * fa.size(),
+                     hipMemcpyHostToDevice, b->st) != hipSuccess ||
+      hipMemcpyAsync(b->segs_dev, segs.data(), sizeof(gmf::BatchSeg) * segs.size(),
+                     hipMemcpyHostToDevice, b->st) != hipSuccess ||
+      hipStreamSynchronize(b->st) != hipSuccess)
+    return bail(GMF_EDEVICE, "cannot upload the batch tables");
+  if (use_graph) {
+    b->use_graph = true;
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bail(GMF_EDEVICE, "cannot capture the batch epoch");
+    const int rc = enqueue_batch_epoch(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->st, &g);
+    b->graph = g;
+    if (rc != GMF_OK || e != hipSuccess) return bail(GMF_EDEVICE, "batch epoch capture failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+      return bail(GMF_EDEVICE, "cannot instantiate the batch epoch graph");
+  }
+  *batch_out = b;
+  return GMF_OK;
+}
+
+extern "C" int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every,
+                             double* dev_trace_host) {
+  if (!batch) return fail(GMF_EINVAL, "batch is NULL");
+  if (epochs < 0 || eval_every < 1) return fail(GMF_EINVAL, "bad epochs / eval_every");
+  Batch* b = static_cast<Batch*>(batch);
+  const int nfits = (int)b->fits.size();
+  const int nevals = epochs / eval_every;
+  // order after the work already queued on the fits' own streams
+  for (Ctx* c : b->fits) {
+    HIP_TRY(hipEventRecord(b->ev, c->st));
+    HIP_TRY(hipStreamWaitEvent(b->st, b->ev, 0));
+  }
+  // a fresh table at every call: the fits may have been stepped on their own
+  b->used = b->valid = 0;
+  int ev_i = 0;
+  for (int e = 0; e < epochs; ++e) {
+    if (b->used == b->valid) {
+      const int rc = refill_batch_table(b, std::min(b->table_epochs, epochs - e));
+      if (rc != GMF_OK) return rc;
+    }
+    if (b->use_graph) {
+      HIP_TRY(hipGraphLaunch(b->exec, b->st));
+    } else {
+      const int rc = enqueue_batch_epoch(b);
+      if (rc != GMF_OK) return rc;
+    }
+    ++b->used;
+    for (Ctx* c : b->fits) c->t += (int64_t)c->P.R * c->P.S;
+    if ((e + 1) % eval_every == 0 && dev_trace_host) {
+      for (int f = 0; f < nfits; ++f) {
+        Ctx* c = b->fits[f];
+        gmf::DevArgs da = dev_args(c);
+        HIP_TRY(gmf::launch_deviance(c->P.fam, c->P.KP, da, b->st));
+        HIP_TRY(gmf::launch_finalize(da.partial, c->P.dev_tiles, nullptr, 0, c->at<int>(c->P.o_flag),
+                                     b->scal + 8 * f, b->st));
+      }
+      std::vector<double> h(8 * (size_t)nfits);
+      HIP_TRY(hipMemcpyAsync(h.data(), b->scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->st));
+      HIP_TRY(hipStreamSynchronize(b->st));
+      for (int f = 0; f < nfits; ++f) {
+        dev_trace_host[(size_t)f * nevals + ev_i] = h[8 * f];
+        if (h[8 * f + 5] != 0.0) {
+          const int rc = check_flag(b->fits[f]);
+          if (rc != GMF_OK) return rc;
+        }
+      }
+      ++ev_i;
+    }
+  }
+  // the fits' own streams continue after the batch
+  HIP_TRY(hipEventRecord(b->ev, b->st));
+  for (Ctx* c : b->fits) HIP_TRY(hipStreamWaitEvent(c->st, b->ev, 0));
+  return GMF_OK;
+}
+
+extern "C" void gmf_batch_destroy(void* batch) {
+  if (!batch) return;
+  Batch* b = static_cast<Batch*>(batch);
+  (void)hipStreamSynchronize(b->st);
+  destroy_batch(b);
+}

@@ -84,6 +84,7 @@ struct LevelArgs {
   int row_chunk, col_chunk, upd_per_step;
   // numerics
   FamilyArgs f;
+  int fam;             // family (read by the batched kernel; the others take it as a template)
   int p, q, d, KU, KV, KP;
   double lam_B, lam_A, lam_U, lam_V;
   double a1, a2, damping;
@@ -98,6 +99,32 @@ struct LevelArgs {
   int n_tile_steps, n_upd_steps;
   LevelStep steps[kMaxLevelSteps];
 };
+
+// Batched level launches over many fits.  A launch runs one phase (tiles or
+// updates) of one step of several fits; its workgroups are cut into segments,
+// one per (fit, step), in ascending `start` order.  The steps come from a
+// device table of `table_epochs` epochs x `steps_per_epoch` entries (every
+// fit's steps of one epoch, fit f at its own offset); *cursor selects the
+// epoch (mod table_epochs), so one recorded launch sequence serves every
+// epoch.
+struct BatchSeg {
+  int start;        // first workgroup of the segment
+  int fit;          // index into fits
+  int kind;         // 0: tiles, 1: updates
+  int step_index;   // entry inside an epoch of the step table
+};
+struct BatchArgs {
+  const LevelArgs* fits;
+  const BatchSeg* segs;
+  int nsegs;
+  const LevelStep* steps;
+  int64_t steps_per_epoch;
+  int table_epochs;
+  const int* cursor;
+};
+
+hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_advance_cursor(int* cursor, hipStream_t s);
 
 // ev_start / ev_stop (optional): HIP events stamped at the start and end of
 // this kernel's execution.

@@ -459,25 +459,24 @@ __device__ void sum_block_deviance(const LevelArgs& a, const LevelStep& st, doub
 }
 
 // ------------------------------------------------------------- kernel -----
+template <int PREC, int KP>
+union LevelLds {
+  TileLds<PREC, KP> tile;
+  double sums[kTileThreads];
+};
+
+// One task of a level launch: tile `local` of step `st` (tile_task) or update
+// workgroup `local` of step `st`.  Returns the task kind (0 tile, 1 row
+// update, 2 column update, 3 block deviance, -1 nothing to do).
 template <int PREC, int FAM, int KP, bool WANT_DEV>
-__global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
-  __shared__ union {
-    TileLds<PREC, KP> tile;
-    double sums[kTileThreads];
-  } L;
-  const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
-  __shared__ unsigned long long stamps[3];
-  const int T = a.rr_max * a.ct_max;
-  const int ntile_blocks = a.n_tile_steps * T;
-  int b = blockIdx.x;
-  int kind = 0;
-  if (b < ntile_blocks) {
-    const LevelStep& st = a.steps[b / T];
-    const int tile = b % T;
+__device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st, bool tile_task,
+                                        int local, LevelLds<PREC, KP>& L,
+                                        unsigned long long* stamps) {
+  if (tile_task) {
     const int n_b = st.n_b, m_b = st.m_b;
     const int n_ct = st.n_ct, rpw = st.rpw;
-    const int rr = tile / a.ct_max, ct = tile % a.ct_max;
-    if (rr >= st.n_rr || ct >= n_ct) return;   // this block has fewer tiles
+    const int rr = local / a.ct_max, ct = local % a.ct_max;
+    if (rr >= st.n_rr || ct >= n_ct) return -1;   // this block has fewer tiles
     TileView tv;
     tv.ldy = st.ldy;
     tv.Y = a.Y + st.yoff;
@@ -491,34 +490,53 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
     tv.col0 = ct * kTileCols;
     tv.Upart = a.Upart + (int64_t)st.slot * a.slot_u_elems + (int64_t)ct * n_b * (2 * a.KU);
     tv.Vpart = a.Vpart + (int64_t)st.slot * a.slot_v_elems + (int64_t)rr * m_b * (2 * a.KV);
-    tv.stamps = a.trace ? stamps : nullptr;
+    tv.stamps = stamps;
     tv.row_only = a.row_only != 0;
     const FamilyConst fc = family_const(a.f);
     const double dev = compute_tile<PREC, FAM, KP, WANT_DEV>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
     if (WANT_DEV && threadIdx.x == 0)
       a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
+    return 0;
+  }
+  int u = local;
+  const int n_b = st.n_b, m_b = st.m_b;
+  const int nrc = (n_b + a.row_chunk - 1) / a.row_chunk;
+  const int ncc = a.row_only ? 0 : (m_b + a.col_chunk - 1) / a.col_chunk;
+  if (u < nrc) {
+    update_rows(a, st, u * a.row_chunk, min(n_b, (u + 1) * a.row_chunk), L.sums);
+    return 1;
+  }
+  if ((u -= nrc) < ncc) {
+    update_cols(a, st, u * a.col_chunk, min(m_b, (u + 1) * a.col_chunk), L.sums);
+    return 2;
+  }
+  if (u == ncc) {
+    if (WANT_DEV) sum_block_deviance(a, st, L.sums);
+    return 3;
+  }
+  return -1;
+}
+
+template <int PREC, int FAM, int KP, bool WANT_DEV>
+__global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
+  __shared__ LevelLds<PREC, KP> L;
+  const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
+  __shared__ unsigned long long stamps[3];
+  const int T = a.rr_max * a.ct_max;
+  const int ntile_blocks = a.n_tile_steps * T;
+  int b = blockIdx.x;
+  int kind;
+  if (b < ntile_blocks) {
+    kind = run_task<PREC, FAM, KP, WANT_DEV>(a, a.steps[b / T], true, b % T, L,
+                                             a.trace ? stamps : nullptr);
   } else {
     b -= ntile_blocks;
     const int k = b / a.upd_per_step;
     if (k >= a.n_upd_steps) return;
-    const LevelStep& st = a.steps[a.n_tile_steps + k];
-    int u = b % a.upd_per_step;
-    const int n_b = st.n_b, m_b = st.m_b;
-    const int nrc = (n_b + a.row_chunk - 1) / a.row_chunk;
-    const int ncc = a.row_only ? 0 : (m_b + a.col_chunk - 1) / a.col_chunk;
-    if (u < nrc) {
-      kind = 1;
-      update_rows(a, st, u * a.row_chunk, min(n_b, (u + 1) * a.row_chunk), L.sums);
-    } else if ((u -= nrc) < ncc) {
-      kind = 2;
-      update_cols(a, st, u * a.col_chunk, min(m_b, (u + 1) * a.col_chunk), L.sums);
-    } else if (u == ncc) {
-      kind = 3;
-      if (WANT_DEV) sum_block_deviance(a, st, L.sums);
-    } else {
-      return;
-    }
+    kind = run_task<PREC, FAM, KP, WANT_DEV>(a, a.steps[a.n_tile_steps + k], false,
+                                             b % a.upd_per_step, L, nullptr);
   }
+  if (kind < 0) return;
   if (a.trace && threadIdx.x == 0) {
     const long long gi = (long long)a.trace_base + blockIdx.x;
     if (gi < a.trace_cap) {
@@ -533,6 +551,36 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
       rec[7] = kind == 0 ? stamps[2] : 0;
     }
   }
+}
+
+// Batched launches over many fits (see BatchArgs): the workgroup finds its
+// segment by a binary search over the launch's segment starts, takes the fit's
+// descriptor and the step from the device tables, and runs the task with the
+// fit's family chosen at run time (uniform over the workgroup).
+template <int PREC, int KP>
+__global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
+  __shared__ LevelLds<PREC, KP> L;
+  const int b = blockIdx.x;
+  int lo = 0, hi = ba.nsegs - 1;
+  while (lo < hi) {   // last segment with start <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (ba.segs[mid].start <= b) lo = mid; else hi = mid - 1;
+  }
+  const BatchSeg sg = ba.segs[lo];
+  const LevelArgs& a = ba.fits[sg.fit];
+  const int64_t e = (int64_t)(*ba.cursor % ba.table_epochs);
+  const LevelStep& st = ba.steps[e * ba.steps_per_epoch + sg.step_index];
+  const bool tile_task = sg.kind == 0;
+  const int local = b - sg.start;
+  switch (a.fam) {
+    case kPoisson: run_task<PREC, kPoisson, KP, false>(a, st, tile_task, local, L, nullptr); break;
+    case kNegBin: run_task<PREC, kNegBin, KP, false>(a, st, tile_task, local, L, nullptr); break;
+    default: run_task<PREC, kGaussian, KP, false>(a, st, tile_task, local, L, nullptr); break;
+  }
+}
+
+__global__ void advance_cursor_kernel(int* cursor) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cursor[0] = cursor[0] + 1;
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -579,6 +627,32 @@ hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArg
   if (ev_start || ev_stop)   // events stamped by the dispatch itself: kernel execution time only
     return hipExtLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s, ev_start, ev_stop, 0);
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s);
+}
+
+hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  const void* k = nullptr;
+  if (prec == kF32) {
+    switch (KP) {
+      case 16: k = reinterpret_cast<const void*>(&batch_kernel<kF32, 16>); break;
+      case 32: k = reinterpret_cast<const void*>(&batch_kernel<kF32, 32>); break;
+      case 48: k = reinterpret_cast<const void*>(&batch_kernel<kF32, 48>); break;
+      case 64: k = reinterpret_cast<const void*>(&batch_kernel<kF32, 64>); break;
+    }
+  } else {
+    switch (KP) {
+      case 32: k = reinterpret_cast<const void*>(&batch_kernel<kBF16, 32>); break;
+      case 64: k = reinterpret_cast<const void*>(&batch_kernel<kBF16, 64>); break;
+    }
+  }
+  if (!k) return hipErrorInvalidValue;
+  void* args[] = {const_cast<BatchArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s);
+}
+
+hipError_t launch_advance_cursor(int* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(advance_cursor_kernel, dim3(1), dim3(64), 0, s, cursor);
+  return hipGetLastError();
 }
 
 }  // namespace gmf

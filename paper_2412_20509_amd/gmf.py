@@ -42,6 +42,7 @@ class gmf_config(C.Structure):
         ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
         ("seed", C.c_uint64),
         ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
+        ("panel_stride", C.c_int32),
     ]
 
 
@@ -92,6 +93,11 @@ def load_library(path: str = LIB_PATH):
                                   f64p]),
         "gmf_project_warm": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, i32, i32, vp,
                                        vp, f64p, f64p, C.POINTER(i64)]),
+        "gmf_batch_workspace_bytes": (C.c_size_t, [C.POINTER(vp), i32, i32]),
+        "gmf_batch_init": (C.c_int, [C.POINTER(vp), C.POINTER(vp), i32, vp, C.c_size_t, i32,
+                                     i32]),
+        "gmf_batch_run": (C.c_int, [vp, i32, i32, f64p]),
+        "gmf_batch_destroy": (None, [vp]),
         "gmf_mlp_config_default": (None, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_workspace_bytes": (C.c_size_t, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_init": (C.c_int, [C.POINTER(vp), C.POINTER(gmf_mlp_config), vp, C.c_size_t,
@@ -287,6 +293,7 @@ class FitConfig:
     seed: int = 0
     tile_rows: int = 0
     skip_block_deviance: int = 0
+    panel_stride: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -305,6 +312,7 @@ class FitConfig:
         c.seed = self.seed
         c.tile_rows = self.tile_rows
         c.skip_block_deviance = self.skip_block_deviance
+        c.panel_stride = self.panel_stride
         return c
 
 
@@ -576,6 +584,51 @@ class Encoder:
         if getattr(self, "enc", None) is not None and self.enc.value:
             load_library().gmf_encoder_destroy(self.enc)
             self.enc = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ batched fits --
+
+class Batch:
+    """Several GMF contexts advanced together (gmf_batch_*)."""
+
+    def __init__(self, gmfs, table_epochs=4, use_graph=True):
+        import torch
+        self.torch = torch
+        self.gmfs = list(gmfs)
+        lib = load_library()
+        n = len(self.gmfs)
+        self._ctxs = (C.c_void_p * n)(*[g.ctx.value for g in self.gmfs])
+        nbytes = lib.gmf_batch_workspace_bytes(self._ctxs, n, int(table_epochs))
+        if nbytes == 0:
+            raise GMFError(GMF_EINVAL, "invalid batch")
+        dev = self.gmfs[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.batch = C.c_void_p()
+        _check(lib.gmf_batch_init(C.byref(self.batch), self._ctxs, n,
+                                  self.workspace.data_ptr() + off, nbytes, int(table_epochs),
+                                  int(bool(use_graph))))
+
+    def run(self, epochs, eval_every=1, trace=True):
+        """Run `epochs` epochs; returns the deviance trace (nfits x evaluations) or None."""
+        n = len(self.gmfs)
+        nev = epochs // eval_every
+        tr = (C.c_double * max(1, n * nev))() if trace else None
+        _check(load_library().gmf_batch_run(self.batch, int(epochs), int(eval_every), tr))
+        if not trace:
+            return None
+        return np.array(list(tr)[:n * nev]).reshape(n, nev)
+
+    def close(self):
+        if getattr(self, "batch", None) is not None and self.batch.value:
+            load_library().gmf_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

@@ -1,0 +1,101 @@
+"""Batched fits (gmf_batch_*): several contexts of different shapes and
+families advanced together must follow exactly the trajectories they follow on
+their own (same kernels' arithmetic, same step order per fit), with and without
+the recorded HIP graph, across step-table refills; one fit is also checked
+against the oracle."""
+import numpy as np
+import pytest
+
+from synth import gen_nb, gen_poisson_small
+
+from tests.gpu_helpers import compare_state, gpu_for, oracle_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def problems():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return [
+        gen_nb(n=1800, m=900, d=7, R=4, S=3, seed=1301),                  # k = 11
+        gen_poisson_small(n=700, m=500, d=12, R=5, S=2, seed=1302),       # k = 14
+        gen_nb(n=2500, m=640, d=20, R=6, S=5, seed=1303, family="poisson"),  # k = 24
+        gen_nb(n=333, m=1111, d=3, R=3, S=4, seed=1304),                  # ragged, k = 7
+    ]
+
+
+def _make(problems, stride, **over):
+    return [gpu_for(pr, panel_stride=stride, skip_block_deviance=1, **over) for pr in problems]
+
+
+def _state(g):
+    return [np.asarray(x) for x in g.params()] + [np.asarray(x) for x in g.moments()]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_separate_fits(problems, use_graph):
+    from paper_2412_20509_amd.gmf import Batch
+    print(f"[case] batch of 4 fits, graph={use_graph}", flush=True)
+    solo = _make(problems, 32)
+    for g, pr in zip(solo, problems):
+        g.step(2 * pr.R * pr.S)
+    fits = _make(problems, 32)
+    b = Batch(fits, table_epochs=4, use_graph=use_graph)
+    tr = b.run(2, eval_every=1, trace=True)
+    for g, h, pr in zip(fits, solo, problems):
+        assert g.steps_done() == 2 * pr.R * pr.S
+        for x, y in zip(_state(g), _state(h)):
+            assert np.array_equal(x, y)
+    # the deviance trace is the full deviance of each fit after each epoch
+    for f, (g, h) in enumerate(zip(fits, solo)):
+        assert tr.shape == (4, 2)
+        assert abs(tr[f, 1] - h.deviance()[0]) <= 1e-12 * abs(tr[f, 1])
+    b.close()
+    for g in fits + solo:
+        g.close()
+
+
+def test_batch_table_refill_and_continuation(problems):
+    """Three epochs through a 2-epoch table, then two more epochs in a second
+    call, equal five epochs stepped separately."""
+    from paper_2412_20509_amd.gmf import Batch
+    print("[case] batch refill + continuation", flush=True)
+    solo = _make(problems[:3], 32)
+    for g, pr in zip(solo, problems):
+        g.step(5 * pr.R * pr.S)
+    fits = _make(problems[:3], 32)
+    b = Batch(fits, table_epochs=2, use_graph=True)
+    b.run(3, trace=False)
+    b.run(2, eval_every=2, trace=True)
+    for g, h in zip(fits, solo):
+        for x, y in zip(_state(g), _state(h)):
+            assert np.array_equal(x, y)
+    b.close()
+    for g in fits + solo:
+        g.close()
+
+
+def test_batch_fit_matches_oracle(problems):
+    from paper_2412_20509_amd.gmf import Batch
+    print("[case] batch fit vs oracle", flush=True)
+    pr = problems[0]
+    fits = _make(problems[:2], 32)
+    b = Batch(fits, table_epochs=1, use_graph=True)
+    b.run(1, trace=False)
+    o = oracle_for(pr)
+    o.steps(pr.R * pr.S)
+    compare_state(fits[0], o, 1e-5, "batched NB fit, one epoch")
+    b.close()
+    for g in fits:
+        g.close()
+
+
+def test_batch_rejects_mixed_panel_strides(problems):
+    from paper_2412_20509_amd.gmf import Batch, GMFError
+    fits = [gpu_for(problems[0], panel_stride=16), gpu_for(problems[1], panel_stride=32)]
+    with pytest.raises(GMFError):
+        Batch(fits)
+    for g in fits:
+        g.close()
