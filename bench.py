@@ -24,6 +24,8 @@ Printed JSON line:
   cpu_baseline      the FP64 oracle on the host, bounded sample
   arms              the same measurements for the BF16 arm
   large             the 100000 x 5000 rank-20 workload (steps only)
+  batched           64 uneven fits advanced together (gmf_batch_*) against the
+                    same fits stepped one by one
   warm_start        learned warm start of 1,000,000 new rows: epochs and
                     seconds to 1e-4 of the converged projection deviance for a
                     cold start and for the encoder's bfloat16 predictions
@@ -236,6 +238,84 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
     )
 
 
+def batch_specs(nfits, scale, seed=1004):
+    """Shapes of the batched-fits workload: per fit a seeded coin for the family
+    (Poisson / NB), n ~ U{2000..50000}, m ~ U{1000..5000}, d ~ U{5..30}, with
+    n and m multiplied by `scale`; blocks of 10 % x 20 % (R = 10, S = 5)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(nfits):
+        fam = "negbin" if rng.random() < 0.5 else "poisson"
+        n = int(rng.integers(2000, 50001) * scale)
+        m = int(rng.integers(1000, 5001) * scale)
+        d = int(rng.integers(5, 31))
+        out.append(dict(family=fam, n=n, m=m, d=d, seed=seed * 100 + i))
+    return out
+
+
+def run_batched(nfits, scale, epochs, torch):
+    """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
+    against batched epochs (gmf_batch_*, with and without the recorded graph).
+    Fits are grouped into batches by panel stride (p + q + d <= 32 -> 32,
+    else 48)."""
+    from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF
+    from synth import gen_nb
+    specs = batch_specs(nfits, scale)
+    log(f"batched fits: generating {nfits} problems (scale {scale})")
+    fits, entries = [], 0
+    for sp in specs:
+        pr = gen_nb(n=sp["n"], m=sp["m"], d=sp["d"], R=10, S=5, seed=sp["seed"],
+                    family=sp["family"], chunked=True)
+        stride = 32 if pr.k <= 32 else 48
+        fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
+                       seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1)
+        fits.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
+        entries += pr.n * pr.m
+        del pr
+    torch.cuda.synchronize()
+    groups = {}
+    for g in fits:
+        groups.setdefault(g.cfg.panel_stride, []).append(g)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def solo():
+        for _ in range(epochs):
+            for g in fits:
+                g.step(g.cfg.R * g.cfg.S)
+
+    timed(lambda: [g.step(g.cfg.R * g.cfg.S) for g in fits])      # warm-up epoch
+    t_solo = timed(solo)
+    res = {}
+    for use_graph in (False, True):
+        batches = [Batch(gs, table_epochs=max(epochs, 1), use_graph=use_graph)
+                   for gs in groups.values()]
+        for b in batches:
+            b.run(1, trace=False)                                   # warm-up epoch
+        t = timed(lambda: [b.run(epochs, trace=False) for b in batches])
+        res["graph" if use_graph else "direct"] = t
+        for b in batches:
+            b.close()
+    for g in fits:
+        g.close()
+    return dict(
+        workload=(f"{nfits} fits: family coin Poisson/NB, n ~ U{{2000..50000}} x {scale}, "
+                  f"m ~ U{{1000..5000}} x {scale}, d ~ U{{5..30}}, p = 3, q = 1, blocks 10 % x 20 %"),
+        entries=entries, epochs=epochs, groups={int(k): len(v) for k, v in groups.items()},
+        separate_epochs_per_s=epochs / t_solo,
+        batched_epochs_per_s=epochs / res["direct"],
+        batched_graph_epochs_per_s=epochs / res["graph"],
+        batched_graph_entries_per_s=entries * epochs / res["graph"],
+        speedup_vs_separate=t_solo / res["graph"],
+    )
+
+
 def cpu_baseline(pr, epochs=3):
     from threadpoolctl import threadpool_info
     from oracle import gmf_oracle as G
@@ -270,6 +350,11 @@ def main():
     ap.add_argument("--warm-epochs", type=int, default=60,
                     help="projection epochs per arm (the reference runs 3x as many)")
     ap.add_argument("--encoder-epochs", type=int, default=40)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-fits section")
+    ap.add_argument("--batch-fits", type=int, default=64)
+    ap.add_argument("--batch-scale", type=float, default=0.5,
+                    help="factor on n and m of every batched fit")
+    ap.add_argument("--batch-epochs", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known size, to scale HBM byte counters) and exit")
@@ -333,6 +418,11 @@ def main():
         log(f"warm start: cold {warm['cold']['epochs_to_1e4']} epochs, "
             f"warm {warm['warm']['epochs_to_1e4']} epochs, "
             f"{warm['warm']['fallback_rows']} fallback rows")
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)
+        log(f"batched fits: {batched['batched_graph_epochs_per_s']:.1f} epochs/s batched "
+            f"(graph), {batched['separate_epochs_per_s']:.1f} separately")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
@@ -350,7 +440,7 @@ def main():
                     zero_fraction=float((pr.Y == 0).mean())),
         s_to_1e4=main_arm["s_to_1e4"], epochs_to_1e4=main_arm["epochs_to_1e4"],
         oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu, large=large,
-        warm_start=warm,
+        warm_start=warm, batched=batched,
         arms={k: {kk: vv for kk, vv in v.items()} for k, v in arms.items()},
     )
     print(json.dumps(out))

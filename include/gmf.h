@@ -277,6 +277,34 @@ int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every, double* dev_t
 void gmf_batch_destroy(void* batch);
 
 /* ---------------------------------------------------------------------------
+ * Tile autotuning.  The rows per step tile (gmf_config.tile_rows) trade the
+ * parallelism of a step against the partial sums its tiles write; the best
+ * value depends on the block shape.  gmf_tune measures candidates and records
+ * the fastest in a process-wide table keyed by (precision, family, panel
+ * stride, ceil(log2 |I|), ceil(log2 |J|)) with |I| = ceil(n/R), |J| = ceil(m/S);
+ * gmf_workspace_bytes and gmf_init use the table when tile_rows = 0 (else the
+ * automatic rule).  The table can be saved to and loaded from a text file.
+ * ------------------------------------------------------------------------- */
+/* gmf_tune -- for each candidate tile_rows (multiples of 32): gmf_init a
+ * context with it in ws (ws_bytes must cover gmf_workspace_bytes for every
+ * candidate), run min(steps, R*S) warm-up steps, time `steps` steps with HIP
+ * events on `stream`, destroy it.  us_per_step_host (may be NULL) receives
+ * ncand times; *best_host the fastest candidate, which is stored in the table.
+ * Inputs as in gmf_init.  Synchronises. */
+int gmf_tune(const gmf_config* cfg, void* ws, size_t ws_bytes, void* stream, const void* Y,
+             int32_t y_dtype, const float* X, const float* Z, const float* W, const float* B0,
+             const float* A0, const float* U0, const float* V0, const int32_t* candidates,
+             int32_t ncand, int32_t steps, int32_t* best_host, double* us_per_step_host);
+/* The table's tile_rows for cfg's class, or 0 when it has none. */
+int32_t gmf_tune_lookup(const gmf_config* cfg);
+void gmf_tune_table_clear(void);
+/* Text file, one class per line: precision family panel_stride log2|I| log2|J|
+ * tile_rows us_per_step; '#' starts a comment line.  Load merges into the
+ * table (GMF_EINVAL on a malformed line, the table unchanged). */
+int gmf_tune_table_save(const char* path);
+int gmf_tune_table_load(const char* path);
+
+/* ---------------------------------------------------------------------------
  * Warm-start encoder.  An MLP maps a row's counts to its latent scores:
  * x = log(1 + y_i) (m values) -> Linear(m, H) -> GELU -> Linear(H, H) -> GELU
  * -> Linear(H, d), GELU(z) = z Phi(z).  It is trained on (row, fitted u_i)

@@ -13,6 +13,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -136,12 +140,56 @@ std::string check_config(const gmf_config* c) {
   return "";
 }
 
+// ------------------------------------------------------------- tune table --
+// Rows per step tile chosen by measurement (gmf_tune) for a class of shapes:
+// precision, family, panel stride and the power-of-two classes of the block
+// size |I| = ceil(n/R), |J| = ceil(m/S).  Consulted when tile_rows = 0.
+struct TuneKey {
+  int prec, fam, KP, nb_log2, mb_log2;
+  bool operator<(const TuneKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (fam != o.fam) return fam < o.fam;
+    if (KP != o.KP) return KP < o.KP;
+    if (nb_log2 != o.nb_log2) return nb_log2 < o.nb_log2;
+    return mb_log2 < o.mb_log2;
+  }
+};
+struct TuneVal {
+  int tile_rows;
+  double us_per_step;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+int ilog2_ceil(int64_t x) {
+  int k = 0;
+  while (((int64_t)1 << k) < x) ++k;
+  return k;
+}
+
+int panel_stride_of(const gmf_config* c) {
+  const int k = c->p + c->q + c->d;
+  if (c->panel_stride > 0) return c->panel_stride;
+  return (c->precision == GMF_PREC_BF16) ? round_up(k, 32) : round_up(k, 16);
+}
+
+TuneKey tune_key(const gmf_config* c) {
+  return TuneKey{c->precision, c->family, panel_stride_of(c),
+                 ilog2_ceil((c->n + c->R - 1) / c->R), ilog2_ceil((c->m + c->S - 1) / c->S)};
+}
+
+int tune_lookup(const gmf_config* c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(c));
+  return it == g_tune.end() ? 0 : it->second.tile_rows;
+}
+
 void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.n = c->n; P.m = c->m; P.R = c->R; P.S = c->S;
   P.p = c->p; P.q = c->q; P.d = c->d; P.k = c->p + c->q + c->d;
   P.prec = c->precision; P.fam = c->family; P.with_w = with_w ? 1 : 0;
-  P.KP = (P.prec == GMF_PREC_BF16) ? round_up(P.k, 32) : round_up(P.k, 16);
-  if (c->panel_stride > 0) P.KP = c->panel_stride;
+  P.KP = panel_stride_of(c);
+  const int tuned_rows = c->tile_rows > 0 ? 0 : tune_lookup(c);
   P.KU = P.q + P.d; P.KV = P.p + P.d;
   P.ro.resize(P.R + 1); P.co.resize(P.S + 1);
   for (int r = 0; r <= P.R; ++r) P.ro[r] = (int)((int64_t)r * P.n / P.R);
@@ -164,6 +212,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
     int rpw = round_up((int)std::ceil((double)nr * nct_max / kTilesPerStepTarget), gmf::kRowGroup);
     rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
     if (c->tile_rows > 0) rpw = c->tile_rows;
+    else if (tuned_rows > 0) rpw = tuned_rows;
     P.rpw[r] = rpw;
     P.nrr[r] = (nr + rpw - 1) / rpw;
   }
@@ -1433,4 +1482,108 @@ extern "C" void gmf_batch_destroy(void* batch) {
   Batch* b = static_cast<Batch*>(batch);
   (void)hipStreamSynchronize(b->st);
   destroy_batch(b);
+}
+
+// ------------------------------------------------------------------ tuning --
+extern "C" int gmf_tune(const gmf_config* cfg, void* ws, size_t ws_bytes, void* stream,
+                        const void* Y, int32_t y_dtype, const float* X, const float* Z,
+                        const float* W, const float* B0, const float* A0, const float* U0,
+                        const float* V0, const int32_t* candidates, int32_t ncand, int32_t steps,
+                        int32_t* best_host, double* us_per_step_host) {
+  const std::string bad = check_config(cfg);
+  if (!bad.empty()) return fail(GMF_EINVAL, "invalid config: " + bad);
+  if (!candidates || ncand < 1 || steps < 1) return fail(GMF_EINVAL, "need candidates and steps >= 1");
+  for (int i = 0; i < ncand; ++i) {
+    gmf_config ci = *cfg;
+    ci.tile_rows = candidates[i];
+    if (!check_config(&ci).empty()) return fail(GMF_EINVAL, "bad candidate tile_rows");
+    if (gmf_workspace_bytes(&ci, W != nullptr) > ws_bytes)
+      return fail(GMF_EWORKSPACE, "tuning workspace smaller than a candidate needs");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = 0;
+  double best_us = 0.0;
+  int rc = GMF_OK;
+  for (int i = 0; i < ncand && rc == GMF_OK; ++i) {
+    gmf_config ci = *cfg;
+    ci.tile_rows = candidates[i];
+    void* ctx = nullptr;
+    rc = gmf_init(&ctx, &ci, ws, ws_bytes, stream, Y, y_dtype, X, Z, W, B0, A0, U0, V0);
+    if (rc != GMF_OK) break;
+    Ctx* c = as_ctx(ctx);
+    const int64_t warm = std::min<int64_t>(steps, (int64_t)c->P.R * c->P.S);
+    rc = enqueue_steps(c, warm);
+    if (rc == GMF_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(GMF_EDEVICE, "event");
+    if (rc == GMF_OK) rc = enqueue_steps(c, steps);
+    if (rc == GMF_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      rc = fail(GMF_EDEVICE, "event");
+    float ms = 0.f;
+    if (rc == GMF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(GMF_EDEVICE, "event");
+    if (rc == GMF_OK) rc = check_flag(c);
+    gmf_destroy(ctx);
+    if (rc != GMF_OK) break;
+    const double us = 1e3 * ms / steps;
+    if (us_per_step_host) us_per_step_host[i] = us;
+    if (i == 0 || us < best_us) {
+      best_us = us;
+      best = candidates[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != GMF_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(cfg)] = TuneVal{best, best_us};
+  }
+  if (best_host) *best_host = best;
+  return GMF_OK;
+}
+
+extern "C" int32_t gmf_tune_lookup(const gmf_config* cfg) {
+  if (!cfg || !check_config(cfg).empty()) return 0;
+  return tune_lookup(cfg);
+}
+
+extern "C" void gmf_tune_table_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+extern "C" int gmf_tune_table_save(const char* path) {
+  if (!path) return fail(GMF_EINVAL, "path is NULL");
+  std::ofstream out(path);
+  if (!out) return fail(GMF_EINVAL, std::string("cannot write ") + path);
+  out << "# libgmf tile-rows table: precision family panel_stride log2|I| log2|J| tile_rows us_per_step\n";
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : g_tune)
+    out << kv.first.prec << ' ' << kv.first.fam << ' ' << kv.first.KP << ' ' << kv.first.nb_log2 << ' '
+        << kv.first.mb_log2 << ' ' << kv.second.tile_rows << ' ' << kv.second.us_per_step << '\n';
+  return out.good() ? GMF_OK : fail(GMF_EINVAL, std::string("write failed: ") + path);
+}
+
+extern "C" int gmf_tune_table_load(const char* path) {
+  if (!path) return fail(GMF_EINVAL, "path is NULL");
+  std::ifstream in(path);
+  if (!in) return fail(GMF_EINVAL, std::string("cannot read ") + path);
+  std::map<TuneKey, TuneVal> rows;
+  std::string line;
+  int lineno = 0;
+  while (std::getline(in, line)) {
+    ++lineno;
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream ls(line);
+    TuneKey k;
+    TuneVal v;
+    if (!(ls >> k.prec >> k.fam >> k.KP >> k.nb_log2 >> k.mb_log2 >> v.tile_rows >> v.us_per_step) ||
+        v.tile_rows < 32 || v.tile_rows % 32 != 0 || v.tile_rows > 4096)
+      return fail(GMF_EINVAL, std::string(path) + ": bad line " + std::to_string(lineno));
+    rows[k] = v;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : rows) g_tune[kv.first] = kv.second;
+  return GMF_OK;
 }

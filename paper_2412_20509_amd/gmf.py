@@ -98,6 +98,12 @@ def load_library(path: str = LIB_PATH):
                                      i32]),
         "gmf_batch_run": (C.c_int, [vp, i32, i32, f64p]),
         "gmf_batch_destroy": (None, [vp]),
+        "gmf_tune": (C.c_int, [cfgp, vp, C.c_size_t, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                               C.POINTER(i32), i32, i32, C.POINTER(i32), f64p]),
+        "gmf_tune_lookup": (i32, [cfgp]),
+        "gmf_tune_table_clear": (None, []),
+        "gmf_tune_table_save": (C.c_int, [C.c_char_p]),
+        "gmf_tune_table_load": (C.c_int, [C.c_char_p]),
         "gmf_mlp_config_default": (None, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_workspace_bytes": (C.c_size_t, [C.POINTER(gmf_mlp_config)]),
         "gmf_encoder_init": (C.c_int, [C.POINTER(vp), C.POINTER(gmf_mlp_config), vp, C.c_size_t,
@@ -635,3 +641,62 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ tuning --
+
+def tune_table_load(path):
+    _check(load_library().gmf_tune_table_load(str(path).encode()))
+
+
+def tune_table_save(path):
+    _check(load_library().gmf_tune_table_save(str(path).encode()))
+
+
+def tune_table_clear():
+    load_library().gmf_tune_table_clear()
+
+
+def tune_lookup(cfg: gmf_config) -> int:
+    return int(load_library().gmf_tune_lookup(C.byref(cfg)))
+
+
+def tune(fc: FitConfig, Y, X, Z, B0, A0, U0, V0, candidates=(32, 64, 128, 256, 512),
+         steps=50, device="cuda:0", stream=None):
+    """gmf_tune on the given problem: returns (best tile_rows, {candidate: us per step});
+    the best value is recorded in the library's table for this shape class."""
+    import torch
+    dev = torch.device(device)
+    Y = np.asarray(Y)
+    n, m = Y.shape
+    p = 0 if X is None else np.asarray(X).reshape(n, -1).shape[1]
+    q = 0 if Z is None else np.asarray(Z).reshape(m, -1).shape[1]
+    cfg = fc.to_c(n, m, p, q)
+    need = 0
+    for cand in candidates:
+        ci = fc.to_c(n, m, p, q)
+        ci.tile_rows = int(cand)
+        nb = gmf_workspace_bytes(ci, False)
+        if nb == 0:
+            raise GMFError(GMF_EINVAL, f"bad candidate {cand}")
+        need = max(need, nb)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    f32 = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a, np.float32),
+                                                          device=dev)
+    if np.issubdtype(Y.dtype, np.integer):
+        Yt, ydt = torch.as_tensor(np.ascontiguousarray(Y, np.int32), device=dev), GMF_Y_INT32
+    else:
+        Yt, ydt = f32(Y), GMF_Y_FLOAT32
+    Xt, Zt = f32(None if p == 0 else X), f32(None if q == 0 else Z)
+    Bt, At = f32(None if p == 0 else B0), f32(None if q == 0 else A0)
+    Ut, Vt = f32(U0), f32(V0)
+    cands = (C.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    us = (C.c_double * len(candidates))()
+    best = C.c_int32(0)
+    _check(load_library().gmf_tune(C.byref(cfg), ws.data_ptr() + off, need, st.cuda_stream,
+                                   _ptr(Yt), ydt, _ptr(Xt), _ptr(Zt), None, _ptr(Bt), _ptr(At),
+                                   _ptr(Ut), _ptr(Vt), cands, len(candidates), int(steps),
+                                   C.byref(best), us))
+    return best.value, {int(c): float(u) for c, u in zip(candidates, us)}

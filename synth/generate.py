@@ -135,12 +135,14 @@ def _nb_zero_frac(eta, alpha):
 
 
 def gen_nb(n=10_000, m=2_000, d=10, R=10, S=5, alpha=5.0, zero_frac=0.85,
-           seed=1002, family="negbin", calib_rows=2000, chunk_rows=4096):
+           seed=1002, family="negbin", calib_rows=2000, chunk_rows=4096, chunked=None):
     """Negative binomial (or Poisson with the same mean) single-cell-shaped data.
 
     X = [1, b, x] with b a batch indicator for a seeded half of the rows and
     x ~ N(0, 1); Z = 1.  The intercept shift c is bisected on a seeded subset
-    of rows so that the expected zero fraction equals ``zero_frac``.
+    of rows so that the expected zero fraction equals ``zero_frac``.  Counts are
+    drawn from one stream in row order, or (``chunked``, the default above 1e8
+    entries) in row chunks with a stream per chunk, in parallel.
     """
     rng = _rng(seed)
     batch = np.zeros(n)
@@ -177,7 +179,9 @@ def gen_nb(n=10_000, m=2_000, d=10, R=10, S=5, alpha=5.0, zero_frac=0.85,
     B[:, 0] += c
 
     Y = np.empty((n, m), dtype=np.int32)
-    if n * m < _PAR_THRESHOLD:
+    if chunked is None:
+        chunked = n * m >= _PAR_THRESHOLD
+    if not chunked:
         yr = _rng(seed + 11)
         for r0 in range(0, n, chunk_rows):
             r1 = min(n, r0 + chunk_rows)

@@ -99,3 +99,28 @@ def test_batch_rejects_mixed_panel_strides(problems):
         Batch(fits)
     for g in fits:
         g.close()
+
+
+def test_tune_records_fastest_candidate_and_plans_with_it():
+    from paper_2412_20509_amd import gmf as M
+    print("[case] gmf_tune on NB 3000x800", flush=True)
+    pr = gen_nb(n=3000, m=800, d=6, R=3, S=2, seed=1401)
+    fc = M.FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
+                     seed=pr.sched_seed)
+    M.tune_table_clear()
+    best, us = M.tune(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0,
+                      candidates=(32, 96, 256), steps=12)
+    assert best in (32, 96, 256)
+    assert all(v > 0 for v in us.values()) and us[best] == min(us.values())
+    assert M.tune_lookup(fc.to_c(pr.n, pr.m, pr.p, pr.q)) == best
+    # a context with tile_rows = 0 now plans with the tuned rows: same trajectory
+    # as one given tile_rows = best explicitly
+    g0 = gpu_for(pr)
+    g1 = gpu_for(pr, tile_rows=best)
+    g0.step(9)
+    g1.step(9)
+    for x, y in zip(_state(g0), _state(g1)):
+        assert np.array_equal(x, y)
+    M.tune_table_clear()
+    g0.close()
+    g1.close()

@@ -89,3 +89,39 @@ def test_product_path_does_not_touch_oracle():
         if path.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
             txt = open(path).read()
             assert "oracle" not in txt.lower(), path
+
+
+def test_tune_table_round_trip_and_lookup(lib, tmp_path):
+    """The tile-rows table (host logic only): load, lookup by shape class, the
+    workspace size follows the tuned rows, save/load round trip, bad lines."""
+    from paper_2412_20509_amd import gmf as M
+    cfg = M.gmf_config_default()
+    cfg.family, cfg.n, cfg.m, cfg.d, cfg.p, cfg.q = M.GMF_NEGBIN, 10000, 2000, 10, 3, 1
+    M.tune_table_clear()
+    assert M.tune_lookup(cfg) == 0
+    auto_bytes = M.gmf_workspace_bytes(cfg)
+    # class of this cfg: FP32, NB, stride 16, ceil(log2 1000) = 10, ceil(log2 400) = 9
+    path = tmp_path / "tune.txt"
+    path.write_text("# comment\n0 1 16 10 9 128 3.5\n0 1 16 11 9 64 9.0\n")
+    M.tune_table_load(path)
+    assert M.tune_lookup(cfg) == 128
+    cfg2 = M.gmf_config_default()
+    cfg2.family, cfg2.n, cfg2.m, cfg2.d, cfg2.p, cfg2.q = M.GMF_NEGBIN, 20000, 2000, 10, 3, 1
+    assert M.tune_lookup(cfg2) == 64
+    tuned_bytes = M.gmf_workspace_bytes(cfg)
+    cfg.tile_rows = 128
+    assert tuned_bytes == M.gmf_workspace_bytes(cfg)       # same plan as an explicit 128
+    cfg.tile_rows = 0
+    assert tuned_bytes != auto_bytes
+    out = tmp_path / "saved.txt"
+    M.tune_table_save(out)
+    M.tune_table_clear()
+    assert M.tune_lookup(cfg) == 0
+    M.tune_table_load(out)
+    assert M.tune_lookup(cfg) == 128 and M.tune_lookup(cfg2) == 64
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 1 16 10 9 100 1.0\n")                 # not a multiple of 32
+    with pytest.raises(M.GMFError):
+        M.tune_table_load(bad)
+    assert M.tune_lookup(cfg) == 128                          # unchanged by the failed load
+    M.tune_table_clear()
