@@ -313,6 +313,10 @@ struct Ctx {
   std::vector<hipEvent_t> events;   // 2 per timed launch
   int64_t timed_launches = 0;
   int64_t timed_steps = 0;
+  // sums of w c(y), the count-only part of half the unit deviance, per block
+  // (r * S + s) and in total (float64; constant during the fit)
+  std::vector<double> kblock;
+  double ktotal = 0.0;
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -513,6 +517,23 @@ gmf::DevArgs dev_args(Ctx* c) {
   return a;
 }
 
+// Sums of w c(y) per block from the per-tile sums of count_sum_kernel (tiles of
+// a block are consecutive), in a fixed order; tileblk: tile -> block.
+int count_constants(int fam, const gmf::DevArgs& da, const std::vector<int>& tileblk, int nblocks,
+                    hipStream_t st, std::vector<double>& kblock, double& ktotal) {
+  kblock.assign(nblocks, 0.0);
+  ktotal = 0.0;
+  if (fam == GMF_GAUSSIAN || da.n_tiles == 0) return GMF_OK;
+  HIP_TRY(gmf::launch_count_sum(fam, da, st));
+  std::vector<double> part(da.n_tiles);
+  HIP_TRY(hipMemcpyAsync(part.data(), da.partial, sizeof(double) * part.size(),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int t = 0; t < da.n_tiles; ++t) kblock[tileblk[t]] += part[t];
+  for (double k : kblock) ktotal += k;
+  return GMF_OK;
+}
+
 int compute_deviance(Ctx* c, double* total, double* pen) {
   const Plan& P = c->P;
   gmf::DevArgs a = dev_args(c);
@@ -530,6 +551,7 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
   double h[6];
   HIP_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
+  h[0] += 2.0 * c->ktotal;
   if (total) *total = h[0];
   if (pen) {
     const double* lam = c->cfg.lambda;
@@ -702,7 +724,9 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
     delete c;
     return fail(GMF_EDEVICE, std::string("gmf_init: ") + hipGetErrorString(e));
   }
-  const int rc = check_flag(c);
+  int rc = check_flag(c);
+  if (rc == GMF_OK)
+    rc = count_constants(P.fam, dev_args(c), tileblk, nb, st, c->kblock, c->ktotal);
   if (rc != GMF_OK) {
     delete c;
     return rc;
@@ -770,7 +794,8 @@ int gmf_block_deviance(void* ctx, double* out_host, int64_t count) {
   HIP_TRY(hipStreamSynchronize(c->st));
   for (int64_t k = 0; k < count; ++k) {
     const int64_t t = c->t - count + 1 + k;
-    out_host[k] = ring[(t - 1) % kDevRing];
+    const int r = row_block_of_step(c, t), s = (int)((t - 1) % c->P.S);
+    out_host[k] = ring[(t - 1) % kDevRing] + 2.0 * c->kblock[r * c->P.S + s];
   }
   return check_flag(c);
 }
@@ -1091,11 +1116,18 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
   da.partial = reinterpret_cast<double*>(at(Q.o_devpartial));
   da.n_tiles = Q.dev_tiles;
   double* scal = reinterpret_cast<double*>(at(Q.o_scal));
+  std::vector<double> kproj;
+  double kproj_total = 0.0;
+  if (dev_trace_host) {
+    const int rc = count_constants(P.fam, da, tileblk, P.S, st, kproj, kproj_total);
+    if (rc != GMF_OK) return rc;
+  }
   auto proj_dev = [&](double* out) -> int {
     HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, st));
     HIP_TRY(gmf::launch_finalize(da.partial, Q.dev_tiles, nullptr, 0, nullptr, scal, st));
     HIP_TRY(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    *out += 2.0 * kproj_total;
     return GMF_OK;
   };
   if (dev_trace_host) {
@@ -1462,7 +1494,7 @@ extern "C" int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every,
       HIP_TRY(hipMemcpyAsync(h.data(), b->scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->st));
       HIP_TRY(hipStreamSynchronize(b->st));
       for (int f = 0; f < nfits; ++f) {
-        dev_trace_host[(size_t)f * nevals + ev_i] = h[8 * f];
+        dev_trace_host[(size_t)f * nevals + ev_i] = h[8 * f] + 2.0 * b->fits[f]->ktotal;
         if (h[8 * f + 5] != 0.0) {
           const int rc = check_flag(b->fits[f]);
           if (rc != GMF_OK) return rc;

@@ -7,8 +7,11 @@
 //    order <-> caller arrays in original order.
 //  * deviance_kernel: full deviance sum_ij w D(y, mu) of the current iterate
 //    (definition after eq. 2; Supplementary Table 1; Appendix B for NB), eta on
-//    the float32 matrix cores, per-entry deviance in float32, float64
-//    accumulation in a fixed order (per-tile partials, then one ordered sum).
+//    the float32 matrix cores, per-entry deviance (its mu part) in float32,
+//    float64 accumulation in a fixed order (per-tile partials, then one
+//    ordered sum).
+//  * count_sum_kernel: per deviance tile, sum w c(y) of the count-only part
+//    of the deviance in float64 (constant during a fit).
 #include <hip/hip_runtime.h>
 
 #include "family.hpp"
@@ -389,6 +392,56 @@ static hipError_t launch_dev_kp(int KP, const DevArgs& a, hipStream_t s) {
     case 48: hipLaunchKernelGGL((deviance_kernel<FAM, 48>), grid, block, 0, s, a); break;
     case 64: hipLaunchKernelGGL((deviance_kernel<FAM, 64>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ count-only part --
+template <int FAM>
+__global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
+  __shared__ double red[kTileThreads];
+  const int tile = blockIdx.x;
+  const int blk = a.tile_block[tile];
+  const int local = tile - a.tile_first[blk];
+  const int n_b = a.blk_nb[blk], m_b = a.blk_mb[blk];
+  const int ldy = a.blk_ldy[blk];
+  const int n_ct = a.blk_nct[blk];
+  const int rpw = a.blk_rpw[blk];
+  const float* Y = a.Y + a.blk_yoff[blk];
+  const float* W = a.W ? a.W + a.blk_yoff[blk] : nullptr;
+  const int ct = local % n_ct, rr = local / n_ct;
+  const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
+  const int col0 = ct * kTileCols, col_end = min(m_b, col0 + kTileCols);
+  const double alpha = (double)a.f.nb_alpha;
+  double acc = 0.0;
+  // thread t: column col0 + t % 128 of rows row0 + t / 128, row0 + t / 128 + 2, ...
+  const int c = col0 + (int)(threadIdx.x % kTileCols);
+  if (c < col_end)
+    for (int r = row0 + (int)(threadIdx.x / kTileCols); r < row_end; r += kTileThreads / kTileCols) {
+      const int64_t idx = (int64_t)r * ldy + c;
+      const double w = W ? (double)W[idx] : 1.0;
+      acc += w * count_part<FAM>((double)Y[idx], alpha);
+    }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kTileThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[tile] = red[0];
+}
+
+hipError_t launch_count_sum(int fam, const DevArgs& a, hipStream_t s) {
+  if (a.n_tiles <= 0) return hipSuccess;
+  switch (fam) {
+    case kPoisson:
+      hipLaunchKernelGGL((count_sum_kernel<kPoisson>), dim3(a.n_tiles), dim3(kTileThreads), 0, s, a);
+      break;
+    case kNegBin:
+      hipLaunchKernelGGL((count_sum_kernel<kNegBin>), dim3(a.n_tiles), dim3(kTileThreads), 0, s, a);
+      break;
+    default:
+      return hipSuccess;   // Gaussian: no count-only part
   }
   return hipGetLastError();
 }

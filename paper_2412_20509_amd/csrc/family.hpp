@@ -14,9 +14,17 @@
 //
 //   Unit deviances (Supplementary Table 1 times 2; NB form of Appendix B):
 //   Poisson 2[y log(y/mu) - (y - mu)], NB 2[y log(y/mu) - (y+a) log((y+a)/(mu+a))],
-//   Gaussian (y - mu)^2.  For the log link log(mu) is the clamped eta itself;
-//   the NB term uses (y+a)/(mu+a) = 1 + (y-mu)/(mu+a) and a log1p that keeps
-//   full relative accuracy when y is close to mu (and at y = 0).
+//   Gaussian (y - mu)^2.  For the log link log(mu) is the clamped eta itself.
+//   The Poisson and NB deviances split into a part that depends on the count
+//   only and a part that depends on mu (using (y+a)/(mu+a) = (1 + y/a)/(1 + mu/a)):
+//     Poisson  D/2 = c(y) + [mu - y log mu],                 c(y) = y log y - y,
+//     NB       D/2 = c(y) + [(y+a) log1p(mu/a) - y log mu],  c(y) = y log y - (y+a) log1p(y/a),
+//   with c(0) = 0.  The per-entry epilogue forms only the mu part ("dev" below);
+//   sums of w c(y) over a block never change during a fit, so they are formed
+//   once, in float64, and added to the block and full deviances.
+//   log1p(mu/a) is log(q) for the rounded q = 1 + mu/a plus the correction
+//   for that rounding, which keeps full relative accuracy for small mu/a (the
+//   zero counts); 1/q = a/(a + mu) reuses the reciprocal of the Fisher weight.
 //
 // Arithmetic: the hardware exp2 / log2 / reciprocal instructions (1-ulp
 // class, no denormal range reduction: every argument here is a normal number),
@@ -36,19 +44,12 @@ __device__ __forceinline__ float fast_log(float x) {
   return __builtin_amdgcn_logf(x) * 0.6931471805599453f;
 }
 
-// log(1 + x) for x > -1: series for |x| < 1/8 (truncation below 1e-8
-// relative), the logarithm of 1 + x otherwise.  Branch free.
-__device__ __forceinline__ float log1p_small(float x) {
-  float p = fmaf(x, -0.125f, 0.14285714f);
-  p = fmaf(x, p, -0.16666667f);
-  p = fmaf(x, p, 0.2f);
-  p = fmaf(x, p, -0.25f);
-  p = fmaf(x, p, 0.33333333f);
-  p = fmaf(x, p, -0.5f);
-  p = fmaf(x, p, 1.0f);
-  const float series = x * p;
-  const float direct = fast_log(1.0f + x);
-  return (fabsf(x) < 0.125f) ? series : direct;
+// log(1 + z) for z >= 0 given inv_q = 1/(1 + z): the logarithm of the rounded
+// q = 1 + z plus the first-order correction for that rounding, (z - (q - 1))/q
+// (q - 1 is exact); accurate to a few ulps of log(1 + z) for every z >= 0.
+__device__ __forceinline__ float log1p_pos(float z, float inv_q) {
+  const float q = 1.0f + z;
+  return fmaf(z - (q - 1.0f), inv_q, fast_log(q));
 }
 
 // Per-launch constants of the epilogue.
@@ -67,7 +68,17 @@ __device__ __forceinline__ FamilyConst family_const(const FamilyArgs& f) {
   return c;
 }
 
+// The count-only part c(y) of half the unit deviance (see above), float64.
+template <int FAM>
+__device__ __forceinline__ double count_part(double y, double a) {
+  if (FAM == kGaussian || y <= 0.0) return 0.0;
+  if constexpr (FAM == kPoisson) return y * log(y) - y;
+  else return y * log(y) - (y + a) * log1p(y / a);
+}
+
 // eta: linear predictor, y: response, w: weight (1 when there are none).
+// dev (WANT_DEV): the mu part of the unit deviance times w -- the full unit
+// deviance for the Gaussian family, 2 w [D/2 - c(y)] for Poisson and NB.
 template <int FAM, bool WANT_DEV>
 __device__ __forceinline__ void family_entry(float eta, float y, float w, const FamilyConst& c,
                                              float& d1, float& d2, float& dev) {
@@ -85,9 +96,7 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
       d1 = wp * (mu - y);
       d2 = wp * mu;
       if constexpr (WANT_DEV) {
-        const float ly = fast_log(fmaxf(y, 1.0f));
-        const float t = (y > 0.f) ? fmaf(y, ly - ec, mu - y) : mu;
-        dev = 2.f * w * t;
+        dev = 2.f * w * fmaf(-y, ec, mu);
       }
     } else {
       const float s = c.a + mu;
@@ -96,11 +105,7 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
       d1 = wa * (mu - y);
       d2 = wa * mu;
       if constexpr (WANT_DEV) {
-        // y log(y/mu) - (y+a) log((y+a)/(mu+a)) with log(mu) = ec and
-        // (y+a)/(mu+a) = 1 + (y - mu)/(mu + a)
-        const float ylogy = (y > 0.f) ? y * fast_log(y) : 0.f;
-        const float t = ylogy - y * ec - (y + c.a) * log1p_small((y - mu) * inv);
-        dev = 2.f * w * t;
+        dev = 2.f * w * fmaf(y + c.a, log1p_pos(mu * c.inv_a, c.a * inv), -y * ec);
       }
     }
   }

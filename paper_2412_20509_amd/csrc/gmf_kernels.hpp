@@ -146,6 +146,9 @@ struct DevArgs {
   int n_tiles;
 };
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s);
+// a.partial[tile] = sum over the tile of w c(y), the count-only part of half
+// the unit deviance (float64; nothing for the Gaussian family).
+hipError_t launch_count_sum(int fam, const DevArgs& a, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int count, double* out,
                                hipStream_t s);
 hipError_t launch_norms(const float* Prow, const float* Pcol, int KP, int64_t n, int64_t m,
