@@ -136,6 +136,17 @@ int gmf_step(void* ctx, int64_t nsteps);
 int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
             double* dev_trace_host, int32_t* epochs_done_host);
 
+/* gmf_run -- run `epochs` epochs (R*S steps each) and, every eval_every
+ * epochs when dev_trace_host is not NULL, the full deviance (as gmf_deviance)
+ * of the iterate at that point, evaluated on a second stream from a copy of
+ * the panels so that it overlaps the following steps.  dev_trace_host
+ * receives epochs/eval_every values; eval_ms_host (may be NULL) the time at
+ * which each evaluation finished on the device, in ms since the call's work
+ * began.  No early stop.  Needs no more workspace than gmf_workspace_bytes
+ * gives.  Synchronises at the end (and every 256 evaluations). */
+int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_host,
+            double* eval_ms_host);
+
 /* gmf_deviance -- full deviance sum_ij w_ij D(y_ij, mu_ij) of the current
  * parameters (D as defined after eq. 2, Supplementary Table 1 times 2;
  * NB deviance of Appendix B), accumulated in float64 in a fixed order, and the

@@ -94,11 +94,12 @@ struct Plan {
       o_colloc, o_blkrowbase, o_blknrows, o_blkcoloff, o_blkld, o_tileblk, o_tilefirst,
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
       o_scal, o_sumsq, o_post, o_firstnz, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
-      o_ld, o_nct, o_coP, total;
+      o_ld, o_nct, o_coP, o_snap, o_devpart2, o_evring, total;
   int row_chunk = 1, col_chunk = 1, upd_per_step = 1;
 };
 
 constexpr int kDevRing = 4096;
+constexpr int kEvRing = 256;   // gmf_run evaluation results held on the device
 constexpr int64_t kMaxTimedSteps = 8192;
 constexpr int kMaxSlots = 16;
 constexpr int kTilesPerStepTarget = 256;
@@ -273,6 +274,11 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_devpartial = take(sizeof(double) * (size_t)P.dev_tiles);
   P.o_scal = take(sizeof(double) * 16);
   P.o_sumsq = take(sizeof(double) * kSumsqBlocks * 4);
+  // gmf_run: two snapshots of both panels, two sets of deviance partials and
+  // a ring of evaluation results
+  P.o_snap = take(sizeof(float) * 2 * (size_t)(P.n + P.m) * P.KP);
+  P.o_devpart2 = take(sizeof(double) * 2 * (size_t)P.dev_tiles);
+  P.o_evring = take(sizeof(double) * 8 * kEvRing);
   P.o_post = take(sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks));
   P.o_firstnz = take(sizeof(int) * 64);
   P.o_ro = take(sizeof(int) * (P.R + 1));
@@ -317,6 +323,10 @@ struct Ctx {
   // (r * S + s) and in total (float64; constant during the fit)
   std::vector<double> kblock;
   double ktotal = 0.0;
+  // gmf_run: a second stream for the overlapped deviance and its events
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ev_snap, ev_done;
+  hipEvent_t ev_start = nullptr;
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -1243,7 +1253,105 @@ void gmf_destroy(void* ctx) {
   Ctx* c = as_ctx(ctx);
   if (!c) return;
   for (auto& e : c->events) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    for (auto& e : c->ev_snap) (void)hipEventDestroy(e);
+    for (auto& e : c->ev_done) (void)hipEventDestroy(e);
+    if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+    (void)hipStreamDestroy(c->side);
+  }
   delete c;
+}
+
+// gmf_run: epochs of steps on the context's stream; every eval_every epochs
+// the panels are copied into one of two snapshot buffers and the full
+// deviance of the snapshot is formed on a second stream, overlapped with the
+// following steps.  A snapshot buffer is reused only after the evaluation
+// that read it has finished (the context's stream waits for it).
+int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_host,
+            double* eval_ms_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  if (epochs < 0 || eval_every < 1) return fail(GMF_EINVAL, "bad epochs / eval_every");
+  if (eval_ms_host && !dev_trace_host) return fail(GMF_EINVAL, "eval_ms_host needs dev_trace_host");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  const int64_t per_epoch = (int64_t)P.R * P.S;
+  const int nev = dev_trace_host ? epochs / eval_every : 0;
+  if (nev > 0) {
+    if (!c->side) {
+      HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreate(&c->ev_start));
+    }
+    while ((int)c->ev_done.size() < nev) {
+      hipEvent_t a = nullptr, b = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+      HIP_TRY(hipEventCreate(&b));
+      c->ev_snap.push_back(a);
+      c->ev_done.push_back(b);
+    }
+    HIP_TRY(hipEventRecord(c->ev_start, c->st));
+  }
+  const size_t snap_elems = (size_t)(P.n + P.m) * P.KP;
+  float* snap = c->at<float>(P.o_snap);
+  double* part2 = c->at<double>(P.o_devpart2);
+  double* evring = c->at<double>(P.o_evring);
+  std::vector<double> res(8 * (size_t)std::max(nev, 1));
+  int ev_i = 0, drained = 0;
+  auto drain = [&](int upto) -> int {   // copy evaluations [drained, upto) to the host
+    if (upto <= drained) return GMF_OK;
+    HIP_TRY(hipStreamSynchronize(c->side));
+    for (int i = drained; i < upto; ++i)
+      HIP_TRY(hipMemcpy(&res[8 * (size_t)i], evring + 8 * (i % kEvRing), 8 * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    drained = upto;
+    return GMF_OK;
+  };
+  for (int e = 1; e <= epochs; ++e) {
+    int rc = enqueue_steps(c, per_epoch);
+    if (rc != GMF_OK) return rc;
+    if (nev == 0 || e % eval_every != 0 || ev_i >= nev) continue;
+    const int slot = ev_i & 1;
+    if (ev_i >= 2) HIP_TRY(hipStreamWaitEvent(c->st, c->ev_done[ev_i - 2], 0));
+    if (ev_i - drained >= kEvRing) {
+      rc = drain(ev_i - kEvRing + 1);
+      if (rc != GMF_OK) return rc;
+    }
+    float* srow = snap + slot * snap_elems;
+    float* scol = srow + (size_t)P.n * P.KP;
+    HIP_TRY(hipMemcpyAsync(srow, c->at<float>(P.o_Prow), sizeof(float) * (size_t)P.n * P.KP,
+                           hipMemcpyDeviceToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(scol, c->at<float>(P.o_Pcol), sizeof(float) * (size_t)P.m * P.KP,
+                           hipMemcpyDeviceToDevice, c->st));
+    HIP_TRY(hipEventRecord(c->ev_snap[ev_i], c->st));
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_snap[ev_i], 0));
+    gmf::DevArgs da = dev_args(c);
+    da.Prow = srow;
+    da.Pcol = scol;
+    da.partial = part2 + slot * (size_t)P.dev_tiles;
+    HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, c->side));
+    HIP_TRY(gmf::launch_finalize(da.partial, P.dev_tiles, nullptr, 0, c->at<int>(P.o_flag),
+                                 evring + 8 * (ev_i % kEvRing), c->side));
+    HIP_TRY(hipEventRecord(c->ev_done[ev_i], c->side));
+    ++ev_i;
+  }
+  if (nev > 0) {
+    const int rc = drain(ev_i);
+    if (rc != GMF_OK) return rc;
+    // the context's stream continues after the last evaluation
+    HIP_TRY(hipStreamWaitEvent(c->st, c->ev_done[ev_i - 1], 0));
+    bool flagged = false;
+    for (int i = 0; i < ev_i; ++i) {
+      dev_trace_host[i] = res[8 * (size_t)i] + 2.0 * c->ktotal;
+      flagged = flagged || res[8 * (size_t)i + 5] != 0.0;
+      if (eval_ms_host) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_start, c->ev_done[i]));
+        eval_ms_host[i] = ms;
+      }
+    }
+    if (flagged) return check_flag(c);
+  }
+  return GMF_OK;
 }
 
 }  // extern "C"

@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "gmf_step": (C.c_int, [vp, i64]),
         "gmf_fit": (C.c_int, [vp, i32, C.c_double, i32, f64p, C.POINTER(i32)]),
         "gmf_deviance": (C.c_int, [vp, f64p, f64p]),
+        "gmf_run": (C.c_int, [vp, i32, i32, f64p, f64p]),
         "gmf_block_deviance": (C.c_int, [vp, f64p, i64]),
         "gmf_get_params": (C.c_int, [vp, vp, vp, vp, vp, i32]),
         "gmf_set_params": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -175,6 +176,17 @@ def gmf_fit(ctx, max_epochs: int, tol: float = 0.0, eval_every: int = 1):
         _check(rc)
     k = done.value // eval_every
     return rc, list(trace)[:k], done.value
+
+
+def gmf_run(ctx, epochs: int, eval_every: int = 1, trace: bool = True):
+    """(deviance trace, device completion ms of each evaluation) or (None, None)."""
+    nev = epochs // eval_every if trace else 0
+    tr = (C.c_double * max(nev, 1))() if trace else None
+    ms = (C.c_double * max(nev, 1))() if trace else None
+    _check(load_library().gmf_run(ctx, int(epochs), int(eval_every), tr, ms))
+    if not trace:
+        return None, None
+    return list(tr)[:nev], list(ms)[:nev]
 
 
 def gmf_deviance(ctx):
@@ -369,6 +381,12 @@ class GMF:
 
     def fit(self, max_epochs, tol=0.0, eval_every=1):
         return gmf_fit(self.ctx, max_epochs, tol, eval_every)
+
+    def run(self, epochs, eval_every=1, trace=True):
+        """gmf_run: epochs with the deviance overlapped every eval_every epochs."""
+        out = gmf_run(self.ctx, epochs, eval_every, trace)
+        self.stream.synchronize()
+        return out
 
     def deviance(self):
         return gmf_deviance(self.ctx)

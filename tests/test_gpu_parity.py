@@ -224,3 +224,30 @@ def test_gaussian_full_batch_reaches_truncated_svd():
     M = (P[:, :3] * np.maximum(s[:3] - 0.5, 0)) @ Qt[:3]
     assert np.linalg.norm(U @ V.T - M) / np.linalg.norm(M) < 1e-5
     g.close()
+
+
+def test_run_with_overlapped_deviance_equals_step_then_deviance():
+    """gmf_run evaluates the deviance from a snapshot on a second stream; the
+    values equal gmf_deviance after the same epochs, the iterate equals plain
+    stepping, and the device completion times increase."""
+    from synth import make_problem
+    print("[case] gmf_run vs step + deviance, Poisson 1000x500", flush=True)
+    pr = make_problem("c1")
+    g1 = gpu_for(pr)
+    g2 = gpu_for(pr)
+    tr, ms = g1.run(5, eval_every=2)
+    ref = []
+    for e in range(5):
+        g2.step(pr.R * pr.S)
+        if (e + 1) % 2 == 0:
+            ref.append(g2.deviance()[0])
+    assert len(tr) == 2 and tr == ref
+    assert 0 < ms[0] < ms[1]
+    for x, y in zip(g1.params() + tuple(g1.moments()), g2.params() + tuple(g2.moments())):
+        assert np.array_equal(x, y)
+    tr2, _ = g1.run(3, eval_every=1)            # a second call continues the fit
+    for _ in range(3):
+        g2.step(pr.R * pr.S)
+    assert tr2[-1] == g2.deviance()[0]
+    g1.close()
+    g2.close()
