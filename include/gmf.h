@@ -83,12 +83,19 @@ typedef struct gmf_config {
                            up to 16, or 32 for BF16); else 16, 32, 48 or 64
                            (BF16: 32 or 64) and >= p+q+d.  Fits run together
                            by gmf_batch_* must share it.                       */
+  int32_t tile_waves;   /* wavefronts per step tile: 4 (each takes 32 rows x 32
+                           columns of a 32-row group) or 8 (16 rows x 32
+                           columns each, half the per-wavefront work; FP32
+                           stride 16/32, BF16 32 only); 0 = automatic: 8 when
+                           available and tiles span several 32-row groups or
+                           the FP32 stride is 32, else 4                     */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
- * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0. */
+ * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0,
+ * tile_waves=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight

@@ -81,7 +81,7 @@ int dev_rows_per_wg(int nr) { return std::min(256, (nr + 31) / 32 * 32); }
 struct Plan {
   int64_t n = 0, m = 0;
   int R = 0, S = 0, p = 0, q = 0, d = 0, k = 0, KP = 0, KU = 0, KV = 0;
-  int prec = 0, fam = 0, with_w = 0;
+  int prec = 0, fam = 0, with_w = 0, nw = 4;
   std::vector<int> ro, co, ld, rpw, nrr, nct, nrows, mcols;
   std::vector<int64_t> coP;
   int64_t LDtot = 0;
@@ -104,6 +104,8 @@ constexpr int64_t kMaxTimedSteps = 8192;
 constexpr int kMaxSlots = 16;
 constexpr int kTilesPerStepTarget = 256;
 constexpr int kSumsqBlocks = 256;
+
+int panel_stride_of(const gmf_config* c);
 
 std::string check_config(const gmf_config* c) {
   if (!c) return "cfg is NULL";
@@ -131,6 +133,11 @@ std::string check_config(const gmf_config* c) {
     return "skip_block_deviance must be 0 or 1";
   if (c->tile_rows < 0 || c->tile_rows % 32 != 0 || c->tile_rows > 4096)
     return "tile_rows must be 0 or a multiple of 32 up to 4096";
+  if (c->tile_waves != 0 && c->tile_waves != 4 && c->tile_waves != 8)
+    return "tile_waves must be 0, 4 or 8";
+  if (c->tile_waves == 8 &&
+      !gmf::level_supports_nw8(c->precision, panel_stride_of(c)))
+    return "tile_waves = 8 needs panel stride 16 or 32 (FP32) or 32 (BF16)";
   if (c->panel_stride != 0) {
     const int ps = c->panel_stride;
     const bool ok = (c->precision == GMF_PREC_BF16) ? (ps == 32 || ps == 64)
@@ -190,6 +197,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.p = c->p; P.q = c->q; P.d = c->d; P.k = c->p + c->q + c->d;
   P.prec = c->precision; P.fam = c->family; P.with_w = with_w ? 1 : 0;
   P.KP = panel_stride_of(c);
+
   const int tuned_rows = c->tile_rows > 0 ? 0 : tune_lookup(c);
   P.KU = P.q + P.d; P.KV = P.p + P.d;
   P.ro.resize(P.R + 1); P.co.resize(P.S + 1);
@@ -218,6 +226,13 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
     P.nrr[r] = (nr + rpw - 1) / rpw;
   }
   P.rr_max = *std::max_element(P.nrr.begin(), P.nrr.end());
+  // 8-wavefront tiles halve each wavefront's share of a row group: they pay
+  // off when tiles hold several row groups or when the 4-wavefront FP32 tile
+  // would spill registers (stride 32); single-group tiles of small blocks are
+  // latency-bound and run faster with 4.
+  if (c->tile_waves == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) P.nw = 4;
+  else if (c->tile_waves == 8) P.nw = 8;
+  else P.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || P.rpw[0] >= 2 * gmf::kRowGroup) ? 8 : 4;
   P.ct_max = nct_max;
   P.slot_u = P.slot_v = P.slot_dev = 0; P.dev_tiles = 0;
   for (int r = 0; r < P.R; ++r)
@@ -495,7 +510,7 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
         ev = &c->events[2 * c->timed_launches];
         ++c->timed_launches;
       }
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, a, grid, c->st,
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, P.nw, a, grid, c->st,
                                 ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
   }
@@ -1172,9 +1187,9 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
       stp.t = t;
       a.steps[0] = stp;
       a.n_tile_steps = 1; a.n_upd_steps = 0;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, a, T, st));
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, P.nw, a, T, st));
       a.n_tile_steps = 0; a.n_upd_steps = 1;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, a, Q.upd_per_step, st));
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, P.nw, a, Q.upd_per_step, st));
     }
     if (dev_trace_host) {
       const int rc = proj_dev(dev_trace_host + e + 1);

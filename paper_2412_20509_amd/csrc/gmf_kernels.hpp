@@ -126,11 +126,13 @@ struct BatchArgs {
 hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_advance_cursor(int* cursor, hipStream_t s);
 
+// nw: wavefronts per tile workgroup, 4 or 8 (level_supports_nw8).
 // ev_start / ev_stop (optional): HIP events stamped at the start and end of
 // this kernel's execution.
-hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
-                        hipStream_t s, hipEvent_t ev_start = nullptr,
+hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const LevelArgs& a,
+                        int grid, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
+bool level_supports_nw8(int prec, int KP);
 
 struct DevArgs {
   const float* Y; const float* W;

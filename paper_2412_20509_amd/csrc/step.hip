@@ -56,15 +56,23 @@ template <int PREC> struct TStride { static constexpr int v = (PREC == kF32) ? 3
 template <int PREC>
 using TElem = typename std::conditional<PREC == kF32, float, __bf16>::type;
 
-template <int PREC, int KP>
+// LDS of a tile workgroup of NW wavefronts (4 or 8).  With 4, wavefront w
+// owns columns [32w, 32w+32) and both 16-row sub-tiles of every 32-row group;
+// with 8, wavefronts w and w + 4 share those columns and take sub-tile 0 and
+// 1.  gbuf[c]: the transposed D1/D2 of column group c (read by the V side);
+// with 4 wavefronts it then takes that wavefront's U sums (32 rows), with 8
+// the U sums (16 rows per wavefront) go to ubuf.
+template <int PREC, int KP, int NW>
 struct TileLds {
   static constexpr int TS = TStride<PREC>::v;
   static constexpr int T_BYTES = 2 * kWaveCols * TS * (int)sizeof(TElem<PREC>);
-  static constexpr int U_BYTES = kRowGroup * (2 * KP + 1) * 4;
-  static constexpr int WB = (T_BYTES > U_BYTES ? T_BYTES : U_BYTES);
+  static constexpr int U_ROWS = kRowGroup * 4 / NW;
+  static constexpr int U_BYTES = U_ROWS * (2 * KP + 1) * 4;
+  static constexpr int GB = (NW == 4 && U_BYTES > T_BYTES) ? U_BYTES : T_BYTES;
   float sP[kRowGroup][KP + 4];
-  alignas(16) char wave_buf[kTileWaves][WB];   // per wavefront: transpose, then U sums
-  double sDev[kTileWaves];
+  alignas(16) char gbuf[4][GB];
+  alignas(16) char ubuf[NW == 8 ? NW : 1][NW == 8 ? U_BYTES : 4];
+  double sDev[NW];
   unsigned long long task;
   int flags[4];
 };
@@ -83,20 +91,27 @@ struct TileView {
   bool row_only;                   // skip the column-side (V) sums
 };
 
-template <int PREC, int FAM, int KP, bool WANT_DEV>
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
 __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p, int q, int d,
-                               int KU, int KV, TileLds<PREC, KP>& L) {
+                               int KU, int KV, TileLds<PREC, KP, NW>& L) {
   constexpr int NB = KP / 16;
   constexpr int TS = TStride<PREC>::v;
+  constexpr int NT = kWave * NW;          // threads
+  constexpr int NR = (NW == 8) ? 1 : 2;   // 16-row sub-tiles per wavefront
+  constexpr int NC = (NW == 8) ? 1 : 2;   // 16-column halves per wavefront on the V side
   using TE = TElem<PREC>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int cg = wave & 3;                 // column group
+  const int R0 = (NW == 8) ? (wave >> 2) : 0;
   const int l16 = lane & 15;
   const int g = lane >> 4;
-  const int colw = tv.col0 + wave * kWaveCols;
-  TE (*sT)[kWaveCols][TS] = reinterpret_cast<TE (*)[kWaveCols][TS]>(L.wave_buf[wave]);
-  float (*sUw)[2 * KP + 1] = reinterpret_cast<float (*)[2 * KP + 1]>(L.wave_buf[wave]);
+  const int colw = tv.col0 + cg * kWaveCols;
+  TE (*sT)[kWaveCols][TS] = reinterpret_cast<TE (*)[kWaveCols][TS]>(L.gbuf[cg]);
+  float (*sUw)[2 * KP + 1] = (NW == 8)
+      ? reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? wave : 0])
+      : reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[cg]);
   const bool has_w = tv.W != nullptr;
 
   // ---- column-panel operands of this wavefront (fixed over the tile)
@@ -146,29 +161,29 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
   }
 
-  floatx4 vacc[2][NB][2];
-  for (int c = 0; c < 2; ++c)
+  floatx4 vacc[NC][NB][2];
+  for (int c = 0; c < NC; ++c)
     for (int ob = 0; ob < NB; ++ob)
       for (int h = 0; h < 2; ++h) vacc[c][ob][h] = floatx4{0.f, 0.f, 0.f, 0.f};
   double dev_acc = 0.0;
 
   // Y of a row group: lane reads rows rg + 2 l16 + R, cols colw + 16C + 4g .. +3
-  auto load_y = [&](int rg, float4 (&y)[2][2]) {
-    for (int R = 0; R < 2; ++R) {
-      const int row = rg + 2 * l16 + R;
+  auto load_y = [&](int rg, float4 (&y)[NR][2]) {
+    for (int rr = 0; rr < NR; ++rr) {
+      const int row = rg + 2 * l16 + R0 + rr;
       for (int C = 0; C < 2; ++C) {
         const int colb = colw + 16 * C + 4 * g;
-        y[R][C] = make_float4(0.f, 0.f, 0.f, 0.f);
+        y[rr][C] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (row < tv.row_end && colb < tv.ldy)
-          y[R][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
+          y[rr][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
       }
     }
   };
   // row-panel rows of a group, float4 granules spread over the workgroup
-  constexpr int PF = (kRowGroup * (KP / 4) + kTileThreads - 1) / kTileThreads;
+  constexpr int PF = (kRowGroup * (KP / 4) + NT - 1) / NT;
   auto load_p = [&](int rg, float4 (&pf)[PF]) {
     for (int u = 0; u < PF; ++u) {
-      const int idx = tid + u * kTileThreads;
+      const int idx = tid + u * NT;
       pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (idx < kRowGroup * (KP / 4)) {
         const int r = idx / (KP / 4), c4 = idx % (KP / 4);
@@ -177,7 +192,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       }
     }
   };
-  float4 ynext[2][2];
+  float4 ynext[NR][2];
   float4 pnext[PF];
   load_p(tv.row0, pnext);
   load_y(tv.row0, ynext);
@@ -190,12 +205,12 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   }
 
   for (int rg = tv.row0; rg < tv.row_end; rg += kRowGroup) {
-    float4 ycur[2][2];
-    for (int R = 0; R < 2; ++R)
-      for (int C = 0; C < 2; ++C) ycur[R][C] = ynext[R][C];
-    __syncthreads();   // previous group's readers of sP and of the wave buffers are done
+    float4 ycur[NR][2];
+    for (int rr = 0; rr < NR; ++rr)
+      for (int C = 0; C < 2; ++C) ycur[rr][C] = ynext[rr][C];
+    __syncthreads();   // previous group's readers of sP and of the buffers are done
     for (int u = 0; u < PF; ++u) {
-      const int idx = tid + u * kTileThreads;
+      const int idx = tid + u * NT;
       if (idx < kRowGroup * (KP / 4))
         *reinterpret_cast<float4*>(&L.sP[idx / (KP / 4)][4 * (idx % (KP / 4))]) = pnext[u];
     }
@@ -207,8 +222,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     float dev_grp = 0.f;
 
     // ---- per 16-row sub-tile R: eta, epilogue, transpose store, U-side sums
-    floatx4 ug[2][NB], uh[2][NB];
-    for (int R = 0; R < 2; ++R) {
+    floatx4 ug[NR][NB], uh[NR][NB];
+    for (int rr = 0; rr < NR; ++rr) {
+      const int R = R0 + rr;
       const int lrow = 2 * l16 + R;
       const int row = rg + lrow;
       const bool row_ok = row < tv.row_end;
@@ -228,7 +244,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
         if (has_w && row_ok && colb < tv.ldy)
           w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)row * tv.ldy + colb);
-        const float ys[4] = {ycur[R][C].x, ycur[R][C].y, ycur[R][C].z, ycur[R][C].w};
+        const float ys[4] = {ycur[rr][C].x, ycur[rr][C].y, ycur[rr][C].z, ycur[rr][C].w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
         for (int v = 0; v < 4; ++v) {
           float x1, x2, dv = 0.f;
@@ -249,15 +265,15 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           }
       // U side: G_U[row][o] = sum over this wavefront's cols of D1[row][col] P[col][o]
       for (int ob = 0; ob < NB; ++ob) {
-        ug[R][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
-        uh[R][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
+        ug[rr][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
+        uh[rr][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
       if constexpr (PREC == kF32) {
         for (int C = 0; C < 2; ++C)
           for (int v = 0; v < 4; ++v)
             for (int ob = 0; ob < NB; ++ob) {
-              ug[R][ob] = mfma_f32(d1[C][v], ub32[C][v][ob], ug[R][ob]);
-              uh[R][ob] = mfma_f32(d2[C][v], ub32q[C][v][ob], uh[R][ob]);
+              ug[rr][ob] = mfma_f32(d1[C][v], ub32[C][v][ob], ug[rr][ob]);
+              uh[rr][ob] = mfma_f32(d2[C][v], ub32q[C][v][ob], uh[rr][ob]);
             }
       } else {
         const bf16x8 b1 = to_bf16(floatx8{d1[0][0], d1[0][1], d1[0][2], d1[0][3],
@@ -265,17 +281,18 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         const bf16x8 b2 = to_bf16(floatx8{d2[0][0], d2[0][1], d2[0][2], d2[0][3],
                                           d2[1][0], d2[1][1], d2[1][2], d2[1][3]});
         for (int ob = 0; ob < NB; ++ob) {
-          ug[R][ob] = mfma_bf16(b1, ub16[ob], ug[R][ob]);
-          uh[R][ob] = mfma_bf16(b2, ub16q[ob], uh[R][ob]);
+          ug[rr][ob] = mfma_bf16(b1, ub16[ob], ug[rr][ob]);
+          uh[rr][ob] = mfma_bf16(b2, ub16q[ob], uh[rr][ob]);
         }
       }
     }
-    __syncthreads();
+    __syncthreads();   // the column group's transposed rows are complete
 
     if constexpr (WANT_DEV) dev_acc += (double)dev_grp;
     if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
-    for (int C = 0; C < 2 && !tv.row_only; ++C) {
+    for (int cc = 0; cc < NC && !tv.row_only; ++cc) {
+      const int C = (NW == 8) ? R0 : cc;
       if constexpr (PREC == kF32) {
         const float4 ta = *reinterpret_cast<const float4*>(&sT[0][16 * C + l16][8 * g]);
         const float4 tb = *reinterpret_cast<const float4*>(&sT[0][16 * C + l16][8 * g + 4]);
@@ -286,8 +303,8 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         for (int s = 0; s < 8; ++s)
           for (int ob = 0; ob < NB; ++ob) {
             const float pb = L.sP[8 * g + s][16 * ob + l16];
-            vacc[C][ob][0] = mfma_f32(t1[s], pb, vacc[C][ob][0]);
-            vacc[C][ob][1] = mfma_f32(t2[s], pb * pb, vacc[C][ob][1]);
+            vacc[cc][ob][0] = mfma_f32(t1[s], pb, vacc[cc][ob][0]);
+            vacc[cc][ob][1] = mfma_f32(t2[s], pb * pb, vacc[cc][ob][1]);
           }
       } else {
         const bf16x8 t1 = *reinterpret_cast<const bf16x8*>(&sT[0][16 * C + l16][8 * g]);
@@ -296,30 +313,35 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           float xs[8];
           for (int u = 0; u < 8; ++u) xs[u] = L.sP[8 * g + u][16 * ob + l16];
           const floatx8 x = {xs[0], xs[1], xs[2], xs[3], xs[4], xs[5], xs[6], xs[7]};
-          vacc[C][ob][0] = mfma_bf16(t1, to_bf16(x), vacc[C][ob][0]);
-          vacc[C][ob][1] = mfma_bf16(t2, to_bf16(x * x), vacc[C][ob][1]);
+          vacc[cc][ob][0] = mfma_bf16(t1, to_bf16(x), vacc[cc][ob][0]);
+          vacc[cc][ob][1] = mfma_bf16(t2, to_bf16(x * x), vacc[cc][ob][1]);
         }
       }
     }
-    // the wave buffer now takes the U sums: rows 2(4g+v)+R of the group, output 16ob+l16
-    for (int R = 0; R < 2; ++R)
+    // U sums to LDS: row 4g+v of the wavefront's sub-tile rr (group row 2(4g+v)+R)
+    for (int rr = 0; rr < NR; ++rr)
       for (int ob = 0; ob < NB; ++ob)
         for (int v = 0; v < 4; ++v) {
-          sUw[2 * (4 * g + v) + R][16 * ob + l16] = ug[R][ob][v];
-          sUw[2 * (4 * g + v) + R][KP + 16 * ob + l16] = uh[R][ob][v];
+          const int ur = (NW == 8) ? (4 * g + v) : (2 * (4 * g + v) + rr);
+          sUw[ur][16 * ob + l16] = ug[rr][ob][v];
+          sUw[ur][KP + 16 * ob + l16] = uh[rr][ob][v];
         }
     __syncthreads();
 
-    // ---- sum over the 4 wavefronts (fixed order) and store the strip partial
-    for (int idx = tid; idx < kRowGroup * 2 * KU; idx += kTileThreads) {
+    // ---- sum over the 4 column groups (fixed order) and store the strip partial
+    for (int idx = tid; idx < kRowGroup * 2 * KU; idx += NT) {
       const int r = idx / (2 * KU);
       const int oo = idx % (2 * KU);
       const int row = rg + r;
       if (row < tv.row_end) {
         const int src = (oo < KU) ? (p + oo) : (KP + p + (oo - KU));
         float s = 0.f;
-        for (int w = 0; w < kTileWaves; ++w)
-          s += reinterpret_cast<float (*)[2 * KP + 1]>(L.wave_buf[w])[r][src];
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (NW == 8)
+            s += reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? c + 4 * (r & 1) : 0])[r >> 1][src];
+          else
+            s += reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[c])[r][src];
+        }
         tv.Upart[(int64_t)row * (2 * KU) + oo] = s;
       }
     }
@@ -327,7 +349,8 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
 
   if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
   // ---- V-side partial of this row range
-  for (int C = 0; C < 2 && !tv.row_only; ++C)
+  for (int cc = 0; cc < NC && !tv.row_only; ++cc) {
+    const int C = (NW == 8) ? R0 : cc;
     for (int v = 0; v < 4; ++v) {
       const int col = colw + 16 * C + 4 * g + v;
       if (col < tv.m_b) {
@@ -338,12 +361,13 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           if (o < p) oo = o;
           else if (o >= p + q && o < p + q + d) oo = o - q;
           if (oo >= 0) {
-            dst[oo] = vacc[C][ob][0][v];
-            dst[KV + oo] = vacc[C][ob][1][v];
+            dst[oo] = vacc[cc][ob][0][v];
+            dst[KV + oo] = vacc[cc][ob][1][v];
           }
         }
       }
     }
+  }
 
   // ---- tile deviance (fixed reduction tree), result valid in thread 0
   double total = 0.0;
@@ -352,6 +376,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     if (lane == 0) L.sDev[wave] = dev_acc;
     __syncthreads();
     total = ((L.sDev[0] + L.sDev[1]) + L.sDev[2]) + L.sDev[3];
+    if constexpr (NW == 8) total += ((L.sDev[4] + L.sDev[5]) + L.sDev[6]) + L.sDev[7];
   }
   return total;
 }
@@ -459,18 +484,18 @@ __device__ void sum_block_deviance(const LevelArgs& a, const LevelStep& st, doub
 }
 
 // ------------------------------------------------------------- kernel -----
-template <int PREC, int KP>
+template <int PREC, int KP, int NW>
 union LevelLds {
-  TileLds<PREC, KP> tile;
-  double sums[kTileThreads];
+  TileLds<PREC, KP, NW> tile;
+  double sums[kWave * NW];
 };
 
 // One task of a level launch: tile `local` of step `st` (tile_task) or update
 // workgroup `local` of step `st`.  Returns the task kind (0 tile, 1 row
 // update, 2 column update, 3 block deviance, -1 nothing to do).
-template <int PREC, int FAM, int KP, bool WANT_DEV>
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
 __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st, bool tile_task,
-                                        int local, LevelLds<PREC, KP>& L,
+                                        int local, LevelLds<PREC, KP, NW>& L,
                                         unsigned long long* stamps) {
   if (tile_task) {
     const int n_b = st.n_b, m_b = st.m_b;
@@ -493,7 +518,7 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     tv.stamps = stamps;
     tv.row_only = a.row_only != 0;
     const FamilyConst fc = family_const(a.f);
-    const double dev = compute_tile<PREC, FAM, KP, WANT_DEV>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
+    const double dev = compute_tile<PREC, FAM, KP, WANT_DEV, NW>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
     if (WANT_DEV && threadIdx.x == 0)
       a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
     return 0;
@@ -517,9 +542,9 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
   return -1;
 }
 
-template <int PREC, int FAM, int KP, bool WANT_DEV>
-__global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
-  __shared__ LevelLds<PREC, KP> L;
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
+__global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : 2) void level_kernel(LevelArgs a) {
+  __shared__ LevelLds<PREC, KP, NW> L;
   const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
   __shared__ unsigned long long stamps[3];
   const int T = a.rr_max * a.ct_max;
@@ -527,14 +552,14 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
   int b = blockIdx.x;
   int kind;
   if (b < ntile_blocks) {
-    kind = run_task<PREC, FAM, KP, WANT_DEV>(a, a.steps[b / T], true, b % T, L,
-                                             a.trace ? stamps : nullptr);
+    kind = run_task<PREC, FAM, KP, WANT_DEV, NW>(a, a.steps[b / T], true, b % T, L,
+                                                 a.trace ? stamps : nullptr);
   } else {
     b -= ntile_blocks;
     const int k = b / a.upd_per_step;
     if (k >= a.n_upd_steps) return;
-    kind = run_task<PREC, FAM, KP, WANT_DEV>(a, a.steps[a.n_tile_steps + k], false,
-                                             b % a.upd_per_step, L, nullptr);
+    kind = run_task<PREC, FAM, KP, WANT_DEV, NW>(a, a.steps[a.n_tile_steps + k], false,
+                                                 b % a.upd_per_step, L, nullptr);
   }
   if (kind < 0) return;
   if (a.trace && threadIdx.x == 0) {
@@ -559,7 +584,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void level_kernel(LevelArgs a) {
 // fit's family chosen at run time (uniform over the workgroup).
 template <int PREC, int KP>
 __global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
-  __shared__ LevelLds<PREC, KP> L;
+  __shared__ LevelLds<PREC, KP, 4> L;
   const int b = blockIdx.x;
   int lo = 0, hi = ba.nsegs - 1;
   while (lo < hi) {   // last segment with start <= b
@@ -573,9 +598,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
   const bool tile_task = sg.kind == 0;
   const int local = b - sg.start;
   switch (a.fam) {
-    case kPoisson: run_task<PREC, kPoisson, KP, false>(a, st, tile_task, local, L, nullptr); break;
-    case kNegBin: run_task<PREC, kNegBin, KP, false>(a, st, tile_task, local, L, nullptr); break;
-    default: run_task<PREC, kGaussian, KP, false>(a, st, tile_task, local, L, nullptr); break;
+    case kPoisson: run_task<PREC, kPoisson, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
+    case kNegBin: run_task<PREC, kNegBin, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
+    default: run_task<PREC, kGaussian, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
   }
 }
 
@@ -584,49 +609,66 @@ __global__ void advance_cursor_kernel(int* cursor) {
 }
 
 // ------------------------------------------------------------ launchers ----
+// 8-wavefront tiles exist for the panel strides whose LDS still lets two
+// workgroups share a compute unit (FP32 16 and 32, BF16 32).
+template <int PREC, int KP>
+constexpr bool has_nw8() {
+  return (PREC == kF32 && (KP == 16 || KP == 32)) || (PREC == kBF16 && KP == 32);
+}
+
 template <int PREC, int FAM, int KP>
-static const void* kernel_ptr(bool want_dev) {
-  return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true>)
-                  : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false>);
+static const void* kernel_ptr(bool want_dev, int nw) {
+  if constexpr (has_nw8<PREC, KP>())
+    if (nw == 8)
+      return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 8>)
+                      : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 8>);
+  if (nw != 4) return nullptr;
+  return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 4>)
+                  : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 4>);
 }
 
 template <int PREC, int FAM>
-static const void* kernel_ptr_kp(int KP, bool want_dev) {
+static const void* kernel_ptr_kp(int KP, bool want_dev, int nw) {
   switch (KP) {
-    case 16: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 16>(want_dev); else break;
-    case 32: return kernel_ptr<PREC, FAM, 32>(want_dev);
-    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(want_dev); else break;
-    case 64: return kernel_ptr<PREC, FAM, 64>(want_dev);
+    case 16: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 16>(want_dev, nw); else break;
+    case 32: return kernel_ptr<PREC, FAM, 32>(want_dev, nw);
+    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(want_dev, nw); else break;
+    case 64: return kernel_ptr<PREC, FAM, 64>(want_dev, nw);
   }
   return nullptr;
 }
 
-static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev) {
+static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev, int nw) {
   if (prec == kF32) {
     switch (fam) {
-      case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev);
-      case kNegBin: return kernel_ptr_kp<kF32, kNegBin>(KP, want_dev);
-      case kGaussian: return kernel_ptr_kp<kF32, kGaussian>(KP, want_dev);
+      case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev, nw);
+      case kNegBin: return kernel_ptr_kp<kF32, kNegBin>(KP, want_dev, nw);
+      case kGaussian: return kernel_ptr_kp<kF32, kGaussian>(KP, want_dev, nw);
     }
   } else {
     switch (fam) {
-      case kPoisson: return kernel_ptr_kp<kBF16, kPoisson>(KP, want_dev);
-      case kNegBin: return kernel_ptr_kp<kBF16, kNegBin>(KP, want_dev);
-      case kGaussian: return kernel_ptr_kp<kBF16, kGaussian>(KP, want_dev);
+      case kPoisson: return kernel_ptr_kp<kBF16, kPoisson>(KP, want_dev, nw);
+      case kNegBin: return kernel_ptr_kp<kBF16, kNegBin>(KP, want_dev, nw);
+      case kGaussian: return kernel_ptr_kp<kBF16, kGaussian>(KP, want_dev, nw);
     }
   }
   return nullptr;
 }
 
-hipError_t launch_level(int prec, int fam, int KP, bool want_dev, const LevelArgs& a, int grid,
-                        hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const void* k = level_kernel_for(prec, fam, KP, want_dev);
+bool level_supports_nw8(int prec, int KP) {
+  return (prec == kF32 && (KP == 16 || KP == 32)) || (prec == kBF16 && KP == 32);
+}
+
+hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const LevelArgs& a,
+                        int grid, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const void* k = level_kernel_for(prec, fam, KP, want_dev, nw);
   if (!k) return hipErrorInvalidValue;
   if (grid <= 0) return hipSuccess;
   void* args[] = {const_cast<LevelArgs*>(&a)};
+  const dim3 block(kWave * nw);
   if (ev_start || ev_stop)   // events stamped by the dispatch itself: kernel execution time only
-    return hipExtLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s, ev_start, ev_stop, 0);
-  return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, s);
+    return hipExtLaunchKernel(k, dim3(grid), block, args, 0, s, ev_start, ev_stop, 0);
+  return hipLaunchKernel(k, dim3(grid), block, args, 0, s);
 }
 
 hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s) {

@@ -42,7 +42,7 @@ class gmf_config(C.Structure):
         ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
         ("seed", C.c_uint64),
         ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
-        ("panel_stride", C.c_int32),
+        ("panel_stride", C.c_int32), ("tile_waves", C.c_int32),
     ]
 
 
@@ -312,6 +312,7 @@ class FitConfig:
     tile_rows: int = 0
     skip_block_deviance: int = 0
     panel_stride: int = 0
+    tile_waves: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -331,6 +332,7 @@ class FitConfig:
         c.tile_rows = self.tile_rows
         c.skip_block_deviance = self.skip_block_deviance
         c.panel_stride = self.panel_stride
+        c.tile_waves = self.tile_waves
         return c
 
 

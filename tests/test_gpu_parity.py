@@ -251,3 +251,24 @@ def test_run_with_overlapped_deviance_equals_step_then_deviance():
     assert tr2[-1] == g2.deviance()[0]
     g1.close()
     g2.close()
+
+
+@pytest.mark.parametrize("precision,d", [("fp32", 10), ("fp32", 20), ("bf16", 10)])
+def test_eight_wave_tiles_equal_four_wave_tiles(precision, d):
+    """The 8-wavefront tile splits each 32-row group between two wavefronts
+    but keeps every product and sum of the step in the same order: the
+    iterates are bit-identical to the 4-wavefront tile's.  The block deviance
+    (a monitor) sums each lane's entries in float32 before float64, over 8
+    instead of 16 entries, so it agrees to float32 rounding only."""
+    print(f"[case] tile waves 4 vs 8, {precision} d={d}", flush=True)
+    pr = gen_nb(n=2600, m=900, d=d, R=4, S=3, seed=1500 + d)
+    g4 = gpu_for(pr, precision=precision, tile_waves=4)
+    g8 = gpu_for(pr, precision=precision, tile_waves=8)
+    g4.step(20)
+    g8.step(20)
+    for x, y in zip(g4.params() + tuple(g4.moments()), g8.params() + tuple(g8.moments())):
+        assert np.array_equal(x, y)
+    b4, b8 = g4.block_deviance(20), g8.block_deviance(20)
+    assert np.max(np.abs(b4 - b8) / np.abs(b4)) < 1e-6
+    g4.close()
+    g8.close()
