@@ -95,7 +95,7 @@ struct Plan {
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
       o_scal, o_sumsq, o_post, o_firstnz, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
       o_ld, o_nct, o_coP, o_snap, o_devpart2, o_evring, total;
-  int row_chunk = 1, col_chunk = 1, upd_per_step = 1;
+  int row_chunk = 1, col_chunk = 1, upd_sub = 1, upd_per_step = 1;
 };
 
 constexpr int kDevRing = 4096;
@@ -103,6 +103,7 @@ constexpr int kEvRing = 256;   // gmf_run evaluation results held on the device
 constexpr int64_t kMaxTimedSteps = 8192;
 constexpr int kMaxSlots = 16;
 constexpr int kTilesPerStepTarget = 256;
+constexpr int kUpdPerTile = 4;   // update workgroups per tile workgroup, at most about
 constexpr int kSumsqBlocks = 256;
 
 int panel_stride_of(const gmf_config* c);
@@ -190,6 +191,14 @@ int tune_lookup(const gmf_config* c) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(c));
   return it == g_tune.end() ? 0 : it->second.tile_rows;
+}
+
+// Update workgroups of one step: row part, column part (none for row-only
+// projection steps) and the block-deviance workgroup.
+int upd_workgroups(int n_b, int m_b, int row_chunk, int col_chunk, int sub, bool row_only) {
+  const int rw = ((n_b + row_chunk - 1) / row_chunk + sub - 1) / sub;
+  const int cw = row_only ? 0 : ((m_b + col_chunk - 1) / col_chunk + sub - 1) / sub;
+  return rw + cw + 1;
 }
 
 void make_plan(const gmf_config* c, int with_w, Plan& P) {
@@ -307,11 +316,23 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_coP = take(sizeof(int64_t) * (P.S + 1));
   P.row_chunk = std::max(1, gmf::kTileThreads / (2 * P.KU));
   P.col_chunk = std::max(1, gmf::kTileThreads / (2 * P.KV));
+  // chunks per update workgroup: at most about four update workgroups per
+  // step per tile workgroup (a workgroup's chunks run one after another, so
+  // fewer, longer update workgroups trade start-up cost for latency)
+  {
+    int chunks = 1;
+    for (int r = 0; r < P.R; ++r)
+      for (int s = 0; s < P.S; ++s)
+        chunks = std::max(chunks, (P.nrows[r] + P.row_chunk - 1) / P.row_chunk +
+                                      (P.mcols[s] + P.col_chunk - 1) / P.col_chunk);
+    const int per = kUpdPerTile * P.rr_max * P.ct_max;
+    P.upd_sub = std::max(1, (chunks + per - 1) / per);
+  }
   P.upd_per_step = 1;
   for (int r = 0; r < P.R; ++r)
     for (int s = 0; s < P.S; ++s)
-      P.upd_per_step = std::max(P.upd_per_step, (P.nrows[r] + P.row_chunk - 1) / P.row_chunk +
-                                                    (P.mcols[s] + P.col_chunk - 1) / P.col_chunk + 1);
+      P.upd_per_step = std::max(P.upd_per_step, upd_workgroups(P.nrows[r], P.mcols[s], P.row_chunk,
+                                                              P.col_chunk, P.upd_sub, false));
   P.total = o;
 }
 
@@ -418,6 +439,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   a.slot_dev_elems = P.slot_dev;
   a.row_chunk = P.row_chunk;
   a.col_chunk = P.col_chunk;
+  a.upd_sub = P.upd_sub;
   a.upd_per_step = P.upd_per_step;
   a.f = family_args(cf);
   a.fam = P.fam;
@@ -935,7 +957,7 @@ namespace {
 
 struct ProjPlan {
   int64_t n_new = 0;
-  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_per_step = 0;
+  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_sub = 1, upd_per_step = 0;
   int64_t slot_u = 0;
   size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
@@ -954,7 +976,12 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.dev_tiles = 0;
   for (int s = 0; s < P.S; ++s) Q.dev_tiles += (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];
   Q.slot_u = ((int64_t)P.ct_max * n_new * 2 * P.KU + 63) / 64 * 64;
-  Q.upd_per_step = (int)((n_new + P.row_chunk - 1) / P.row_chunk) + 1;
+  {
+    const int64_t chunks = (n_new + P.row_chunk - 1) / P.row_chunk;
+    const int64_t per = (int64_t)kUpdPerTile * Q.nrr * P.ct_max;
+    Q.upd_sub = (int)std::max<int64_t>(1, (chunks + per - 1) / per);
+    Q.upd_per_step = upd_workgroups((int)n_new, 0, P.row_chunk, P.col_chunk, Q.upd_sub, true);
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   Q.o_Yb = take(sizeof(float) * (size_t)n_new * P.LDtot);
@@ -1170,6 +1197,7 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
   a.devpart = reinterpret_cast<double*>(at(Q.o_devpart));
   a.slot_u_elems = Q.slot_u; a.slot_v_elems = 0; a.slot_dev_elems = 0;
   a.rr_max = Q.nrr;
+  a.upd_sub = Q.upd_sub;
   a.upd_per_step = Q.upd_per_step;
   a.row_only = 1;
   a.trace = nullptr;

@@ -81,7 +81,9 @@ struct LevelArgs {
   float* Upart; float* Vpart; double* devpart;
   int64_t slot_u_elems, slot_v_elems, slot_dev_elems;
   // update work split
-  int row_chunk, col_chunk, upd_per_step;
+  // update work split: an update workgroup walks upd_sub chunks of row_chunk
+  // rows (or col_chunk columns); upd_per_step workgroups cover a step
+  int row_chunk, col_chunk, upd_sub, upd_per_step;
   // numerics
   FamilyArgs f;
   int fam;             // family (read by the batched kernel; the others take it as a template)

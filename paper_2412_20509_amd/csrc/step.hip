@@ -525,17 +525,27 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
   }
   int u = local;
   const int n_b = st.n_b, m_b = st.m_b;
-  const int nrc = (n_b + a.row_chunk - 1) / a.row_chunk;
-  const int ncc = a.row_only ? 0 : (m_b + a.col_chunk - 1) / a.col_chunk;
-  if (u < nrc) {
-    update_rows(a, st, u * a.row_chunk, min(n_b, (u + 1) * a.row_chunk), L.sums);
+  const int sub = a.upd_sub;
+  const int rspan = a.row_chunk * sub, cspan = a.col_chunk * sub;
+  const int nrw = (n_b + rspan - 1) / rspan;
+  const int ncw = a.row_only ? 0 : (m_b + cspan - 1) / cspan;
+  if (u < nrw) {
+    const int end = min(n_b, (u + 1) * rspan);
+    for (int r0 = u * rspan; r0 < end; r0 += a.row_chunk) {
+      update_rows(a, st, r0, min(end, r0 + a.row_chunk), L.sums);
+      __syncthreads();   // sums is reused by the next chunk
+    }
     return 1;
   }
-  if ((u -= nrc) < ncc) {
-    update_cols(a, st, u * a.col_chunk, min(m_b, (u + 1) * a.col_chunk), L.sums);
+  if ((u -= nrw) < ncw) {
+    const int end = min(m_b, (u + 1) * cspan);
+    for (int c0 = u * cspan; c0 < end; c0 += a.col_chunk) {
+      update_cols(a, st, c0, min(end, c0 + a.col_chunk), L.sums);
+      __syncthreads();
+    }
     return 2;
   }
-  if (u == ncc) {
+  if (u == ncw) {
     if (WANT_DEV) sum_block_deviance(a, st, L.sums);
     return 3;
   }
