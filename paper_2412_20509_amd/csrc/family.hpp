@@ -89,7 +89,7 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
     d2 = wp;
     if constexpr (WANT_DEV) dev = w * r * r;
   } else {
-    const float ec = fminf(fmaxf(eta, c.lo), c.hi);
+    const float ec = __builtin_amdgcn_fmed3f(eta, c.lo, c.hi);   // clamp to [lo, hi]
     const float mu = fast_exp(ec);
     if constexpr (FAM == kPoisson) {
       const float wp = w * c.phi_inv;

@@ -42,6 +42,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
@@ -70,6 +71,11 @@ struct TileLds {
   static constexpr int U_BYTES = U_ROWS * (2 * KP + 1) * 4;
   static constexpr int GB = (NW == 4 && U_BYTES > T_BYTES) ? U_BYTES : T_BYTES;
   float sP[kRowGroup][KP + 4];
+  // bfloat16 copies of the group's row panel, converted once per group:
+  // row-major (eta operand) and transposed, plain and squared (V-side operand)
+  static constexpr int PB = (PREC == kBF16) ? 1 : 0;
+  alignas(16) __bf16 sPb[PB ? kRowGroup : 1][PB ? KP + 8 : 8];
+  alignas(16) __bf16 sPT[PB ? 2 : 1][PB ? KP : 1][PB ? kRowGroup + 8 : 8];
   alignas(16) char gbuf[4][GB];
   alignas(16) char ubuf[NW == 8 ? NW : 1][NW == 8 ? U_BYTES : 4];
   double sDev[NW];
@@ -91,7 +97,7 @@ struct TileView {
   bool row_only;                   // skip the column-side (V) sums
 };
 
-template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool HAS_W>
 __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p, int q, int d,
                                int KU, int KV, TileLds<PREC, KP, NW>& L) {
   constexpr int NB = KP / 16;
@@ -112,8 +118,6 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   float (*sUw)[2 * KP + 1] = (NW == 8)
       ? reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? wave : 0])
       : reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[cg]);
-  const bool has_w = tv.W != nullptr;
-
   // ---- column-panel operands of this wavefront (fixed over the tile)
   float pa32[2][(PREC == kF32) ? KP / 4 : 1];
   bf16x8 pa16[2][(PREC == kBF16) ? KP / 32 : 1];
@@ -211,8 +215,20 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     __syncthreads();   // previous group's readers of sP and of the buffers are done
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * NT;
-      if (idx < kRowGroup * (KP / 4))
-        *reinterpret_cast<float4*>(&L.sP[idx / (KP / 4)][4 * (idx % (KP / 4))]) = pnext[u];
+      if (idx < kRowGroup * (KP / 4)) {
+        const int r = idx / (KP / 4), c0 = 4 * (idx % (KP / 4));
+        *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
+        if constexpr (PREC == kBF16) {
+          const floatx4 x = {pnext[u].x, pnext[u].y, pnext[u].z, pnext[u].w};
+          const bf16x4 xb = __builtin_convertvector(x, bf16x4);
+          const bf16x4 xq = __builtin_convertvector(x * x, bf16x4);
+          *reinterpret_cast<bf16x4*>(&L.sPb[r][c0]) = xb;
+          for (int i = 0; i < 4; ++i) {
+            L.sPT[0][c0 + i][r] = xb[i];
+            L.sPT[1][c0 + i][r] = xq[i];
+          }
+        }
+      }
     }
     if (rg + kRowGroup < tv.row_end) {   // prefetch the next group
       load_p(rg + kRowGroup, pnext);
@@ -234,25 +250,24 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         if constexpr (PREC == kF32) {
           for (int kk = 0; kk < KP / 4; ++kk) e = mfma_f32(pa32[C][kk], L.sP[lrow][4 * kk + g], e);
         } else {
-          for (int kk = 0; kk < KP / 32; ++kk) {
-            const float4 a = *reinterpret_cast<const float4*>(&L.sP[lrow][32 * kk + 8 * g]);
-            const float4 b = *reinterpret_cast<const float4*>(&L.sP[lrow][32 * kk + 8 * g + 4]);
-            e = mfma_bf16(pa16[C][kk], to_bf16(floatx8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}), e);
-          }
+          for (int kk = 0; kk < KP / 32; ++kk)
+            e = mfma_bf16(pa16[C][kk], *reinterpret_cast<const bf16x8*>(&L.sPb[lrow][32 * kk + 8 * g]), e);
         }
         const int colb = colw + 16 * C + 4 * g;
-        float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (has_w && row_ok && colb < tv.ldy)
-          w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)row * tv.ldy + colb);
+        float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);   // a literal 1 without weights
+        if constexpr (HAS_W)
+          if (row_ok && colb < tv.ldy)
+            w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)row * tv.ldy + colb);
         const float ys[4] = {ycur[rr][C].x, ycur[rr][C].y, ycur[rr][C].z, ycur[rr][C].w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        // Entries outside the block (rows past the tile end, padded columns)
+        // need no masking in D1/D2: every contraction meets them with a zero
+        // operand (zero-filled panel rows, zero column operands), and their
+        // eta, mu, D1, D2 are finite.  Only the deviance sum is masked.
         for (int v = 0; v < 4; ++v) {
-          float x1, x2, dv = 0.f;
-          family_entry<FAM, WANT_DEV>(e[v], ys[v], ws[v], fc, x1, x2, dv);
-          const bool ok = row_ok && (colb + v < tv.m_b);
-          d1[C][v] = ok ? x1 : 0.f;
-          d2[C][v] = ok ? x2 : 0.f;
-          if constexpr (WANT_DEV) dev_grp += ok ? dv : 0.f;
+          float dv = 0.f;
+          family_entry<FAM, WANT_DEV>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+          if constexpr (WANT_DEV) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
         }
       }
       // transposed copies for the V side: sT[h][col][row]
@@ -310,11 +325,10 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         const bf16x8 t1 = *reinterpret_cast<const bf16x8*>(&sT[0][16 * C + l16][8 * g]);
         const bf16x8 t2 = *reinterpret_cast<const bf16x8*>(&sT[1][16 * C + l16][8 * g]);
         for (int ob = 0; ob < NB; ++ob) {
-          float xs[8];
-          for (int u = 0; u < 8; ++u) xs[u] = L.sP[8 * g + u][16 * ob + l16];
-          const floatx8 x = {xs[0], xs[1], xs[2], xs[3], xs[4], xs[5], xs[6], xs[7]};
-          vacc[cc][ob][0] = mfma_bf16(t1, to_bf16(x), vacc[cc][ob][0]);
-          vacc[cc][ob][1] = mfma_bf16(t2, to_bf16(x * x), vacc[cc][ob][1]);
+          const bf16x8 xb = *reinterpret_cast<const bf16x8*>(&L.sPT[0][16 * ob + l16][8 * g]);
+          const bf16x8 xq = *reinterpret_cast<const bf16x8*>(&L.sPT[1][16 * ob + l16][8 * g]);
+          vacc[cc][ob][0] = mfma_bf16(t1, xb, vacc[cc][ob][0]);
+          vacc[cc][ob][1] = mfma_bf16(t2, xq, vacc[cc][ob][1]);
         }
       }
     }
@@ -518,7 +532,9 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     tv.stamps = stamps;
     tv.row_only = a.row_only != 0;
     const FamilyConst fc = family_const(a.f);
-    const double dev = compute_tile<PREC, FAM, KP, WANT_DEV, NW>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
+    const double dev =
+        tv.W ? compute_tile<PREC, FAM, KP, WANT_DEV, NW, true>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile)
+             : compute_tile<PREC, FAM, KP, WANT_DEV, NW, false>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
     if (WANT_DEV && threadIdx.x == 0)
       a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
     return 0;
