@@ -358,8 +358,11 @@ int gmf_encoder_init(void** enc_out, const gmf_mlp_config* cfg, void* ws, size_t
  * (synchronises once per epoch when given). */
 int gmf_encoder_train(void* enc, const void* Y, int32_t y_dtype, const float* U, int64_t nrows,
                       int32_t epochs, double* loss_trace_host);
-/* gmf_encoder_forward -- U_out (nrows x d, device) = encoder(Y); bf16 != 0
- * uses bfloat16 operands.  Enqueued. */
+/* gmf_encoder_forward -- U_out (nrows x d, device) = encoder(Y).  bf16 = 0:
+ * float32 operands; 1: bfloat16 operands, all three layers fused in one
+ * kernel (64 rows per workgroup, activations kept on chip) when hidden is a
+ * multiple of 64 up to 256 and d <= 64, else layer by layer; 2: bfloat16
+ * operands layer by layer (same products and rounding as 1).  Enqueued. */
 int gmf_encoder_forward(void* enc, const void* Y, int32_t y_dtype, int64_t nrows, float* U_out,
                         int32_t bf16);
 /* gmf_encoder_loss_grad -- for one minibatch (nrows <= cfg.batch) compute the

@@ -241,6 +241,10 @@ struct EncPlan {
   int64_t oW1, ob1, oW2, ob2, oW3, ob3;   // offsets (floats) inside the flat parameter vector
   size_t o_P, o_G, o_M, o_V, o_Z1, o_H1, o_Z2, o_H2, o_O, o_dO, o_dH, o_dZ, o_part, o_scal, total;
   int64_t inf_rows;   // rows per inference chunk
+  // bfloat16 weights of the fused inference kernel (zero-padded): W1 H x k1p,
+  // W2 H x H, W3 d3p x H with k1p = m rounded up to 32, d3p = d rounded up to 16
+  int k1p, d3p;
+  size_t o_W1b, o_W2b, o_W3b;
 };
 
 void plan_enc(const gmf_mlp_config* c, EncPlan& E) {
@@ -271,6 +275,11 @@ void plan_enc(const gmf_mlp_config* c, EncPlan& E) {
   E.o_dZ = take(4 * (int64_t)E.batch * E.H);
   E.o_part = take(8 * 256);
   E.o_scal = take(8 * 4);
+  E.k1p = (E.m + 31) / 32 * 32;
+  E.d3p = (E.d + 15) / 16 * 16;
+  E.o_W1b = take(2 * (size_t)E.H * E.k1p);
+  E.o_W2b = take(2 * (size_t)E.H * E.H);
+  E.o_W3b = take(2 * (size_t)E.d3p * E.H);
   E.total = b;
 }
 
@@ -280,6 +289,7 @@ struct Enc {
   char* ws;
   hipStream_t st;
   int64_t t = 0;   // Adam updates done
+  bool wb_valid = false;   // the bfloat16 weight copies match the weights
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   float* P(int64_t off) const { return at<float>(E.o_P) + off; }
   float* G(int64_t off) const { return at<float>(E.o_G) + off; }
@@ -347,6 +357,169 @@ int grads_batch(Enc* e, const void* Y, const float* U, int rows, double* loss_pa
   return GMF_OK;
 }
 
+// ------------------------------------------------------ fused inference --
+// out = MLP(log(1 + Y)) for 64 rows per workgroup, all three layers in one
+// kernel with bfloat16 operands and float32 accumulation: the layer-1 count
+// tile is staged through LDS (double-buffered, the next tile's loads in
+// flight during the current tile's products); the activations of a layer
+// stay in LDS as bfloat16 and feed the next layer; only the d outputs of a
+// row are written.  Wavefront w computes hidden columns [H/4 w, H/4 (w+1)) of
+// layers 1 and 2 (NJ = H/64 16-column tiles) and rows [16 w, 16 w + 16) of
+// layer 3.  Products, their order and the rounding points (the log1p counts,
+// the weights and each layer's GELU output rounded to bfloat16) are those of
+// the layer-by-layer path, so the results agree with it bit for bit.
+struct FusedArgs {
+  const void* Y;
+  int64_t rows;
+  int m, H, d, k1p, d3p;
+  const __bf16* W1b; const float* b1;
+  const __bf16* W2b; const float* b2;
+  const __bf16* W3b; const float* b3;
+  float* out;
+};
+
+constexpr int kFusedRows = 64;
+
+template <int COUNTS, int NJ>
+__global__ __launch_bounds__(256) void fused_forward_kernel(FusedArgs a) {
+  constexpr int BM = kFusedRows;
+  constexpr int HMAX = 64 * NJ;
+  __shared__ alignas(16) __bf16 sA[2][BM][32 + 8];
+  __shared__ alignas(16) __bf16 sH[BM][HMAX + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * BM;
+  const int colw = wave * 16 * NJ;
+  floatx4 acc[4][NJ];
+  // ---- layer 1: K = m in tiles of 32, counts staged through LDS
+  const int sr = tid >> 2, sk = (tid & 3) * 8;   // this thread's staging slot
+  const int64_t srow = row0 + sr;
+  auto load_counts = [&](int k0, float (&v)[8]) {
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + sk + u;
+      v[u] = (srow < a.rows && k < a.m) ? load_elem<COUNTS>(a.Y, srow * a.m + k) : 0.f;
+    }
+  };
+  auto store_counts = [&](int buf, const float (&v)[8]) {
+    const floatx8 x = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+    *reinterpret_cast<bf16x8*>(&sA[buf][sr][sk]) = __builtin_convertvector(x, bf16x8);
+  };
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float pre[8];
+  load_counts(0, pre);
+  store_counts(0, pre);
+  __syncthreads();
+  const int nk = a.k1p / 32;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1, k0 = kt * 32;
+    if (kt + 1 < nk) load_counts(k0 + 32, pre);
+    bf16x8 av[4], bv[NJ];
+    for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][16 * i + l16][8 * g]);
+    for (int j = 0; j < NJ; ++j)
+      bv[j] = *reinterpret_cast<const bf16x8*>(a.W1b + (int64_t)(colw + 16 * j + l16) * a.k1p + k0 + 8 * g);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < NJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nk) store_counts(buf ^ 1, pre);
+    __syncthreads();
+  }
+  // bias + GELU, bfloat16 into sH
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < NJ; ++j) {
+      const int col = colw + 16 * j + l16;
+      const float bb = a.b1[col];
+      for (int v = 0; v < 4; ++v) sH[16 * i + 4 * g + v][col] = (__bf16)gelu_f(acc[i][j][v] + bb);
+    }
+  __syncthreads();
+  // ---- layer 2: K = H from sH
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < a.H; k0 += 32) {
+    bf16x8 av[4], bv[NJ];
+    for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf16x8*>(&sH[16 * i + l16][k0 + 8 * g]);
+    for (int j = 0; j < NJ; ++j)
+      bv[j] = *reinterpret_cast<const bf16x8*>(a.W2b + (int64_t)(colw + 16 * j + l16) * a.H + k0 + 8 * g);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < NJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  __syncthreads();   // every wavefront has read layer 1's activations
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < NJ; ++j) {
+      const int col = colw + 16 * j + l16;
+      const float bb = a.b2[col];
+      for (int v = 0; v < 4; ++v) sH[16 * i + 4 * g + v][col] = (__bf16)gelu_f(acc[i][j][v] + bb);
+    }
+  __syncthreads();
+  // ---- layer 3: rows [16 wave, +16), d outputs in tiles of 16
+  const int nj3 = a.d3p / 16;
+  for (int j = 0; j < nj3; ++j) {
+    floatx4 o = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < a.H; k0 += 32) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&sH[16 * wave + l16][k0 + 8 * g]);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(a.W3b + (int64_t)(16 * j + l16) * a.H + k0 + 8 * g);
+      o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, o, 0, 0, 0);
+    }
+    const int col = 16 * j + l16;
+    if (col < a.d)
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 16 * wave + 4 * g + v;
+        if (row < a.rows) a.out[row * a.d + col] = o[v] + a.b3[col];
+      }
+  }
+}
+
+// float weights (rows x cols) -> bfloat16 (out_rows x out_cols, zero padded)
+__global__ void weight_bf16_kernel(const float* W, int rows, int cols, __bf16* out, int out_rows,
+                                   int out_cols) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)out_rows * out_cols) return;
+  const int r = (int)(idx / out_cols), c = (int)(idx % out_cols);
+  out[idx] = (r < rows && c < cols) ? (__bf16)W[(int64_t)r * cols + c] : (__bf16)0.f;
+}
+
+bool fused_supported(const EncPlan& E) { return E.H % 64 == 0 && E.H <= 256 && E.d <= 64; }
+
+int refresh_bf16_weights(Enc* e) {
+  const EncPlan& E = e->E;
+  if (e->wb_valid) return GMF_OK;
+  struct Job { int64_t src; int rows, cols; size_t dst; int orows, ocols; };
+  const Job jobs[3] = {{E.oW1, E.H, E.m, E.o_W1b, E.H, E.k1p},
+                       {E.oW2, E.H, E.H, E.o_W2b, E.H, E.H},
+                       {E.oW3, E.d, E.H, E.o_W3b, E.d3p, E.H}};
+  for (const Job& jb : jobs) {
+    const int64_t n = (int64_t)jb.orows * jb.ocols;
+    hipLaunchKernelGGL(weight_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, e->st,
+                       e->P(jb.src), jb.rows, jb.cols, e->at<__bf16>(jb.dst), jb.orows, jb.ocols);
+    EHIP(hipGetLastError());
+  }
+  e->wb_valid = true;
+  return GMF_OK;
+}
+
+template <int COUNTS>
+int fused_forward(Enc* e, const void* Y, int64_t rows, float* out) {
+  const EncPlan& E = e->E;
+  int rc = refresh_bf16_weights(e);
+  if (rc != GMF_OK) return rc;
+  FusedArgs f;
+  f.Y = Y; f.rows = rows; f.m = E.m; f.H = E.H; f.d = E.d; f.k1p = E.k1p; f.d3p = E.d3p;
+  f.W1b = e->at<__bf16>(E.o_W1b); f.b1 = e->P(E.ob1);
+  f.W2b = e->at<__bf16>(E.o_W2b); f.b2 = e->P(E.ob2);
+  f.W3b = e->at<__bf16>(E.o_W3b); f.b3 = e->P(E.ob3);
+  f.out = out;
+  const dim3 grid((unsigned)((rows + kFusedRows - 1) / kFusedRows));
+  switch (E.H / 64) {
+    case 1: hipLaunchKernelGGL((fused_forward_kernel<COUNTS, 1>), grid, dim3(256), 0, e->st, f); break;
+    case 2: hipLaunchKernelGGL((fused_forward_kernel<COUNTS, 2>), grid, dim3(256), 0, e->st, f); break;
+    case 3: hipLaunchKernelGGL((fused_forward_kernel<COUNTS, 3>), grid, dim3(256), 0, e->st, f); break;
+    default: hipLaunchKernelGGL((fused_forward_kernel<COUNTS, 4>), grid, dim3(256), 0, e->st, f); break;
+  }
+  EHIP(hipGetLastError());
+  return GMF_OK;
+}
+
 // One Adam step on the batch of `rows` rows.
 template <int COUNTS>
 int train_batch(Enc* e, const void* Y, const float* U, int rows, double* loss_partial) {
@@ -354,6 +527,7 @@ int train_batch(Enc* e, const void* Y, const float* U, int rows, double* loss_pa
   int rc = grads_batch<COUNTS>(e, Y, U, rows, loss_partial);
   if (rc != GMF_OK) return rc;
   e->t += 1;
+  e->wb_valid = false;
   const gmf_mlp_config& c = e->cfg;
   const float c1 = (float)(1.0 - std::pow(c.beta1, (double)e->t));
   const float c2 = (float)(1.0 - std::pow(c.beta2, (double)e->t));
@@ -466,6 +640,10 @@ int gmf_encoder_forward(void* enc, const void* Y, int32_t y_dtype, int64_t nrows
   if (y_dtype != GMF_Y_INT32 && y_dtype != GMF_Y_FLOAT32) return gmf::efail(GMF_EINVAL, "bad y_dtype");
   Enc* e = static_cast<Enc*>(enc);
   const EncPlan& E = e->E;
+  if (bf16 < 0 || bf16 > 2) return gmf::efail(GMF_EINVAL, "bf16 must be 0, 1 or 2");
+  if (bf16 == 1 && gmf::fused_supported(E))
+    return (y_dtype == GMF_Y_INT32) ? gmf::fused_forward<1>(e, Y, nrows, U_out)
+                                    : gmf::fused_forward<2>(e, Y, nrows, U_out);
   for (int64_t r0 = 0; r0 < nrows; r0 += E.inf_rows) {
     const int rows = (int)std::min<int64_t>(E.inf_rows, nrows - r0);
     const void* Yb = (y_dtype == GMF_Y_INT32)

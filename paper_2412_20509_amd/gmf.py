@@ -570,12 +570,14 @@ class Encoder:
         self.stream.synchronize()
         return list(tr)[:epochs] if trace else None
 
-    def forward(self, Y, bf16=True):
+    def forward(self, Y, bf16=True, fused=True):
+        """Encoder output; bf16 with fused=False runs the layer-by-layer kernels."""
         t = self.torch
         Yt, ydt = self._y(Y)
         out = t.empty((Yt.shape[0], self.d), dtype=t.float32, device=self.device)
+        mode = 0 if not bf16 else (1 if fused else 2)
         _echeck(load_library().gmf_encoder_forward(self.enc, Yt.data_ptr(), ydt, Yt.shape[0],
-                                                   out.data_ptr(), int(bool(bf16))))
+                                                   out.data_ptr(), mode))
         self.stream.synchronize()
         return out
 

@@ -148,3 +148,32 @@ def test_encoder_rejects_bad_sizes(data):
     with pytest.raises(GMFError):
         enc.loss_grad(Y[:BATCH + 1], U[:BATCH + 1])
     enc.close()
+
+
+@pytest.mark.parametrize("hidden,d", [(64, 5), (128, 10), (256, 20)])
+def test_fused_bf16_inference_equals_layer_by_layer(hidden, d):
+    """The fused bfloat16 kernel (three layers per 64-row workgroup) makes the
+    same products in the same order, with the same bfloat16 rounding points,
+    as the layer-by-layer bfloat16 path: identical outputs, on a row count
+    that leaves a ragged last workgroup and a column count with a K tail."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"[case] fused vs layered bf16 inference, hidden={hidden} d={d}", flush=True)
+    from paper_2412_20509_amd.gmf import Encoder
+    rng = np.random.default_rng(3 + hidden)
+    m = 1000                                   # 31 K-tiles of 32 and a tail of 8
+    Y = rng.poisson(rng.gamma(0.5, 2.0, size=(777, m))).astype(np.int32)
+    w = mlp_init(m, hidden, d, seed=hidden)
+    enc = Encoder(m, d, w, hidden=hidden, batch=64)
+    fused = enc.forward(Y, bf16=True, fused=True).cpu().numpy()
+    layered = enc.forward(Y, bf16=True, fused=False).cpu().numpy()
+    assert np.array_equal(fused, layered)
+    out_o = oracle_mlp(w).forward(Y)[0]
+    assert nrel(fused, out_o) <= 2e-2
+    # after a training step the bfloat16 weight copies are refreshed
+    enc.train(Y[:64], rng.standard_normal((64, d)).astype(np.float32), 1)
+    fused2 = enc.forward(Y, bf16=True, fused=True).cpu().numpy()
+    layered2 = enc.forward(Y, bf16=True, fused=False).cpu().numpy()
+    assert np.array_equal(fused2, layered2) and not np.array_equal(fused2, fused)
+    enc.close()
