@@ -403,7 +403,7 @@ def main():
     bytes_launch = bytes_step * main_arm["timed_steps"] / max(main_arm["launches"], 1)
     mean_launch_s = main_arm["launch_ms_total"] * 1e-3 / max(main_arm["launches"], 1)
     achieved = bytes_launch / mean_launch_s / 1e9
-    roof = dict(bound="hbm", kernel="level_kernel<FP32,NB,KP=16,dev>", achieved=achieved,
+    roof = dict(bound="hbm", kernel="level_kernel<0, 1, 16, true, 4>", achieved=achieved,
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                 traffic=recorded_traffic(), bytes_per_launch=bytes_launch,
                 mean_launch_us=1e6 * mean_launch_s, steps_per_launch=main_arm["timed_steps"] /
