@@ -40,6 +40,8 @@ struct GemmArgs {
   float* Zout;         // EPI_BIAS_GELU: pre-activation, leading dim ldc
   const float* Zin;    // EPI_GELU_BWD: pre-activation, leading dim ldc
   int mtiles, ntiles;
+  int kchunk;          // K range of blockIdx.y: [y kchunk, (y+1) kchunk) (multiple of TK)
+  int64_t cstride;     // output offset of blockIdx.y (split K writes partial products)
 };
 
 __device__ __forceinline__ float gelu_f(float z) {
@@ -81,7 +83,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  const int kb = blockIdx.y * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  float* const Cout = g.C + blockIdx.y * g.cstride;
+  for (int k0 = kb; k0 < ke; k0 += TK) {
     __syncthreads();
     // A tile: element (m0+i, k0+kk) -> As[i][kk]
     if constexpr (!TA) {
@@ -155,30 +160,83 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           x = gelu_f(x);
         }
         if constexpr (EPI == EPI_GELU_BWD) x *= gelu_grad_f(g.Zin[ci]);
-        g.C[ci] = x;
+        Cout[ci] = x;
       }
     }
 }
 
+// Split-K epilogue: C = epilogue(sum over S partial products, in order).
+template <int EPI>
+__global__ void splitk_epilogue_kernel(const float* part, int S, int M, int N, const float* bias,
+                                       float* C, int64_t ldc, float* Zout, const float* Zin) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  const int m = (int)(idx / N), n = (int)(idx % N);
+  float x = 0.f;
+  for (int s = 0; s < S; ++s) x += part[(int64_t)s * M * N + idx];
+  const int64_t ci = (int64_t)m * ldc + n;
+  if constexpr (EPI == EPI_BIAS) x += bias[n];
+  if constexpr (EPI == EPI_BIAS_GELU) {
+    x += bias[n];
+    Zout[ci] = x;
+    x = gelu_f(x);
+  }
+  if constexpr (EPI == EPI_GELU_BWD) x *= gelu_grad_f(Zin[ci]);
+  C[ci] = x;
+}
+
+constexpr int kMaxSplit = 8;
+
+// C = op(A) op(B) with the epilogue.  Float32 products with few output tiles
+// and a long K (the first layer of a training batch) split K over up to
+// kMaxSplit workgroups per tile when a buffer of kMaxSplit * M * N floats is
+// given; bfloat16 products never split (their K order is fixed).
 template <int PREC, bool TA, bool TB, int AC, int BC, int EPI>
-hipError_t gemm(const GemmArgs& a0, hipStream_t s) {
+hipError_t gemm(const GemmArgs& a0, hipStream_t s, float* split_buf = nullptr,
+                int64_t split_cap = 0) {
   GemmArgs a = a0;
   a.mtiles = (a.M + TM - 1) / TM;
   a.ntiles = (a.N + TN - 1) / TN;
   const int groups = (a.mtiles + 7) / 8;
   const int grid = groups * 8 * a.ntiles;
   if (a.M <= 0 || a.N <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, AC, BC, EPI>), dim3(grid), dim3(256), 0, s, a);
+  int S = 1;
+  if (PREC == kF32 && split_buf && a.mtiles * a.ntiles < 64 && a.K >= 1024 &&
+      (int64_t)kMaxSplit * a.M * a.N <= split_cap)
+    S = std::min(kMaxSplit, a.K / 256);
+  if (S <= 1) {
+    a.kchunk = (a.K + TK - 1) / TK * TK;
+    a.cstride = 0;
+    hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, AC, BC, EPI>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  GemmArgs p = a;
+  p.kchunk = ((a.K + S - 1) / S + TK - 1) / TK * TK;
+  S = (a.K + p.kchunk - 1) / p.kchunk;
+  p.C = split_buf;
+  p.ldc = a.N;
+  p.cstride = (int64_t)a.M * a.N;
+  hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, AC, BC, EPI_NONE>), dim3(grid, S), dim3(256), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)a.M * a.N;
+  hipLaunchKernelGGL((splitk_epilogue_kernel<EPI>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     split_buf, S, a.M, a.N, a.bias, a.C, a.ldc, a.Zout, a.Zin);
   return hipGetLastError();
 }
 
-// db[n] = sum_m D[m][n] (fixed order per column).
+// db[n] = sum_m D[m][n]: 64 columns per workgroup, rows split over 4 lanes
+// groups (rows r = 4i + part), float64, then the four parts in order.
 __global__ void colsum_kernel(const float* D, int M, int N, float* out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+  __shared__ double red[4][64];
+  const int t = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + t;
   double s = 0.0;
-  for (int m = 0; m < M; ++m) s += (double)D[(int64_t)m * N + n];
-  out[n] = (float)s;
+  if (n < N)
+    for (int m = part; m < M; m += 4) s += (double)D[(int64_t)m * N + n];
+  red[part][t] = s;
+  __syncthreads();
+  if (part == 0 && n < N) out[n] = (float)(((red[0][t] + red[1][t]) + red[2][t]) + red[3][t]);
 }
 
 // dO = 2 (O - U) / (B d); loss partial sums of (O - U)^2 per block.
@@ -245,6 +303,7 @@ struct EncPlan {
   // W2 H x H, W3 d3p x H with k1p = m rounded up to 32, d3p = d rounded up to 16
   int k1p, d3p;
   size_t o_W1b, o_W2b, o_W3b;
+  size_t o_split;      // split-K partial products of a training batch's first layer
 };
 
 void plan_enc(const gmf_mlp_config* c, EncPlan& E) {
@@ -275,6 +334,7 @@ void plan_enc(const gmf_mlp_config* c, EncPlan& E) {
   E.o_dZ = take(4 * (int64_t)E.batch * E.H);
   E.o_part = take(8 * 256);
   E.o_scal = take(8 * 4);
+  E.o_split = take(4 * (size_t)kMaxSplit * E.batch * E.H);
   E.k1p = (E.m + 31) / 32 * 32;
   E.d3p = (E.d + 15) / 16 * 16;
   E.o_W1b = take(2 * (size_t)E.H * E.k1p);
@@ -310,7 +370,8 @@ int forward(Enc* e, const void* Y, int rows) {
   GemmArgs g = gargs(Y, E.m, e->P(E.oW1), E.m, e->at<float>(E.o_H1), E.H, rows, E.H, E.m);
   g.bias = e->P(E.ob1);
   g.Zout = e->at<float>(E.o_Z1);
-  EHIP((gemm<PREC, false, true, COUNTS, false, EPI_BIAS_GELU>(g, e->st)));
+  EHIP((gemm<PREC, false, true, COUNTS, false, EPI_BIAS_GELU>(
+      g, e->st, e->at<float>(E.o_split), (int64_t)kMaxSplit * E.batch * E.H)));
   g = gargs(e->at<float>(E.o_H1), E.H, e->P(E.oW2), E.H, e->at<float>(E.o_H2), E.H, rows, E.H, E.H);
   g.bias = e->P(E.ob2);
   g.Zout = e->at<float>(E.o_Z2);
@@ -338,21 +399,21 @@ int grads_batch(Enc* e, const void* Y, const float* U, int rows, double* loss_pa
   // layer 3: dW3 = dO' H2, db3 = colsum dO, dZ2 = (dO W3) * gelu'(Z2)
   EHIP((gemm<kF32, true, false, false, false, EPI_NONE>(
       gargs(dO, E.d, e->at<float>(E.o_H2), E.H, e->G(E.oW3), E.H, E.d, E.H, rows), e->st)));
-  hipLaunchKernelGGL(colsum_kernel, dim3((E.d + 255) / 256), dim3(256), 0, e->st, dO, rows, E.d, e->G(E.ob3));
+  hipLaunchKernelGGL(colsum_kernel, dim3((E.d + 63) / 64), dim3(256), 0, e->st, dO, rows, E.d, e->G(E.ob3));
   GemmArgs g = gargs(dO, E.d, e->P(E.oW3), E.H, dZ, E.H, rows, E.H, E.d);
   g.Zin = e->at<float>(E.o_Z2);
   EHIP((gemm<kF32, false, false, false, false, EPI_GELU_BWD>(g, e->st)));
   // layer 2: dW2 = dZ2' H1, db2 = colsum dZ2, dZ1 = (dZ2 W2) * gelu'(Z1)
   EHIP((gemm<kF32, true, false, false, false, EPI_NONE>(
       gargs(dZ, E.H, e->at<float>(E.o_H1), E.H, e->G(E.oW2), E.H, E.H, E.H, rows), e->st)));
-  hipLaunchKernelGGL(colsum_kernel, dim3((E.H + 255) / 256), dim3(256), 0, e->st, dZ, rows, E.H, e->G(E.ob2));
+  hipLaunchKernelGGL(colsum_kernel, dim3((E.H + 63) / 64), dim3(256), 0, e->st, dZ, rows, E.H, e->G(E.ob2));
   g = gargs(dZ, E.H, e->P(E.oW2), E.H, dH, E.H, rows, E.H, E.H);
   g.Zin = e->at<float>(E.o_Z1);
   EHIP((gemm<kF32, false, false, false, false, EPI_GELU_BWD>(g, e->st)));
   // layer 1: dW1 = dZ1' log1p(Y), db1 = colsum dZ1
   EHIP((gemm<kF32, true, false, false, COUNTS, EPI_NONE>(
       gargs(dH, E.H, Y, E.m, e->G(E.oW1), E.m, E.H, E.m, rows), e->st)));
-  hipLaunchKernelGGL(colsum_kernel, dim3((E.H + 255) / 256), dim3(256), 0, e->st, dH, rows, E.H, e->G(E.ob1));
+  hipLaunchKernelGGL(colsum_kernel, dim3((E.H + 63) / 64), dim3(256), 0, e->st, dH, rows, E.H, e->G(E.ob1));
   EHIP(hipGetLastError());
   return GMF_OK;
 }
