@@ -267,7 +267,7 @@ def run_batched(nfits, scale, epochs, torch):
     """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
     against batched epochs (gmf_batch_*, with and without the recorded graph).
     Fits are grouped into batches by panel stride (p + q + d <= 32 -> 32,
-    else 48)."""
+    else 48); every fit uses 128-row tiles."""
     from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF
     from synth import gen_nb
     specs = batch_specs(nfits, scale)
@@ -277,8 +277,11 @@ def run_batched(nfits, scale, epochs, torch):
         pr = gen_nb(n=sp["n"], m=sp["m"], d=sp["d"], R=10, S=5, seed=sp["seed"],
                     family=sp["family"], chunked=True)
         stride = 32 if pr.k <= 32 else 48
+        # 128-row tiles: in a batch the other fits supply the parallelism, and
+        # deeper tiles pipeline their row groups (61 vs 51 epochs/s at 32 rows)
         fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
-                       seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1)
+                       seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1,
+                       tile_rows=128)
         fits.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
         entries += pr.n * pr.m
         del pr

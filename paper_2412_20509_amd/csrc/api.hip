@@ -957,7 +957,7 @@ namespace {
 
 struct ProjPlan {
   int64_t n_new = 0;
-  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_sub = 1, upd_per_step = 0;
+  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_sub = 1, upd_per_step = 0, nw = 4;
   int64_t slot_u = 0;
   size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
@@ -972,6 +972,11 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
                      gmf::kRowGroup);
   Q.rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
   Q.nrr = (int)((n_new + Q.rpw - 1) / Q.rpw);
+  // wavefronts per tile by the rule of the fit's plan, for the projection's tiles
+  const int tw = c->cfg.tile_waves;
+  if (tw == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) Q.nw = 4;
+  else if (tw == 8) Q.nw = 8;
+  else Q.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || Q.rpw >= 2 * gmf::kRowGroup) ? 8 : 4;
   Q.dev_rpw = dev_rows_per_wg((int)std::min<int64_t>(n_new, 1 << 30));
   Q.dev_tiles = 0;
   for (int s = 0; s < P.S; ++s) Q.dev_tiles += (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];
@@ -1215,9 +1220,9 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
       stp.t = t;
       a.steps[0] = stp;
       a.n_tile_steps = 1; a.n_upd_steps = 0;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, P.nw, a, T, st));
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, Q.nw, a, T, st));
       a.n_tile_steps = 0; a.n_upd_steps = 1;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, P.nw, a, Q.upd_per_step, st));
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, Q.nw, a, Q.upd_per_step, st));
     }
     if (dev_trace_host) {
       const int rc = proj_dev(dev_trace_host + e + 1);
