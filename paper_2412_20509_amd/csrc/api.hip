@@ -100,6 +100,7 @@ struct Plan {
 
 constexpr int kDevRing = 4096;
 constexpr int kEvRing = 256;   // gmf_run evaluation results held on the device
+constexpr int kDevOverlapWGs = 128;   // workgroups of the deviance that overlaps the steps
 constexpr int64_t kMaxTimedSteps = 8192;
 constexpr int kMaxSlots = 16;
 constexpr int kTilesPerStepTarget = 256;
@@ -543,7 +544,7 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
 
 gmf::DevArgs dev_args(Ctx* c) {
   const Plan& P = c->P;
-  gmf::DevArgs a;
+  gmf::DevArgs a{};
   a.Y = c->at<float>(P.o_Yb);
   a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
   a.Prow = c->at<float>(P.o_Prow);
@@ -1157,7 +1158,7 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
   HIP_TRY(gmf::launch_fill_f64(Hrow, n_new * P.KU, 0.0, st));
 
   // ---- deviance of the new rows
-  gmf::DevArgs da;
+  gmf::DevArgs da{};
   da.Y = Yb; da.W = nullptr; da.Prow = Prow; da.Pcol = Pcol;
   da.tile_block = reinterpret_cast<int*>(at(Q.o_tileblk));
   da.tile_first = reinterpret_cast<int*>(at(Q.o_tilefirst));
@@ -1376,6 +1377,7 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
     da.Prow = srow;
     da.Pcol = scol;
     da.partial = part2 + slot * (size_t)P.dev_tiles;
+    da.grid_cap = kDevOverlapWGs;   // leave compute units to the steps running beside it
     HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, c->side));
     HIP_TRY(gmf::launch_finalize(da.partial, P.dev_tiles, nullptr, 0, c->at<int>(P.o_flag),
                                  evring + 8 * (ev_i % kEvRing), c->side));

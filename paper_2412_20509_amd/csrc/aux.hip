@@ -14,6 +14,8 @@
 //    of the deviance in float64 (constant during a fit).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "family.hpp"
 #include "gmf_kernels.hpp"
 
@@ -286,10 +288,8 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
 // next group's counts and panel rows prefetched.  Same 32x32 pieces and MFMA
 // operand layout as the step kernel (float32 products).
 template <int FAM, int KP>
-__global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
-  __shared__ float sP[kRowGroup][KP + 4];
-  __shared__ double sDev[kTileWaves];
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float (*sP)[KP + 4],
+                                              double* sDev) {
   const FamilyConst fc = family_const(a.f);
   const int blk = a.tile_block[tile];
   const int local = tile - a.tile_first[blk];
@@ -383,9 +383,22 @@ __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   if (tid == 0) a.partial[tile] = ((sDev[0] + sDev[1]) + sDev[2]) + sDev[3];
 }
 
+// One workgroup per tile, or (grid_cap) fewer workgroups walking the tiles:
+// a capped grid leaves compute units to work running beside it.
+template <int FAM, int KP>
+__global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
+  __shared__ float sP[kRowGroup][KP + 4];
+  __shared__ double sDev[kTileWaves];
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    deviance_tile<FAM, KP>(a, tile, sP, sDev);
+    __syncthreads();   // sP and sDev are reused by the next tile
+  }
+}
+
 template <int FAM>
 static hipError_t launch_dev_kp(int KP, const DevArgs& a, hipStream_t s) {
-  const dim3 grid(a.n_tiles), block(kTileThreads);
+  if (a.n_tiles <= 0) return hipSuccess;
+  const dim3 grid(a.grid_cap > 0 ? std::min(a.n_tiles, a.grid_cap) : a.n_tiles), block(kTileThreads);
   switch (KP) {
     case 16: hipLaunchKernelGGL((deviance_kernel<FAM, 16>), grid, block, 0, s, a); break;
     case 32: hipLaunchKernelGGL((deviance_kernel<FAM, 32>), grid, block, 0, s, a); break;

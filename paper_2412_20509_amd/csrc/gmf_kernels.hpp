@@ -148,6 +148,7 @@ struct DevArgs {
   FamilyArgs f;
   double* partial;             // one per tile
   int n_tiles;
+  int grid_cap;                // deviance: at most this many workgroups (0 = one per tile)
 };
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s);
 // a.partial[tile] = sum over the tile of w c(y), the count-only part of half
