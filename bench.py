@@ -25,7 +25,8 @@ Printed JSON line:
                     the 8 TB/s HBM peak; traffic = measured HBM bytes per launch
                     (rocprofv3 counters, summary under profiles/)
   cpu_baseline      the FP64 oracle on the host, bounded sample
-  arms              the same measurements for the BF16 arm
+  arms              the same measurements for the BF16 arm and for BF16 steps
+                    finished by FP32 steps over the last quarter of the epochs
   large             the 100000 x 5000 rank-20 workload (steps only)
   batched           64 uneven fits advanced together (gmf_batch_*) against the
                     same fits stepped one by one
@@ -91,7 +92,9 @@ def tile_bytes_per_launch(pr):
     return 4.0 * ns * ms + 4.0 * (ns + ms) * pr.k
 
 
-def run_arm(pr, precision, epochs, warmup, dstar, torch):
+def run_arm(pr, precision, epochs, warmup, dstar, torch, polish=0):
+    """Timed epochs of one arm; polish > 0: the last `polish` epochs switch
+    from BF16 to FP32 steps (gmf_set_precision) on the same iterate."""
     per_epoch = pr.R * pr.S
     # warm-up on a throwaway context (kernel loading, caches)
     g = make_gmf(pr, precision)
@@ -107,7 +110,14 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch):
     # the timed region: `epochs` epochs, the full deviance of every epoch
     # evaluated on a second stream from a snapshot of the panels (gmf_run)
     t0 = time.perf_counter()
-    devs, ms = g.run(epochs, eval_every=1)
+    if polish > 0:
+        devs, ms = g.run(epochs - polish, eval_every=1)
+        t_mid = time.perf_counter() - t0
+        g.set_precision("fp32")
+        d2, m2 = g.run(polish, eval_every=1)
+        devs, ms = devs + d2, ms + [1e3 * t_mid + x for x in m2]
+    else:
+        devs, ms = g.run(epochs, eval_every=1)
     wall = time.perf_counter() - t0
     t_hit = e_hit = None
     if dstar is not None:
@@ -119,7 +129,12 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch):
     g2 = make_gmf(pr, precision)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    g2.run(epochs, trace=False)
+    if polish > 0:
+        g2.run(epochs - polish, trace=False)
+        g2.set_precision("fp32")
+        g2.run(polish, trace=False)
+    else:
+        g2.run(epochs, trace=False)
     wall_steps = time.perf_counter() - t1
     g2.close()
     del g2
@@ -352,7 +367,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=3, help="untimed warm-up epochs")
-    ap.add_argument("--arms", default="fp32,bf16")
+    ap.add_argument("--arms", default="fp32,bf16",
+                    help="fp32, bf16, bf16+fp32 (BF16 steps, FP32 for the last quarter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 100000x5000 rank-20 throughput section")
@@ -396,10 +412,14 @@ def main():
     dstar = target["final"] if target else None
 
     arms = {}
-    for prec in args.arms.split(","):
-        log(f"arm {prec}: {args.warmup} warm-up + {args.steps} timed epochs")
-        arms[prec] = run_arm(pr, prec, args.steps, args.warmup, dstar, torch)
-        log(f"arm {prec}: {arms[prec]['epochs_per_s']:.1f} epochs/s")
+    for arm in args.arms.split(","):
+        prec, polish = arm, 0
+        if arm == "bf16+fp32":             # BF16, then FP32 for the last quarter
+            prec, polish = "bf16", args.steps // 4
+        log(f"arm {arm}: {args.warmup} warm-up + {args.steps} timed epochs")
+        arms[arm] = run_arm(pr, prec, args.steps, args.warmup, dstar, torch, polish=polish)
+        log(f"arm {arm}: {arms[arm]['epochs_per_s']:.1f} epochs/s, "
+            f"s to 1e-4: {arms[arm]['s_to_1e4']}")
 
     main_arm = arms.get("fp32") or next(iter(arms.values()))
     bytes_step = tile_bytes_per_launch(pr)

@@ -134,6 +134,13 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
  * Errors: GMF_EINVAL (nsteps < 0), GMF_EDEVICE. */
 int gmf_step(void* ctx, int64_t nsteps);
 
+/* gmf_set_precision -- switch the arithmetic of the following steps
+ * (GMF_PREC_FP32 / GMF_PREC_BF16) on the same iterate and moments, e.g. BF16
+ * epochs followed by FP32 epochs that settle the iterate where the FP32 path
+ * converges.  BF16 needs a panel stride of 32 or 64 (automatic for a BF16
+ * context, or cfg.panel_stride).  Errors: GMF_EINVAL. */
+int gmf_set_precision(void* ctx, int32_t precision);
+
 /* gmf_fit -- run epochs of R*S steps (one epoch = R sweeps over J_1..J_S) up
  * to max_epochs; every eval_every epochs evaluate the full deviance and stop
  * when its relative change is below tol (tol <= 0: run all epochs).

@@ -783,6 +783,22 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   return GMF_OK;
 }
 
+int gmf_set_precision(void* ctx, int32_t precision) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  Plan& P = c->P;
+  if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16) return fail(GMF_EINVAL, "unknown precision");
+  const bool ok = (precision == GMF_PREC_BF16) ? (P.KP == 32 || P.KP == 64) : true;
+  if (!ok) return fail(GMF_EINVAL, "BF16 steps need panel stride 32 or 64 (set panel_stride at init)");
+  P.prec = precision;
+  c->cfg.precision = precision;
+  const int tw = c->cfg.tile_waves;
+  if (tw == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) P.nw = 4;
+  else if (tw == 8) P.nw = 8;
+  else P.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || P.rpw[0] >= 2 * gmf::kRowGroup) ? 8 : 4;
+  return GMF_OK;
+}
+
 int gmf_step(void* ctx, int64_t nsteps) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(GMF_EINVAL, "nsteps < 0");

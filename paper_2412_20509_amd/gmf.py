@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "gmf_fit": (C.c_int, [vp, i32, C.c_double, i32, f64p, C.POINTER(i32)]),
         "gmf_deviance": (C.c_int, [vp, f64p, f64p]),
         "gmf_run": (C.c_int, [vp, i32, i32, f64p, f64p]),
+        "gmf_set_precision": (C.c_int, [vp, i32]),
         "gmf_block_deviance": (C.c_int, [vp, f64p, i64]),
         "gmf_get_params": (C.c_int, [vp, vp, vp, vp, vp, i32]),
         "gmf_set_params": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -383,6 +384,10 @@ class GMF:
 
     def fit(self, max_epochs, tol=0.0, eval_every=1):
         return gmf_fit(self.ctx, max_epochs, tol, eval_every)
+
+    def set_precision(self, precision):
+        """gmf_set_precision: 'fp32' or 'bf16' for the following steps."""
+        _check(load_library().gmf_set_precision(self.ctx, PREC_CODES[precision]))
 
     def run(self, epochs, eval_every=1, trace=True):
         """gmf_run: epochs with the deviance overlapped every eval_every epochs."""

@@ -272,3 +272,23 @@ def test_eight_wave_tiles_equal_four_wave_tiles(precision, d):
     assert np.max(np.abs(b4 - b8) / np.abs(b4)) < 1e-6
     g4.close()
     g8.close()
+
+
+def test_precision_switch():
+    """A BF16 context switched to FP32 steps exactly like an FP32 context of the
+    same panel stride; BF16 steps need a stride of 32 or 64."""
+    from paper_2412_20509_amd.gmf import GMFError
+    print("[case] precision switch", flush=True)
+    pr = gen_nb(n=1500, m=600, d=6, R=3, S=2, seed=1601)
+    gb = gpu_for(pr, precision="bf16")                  # stride 32
+    gf = gpu_for(pr, precision="fp32", panel_stride=32)
+    gb.set_precision("fp32")
+    gb.step(12)
+    gf.step(12)
+    for x, y in zip(gb.params() + tuple(gb.moments()), gf.params() + tuple(gf.moments())):
+        assert np.array_equal(x, y)
+    g16 = gpu_for(pr, precision="fp32")                  # stride 16
+    with pytest.raises(GMFError):
+        g16.set_precision("bf16")
+    for g in (gb, gf, g16):
+        g.close()
