@@ -25,14 +25,16 @@ Printed JSON line:
                     the 8 TB/s HBM peak; traffic = measured HBM bytes per launch
                     (rocprofv3 counters, summary under profiles/)
   cpu_baseline      the FP64 oracle on the host, bounded sample
-  arms              the same measurements for the BF16 arm and for BF16 steps
-                    finished by FP32 steps over the last quarter of the epochs
-  large             the 100000 x 5000 rank-20 workload (steps only)
+  arms              the same measurements for each arm: FP32, BF16, split BF16
+                    (bf16x3), optionally BF16 steps finished by FP32 steps over
+                    the last quarter of the epochs (bf16+fp32)
+  large             the 100000 x 5000 rank-20 workload (steps only), per precision
   batched           64 uneven fits advanced together (gmf_batch_*) against the
                     same fits stepped one by one
   warm_start        learned warm start of 1,000,000 new rows: epochs and
                     seconds to 1e-4 of the converged projection deviance for a
-                    cold start and for the encoder's bfloat16 predictions
+                    cold start and for the encoder's bfloat16 predictions, with
+                    FP32 and with split-BF16 projection steps
 """
 import argparse
 import json
@@ -241,8 +243,16 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     _, _, trw, msw, fb = g.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
+    # the same warm start with split-bfloat16 projection steps, on a context
+    # holding the same fitted parameters
+    log("warm start: warm arm, split bfloat16 steps")
+    gx = make_gmf(pr, "bf16x3")
+    gx.set_params(*g.params())
+    _, _, trx, msx, fbx = gx.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
+    gx.close()
     ec, tc = first_hit(trc, msc, dstar)
     ew, tw = first_hit(trw, msw, dstar)
+    ex, tx = first_hit(trx, msx, dstar)
     enc.close()
     g.close()
     return dict(
@@ -259,6 +269,11 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
                   s_to_1e4=None if tw is None else tw / 1e3 + t_inf,
                   deviance_start=trw[0], fallback_rows=fb,
                   ms_per_epoch=(msw[-1] - msw[0]) / max_epochs),
+        warm_bf16x3=dict(epochs_to_1e4=ex,
+                         s_to_1e4=None if tx is None else tx / 1e3 + t_inf,
+                         deviance_start=trx[0], fallback_rows=fbx,
+                         final_rel_to_reference=abs(trx[-1] - dstar) / dstar,
+                         ms_per_epoch=(msx[-1] - msx[0]) / max_epochs),
     )
 
 
@@ -367,8 +382,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=3, help="untimed warm-up epochs")
-    ap.add_argument("--arms", default="fp32,bf16",
-                    help="fp32, bf16, bf16+fp32 (BF16 steps, FP32 for the last quarter)")
+    ap.add_argument("--arms", default="fp32,bf16,bf16x3",
+                    help="fp32, bf16, bf16x3 (split bfloat16), bf16+fp32 (BF16 steps, "
+                         "FP32 for the last quarter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 100000x5000 rank-20 throughput section")
@@ -436,7 +452,7 @@ def main():
         log("generating the 100000x5000 NB workload (rank 20)")
         pr3 = make_problem("c3")
         large = {}
-        for prec in ("bf16", "fp32"):
+        for prec in ("bf16x3", "bf16", "fp32"):
             log(f"large workload, arm {prec}: 1 warm-up + {args.large_epochs} timed epochs")
             large[prec] = run_throughput(pr3, prec, args.large_epochs, torch)
             log(f"large {prec}: {large[prec]['epochs_per_s']:.1f} epochs/s, "
@@ -449,6 +465,7 @@ def main():
         warm = run_warm_start(pr, args.warm_rows, args.warm_epochs, args.encoder_epochs, torch)
         log(f"warm start: cold {warm['cold']['epochs_to_1e4']} epochs, "
             f"warm {warm['warm']['epochs_to_1e4']} epochs, "
+            f"warm bf16x3 {warm['warm_bf16x3']['epochs_to_1e4']} epochs, "
             f"{warm['warm']['fallback_rows']} fallback rows")
     batched = None
     if not args.no_batched:

@@ -53,15 +53,19 @@ enum { GMF_LINK_LOG = 0, GMF_LINK_IDENTITY = 1 };
 /* Arithmetic of the block contractions (eta and the four gradient sums).
  * FP32: float32 matrix-core products with float32 accumulation.
  * BF16: bfloat16 operands (round to nearest even), float32 accumulation.
- * In both, the smoothed moments and the deviance sums are float64. */
-enum { GMF_PREC_FP32 = 0, GMF_PREC_BF16 = 1 };
+ * BF16X3: bfloat16 matrix-core products on operands split into a high and a
+ *   low bfloat16 part (x = hi + lo, lo = bf16(x - hi)), three products per
+ *   contraction (lo*hi + hi*lo + hi*hi), float32 accumulation: about 16
+ *   mantissa bits per operand instead of 8, in eta and in all four sums.
+ * In all, the smoothed moments and the deviance sums are float64. */
+enum { GMF_PREC_FP32 = 0, GMF_PREC_BF16 = 1, GMF_PREC_BF16X3 = 2 };
 /* Element type of the Y array handed to gmf_init. */
 enum { GMF_Y_INT32 = 0, GMF_Y_FLOAT32 = 1 };
 
 typedef struct gmf_config {
   int32_t family;     /* GMF_POISSON, GMF_NEGBIN or GMF_GAUSSIAN             */
   int32_t link;       /* GMF_LINK_LOG (Poisson, NB) or GMF_LINK_IDENTITY     */
-  int32_t precision;  /* GMF_PREC_FP32 or GMF_PREC_BF16                       */
+  int32_t precision;  /* GMF_PREC_FP32, GMF_PREC_BF16 or GMF_PREC_BF16X3     */
   int32_t bias_mode;  /* 0: alpha_t = (1-(1-a2)^t)/(1-(1-a1)^t) (Adam form);
                          1: alpha_t = (1-a2^t)/(1-a1^t) as printed (eq. 11)    */
   int64_t n, m;       /* rows and columns of Y                                 */
@@ -134,11 +138,13 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
  * Errors: GMF_EINVAL (nsteps < 0), GMF_EDEVICE. */
 int gmf_step(void* ctx, int64_t nsteps);
 
-/* gmf_set_precision -- switch the arithmetic of the following steps
- * (GMF_PREC_FP32 / GMF_PREC_BF16) on the same iterate and moments, e.g. BF16
- * epochs followed by FP32 epochs that settle the iterate where the FP32 path
- * converges.  BF16 needs a panel stride of 32 or 64 (automatic for a BF16
- * context, or cfg.panel_stride).  Errors: GMF_EINVAL. */
+/* gmf_set_precision -- switch the arithmetic of the following steps and
+ * projections (GMF_PREC_FP32 / GMF_PREC_BF16 / GMF_PREC_BF16X3) on the same
+ * iterate and moments, e.g. a context fitted in FP32 that projects new rows
+ * in BF16X3.  The bfloat16 precisions need a panel stride of 32 or 64
+ * (automatic for a context created with one, or cfg.panel_stride).
+ * Errors: GMF_EINVAL (unknown precision, panel stride, tile_waves = 8 not
+ * available for it). */
 int gmf_set_precision(void* ctx, int32_t precision);
 
 /* gmf_fit -- run epochs of R*S steps (one epoch = R sweeps over J_1..J_S) up

@@ -121,7 +121,9 @@ std::string check_config(const gmf_config* c) {
     return "Gaussian family supports the identity link only";
   if (c->family != GMF_GAUSSIAN && c->link != GMF_LINK_LOG)
     return "Poisson and NB families support the log link only";
-  if (c->precision != GMF_PREC_FP32 && c->precision != GMF_PREC_BF16) return "unknown precision";
+  if (c->precision != GMF_PREC_FP32 && c->precision != GMF_PREC_BF16 &&
+      c->precision != GMF_PREC_BF16X3)
+    return "unknown precision";
   if (!(c->phi > 0) || !(c->nb_alpha > 0)) return "phi and nb_alpha must be > 0";
   if (!(c->rate0 > 0) || !(c->decay >= 0) || !(c->tau > 0)) return "bad learning-rate parameters";
   if (!(c->alpha1 > 0 && c->alpha1 <= 1) || !(c->alpha2 > 0 && c->alpha2 <= 1))
@@ -139,12 +141,12 @@ std::string check_config(const gmf_config* c) {
     return "tile_waves must be 0, 4 or 8";
   if (c->tile_waves == 8 &&
       !gmf::level_supports_nw8(c->precision, panel_stride_of(c)))
-    return "tile_waves = 8 needs panel stride 16 or 32 (FP32) or 32 (BF16)";
+    return "tile_waves = 8 needs panel stride 16 or 32 (FP32) or 32 (BF16, split BF16)";
   if (c->panel_stride != 0) {
     const int ps = c->panel_stride;
-    const bool ok = (c->precision == GMF_PREC_BF16) ? (ps == 32 || ps == 64)
+    const bool ok = (c->precision != GMF_PREC_FP32) ? (ps == 32 || ps == 64)
                                                     : (ps == 16 || ps == 32 || ps == 48 || ps == 64);
-    if (!ok) return "panel_stride must be 0, 16, 32, 48 or 64 (BF16: 32 or 64)";
+    if (!ok) return "panel_stride must be 0, 16, 32, 48 or 64 (BF16, split BF16: 32 or 64)";
     if (ps < c->p + c->q + c->d) return "panel_stride must be >= p + q + d";
   }
   return "";
@@ -180,7 +182,18 @@ int ilog2_ceil(int64_t x) {
 int panel_stride_of(const gmf_config* c) {
   const int k = c->p + c->q + c->d;
   if (c->panel_stride > 0) return c->panel_stride;
-  return (c->precision == GMF_PREC_BF16) ? round_up(k, 32) : round_up(k, 16);
+  return (c->precision != GMF_PREC_FP32) ? round_up(k, 32) : round_up(k, 16);
+}
+
+// Wavefronts per tile workgroup.  8-wavefront tiles halve each wavefront's
+// share of a row group: they pay off when tiles hold several row groups or
+// when the 4-wavefront FP32 tile would spill registers (stride 32);
+// single-group tiles of small blocks are latency-bound and run faster with 4.
+// tile_waves (4 or 8) overrides the rule.
+int tile_waves_for(int prec, int KP, int rpw, int tile_waves) {
+  if (tile_waves == 4 || !gmf::level_supports_nw8(prec, KP)) return 4;
+  if (tile_waves == 8) return 8;
+  return ((prec == GMF_PREC_FP32 && KP >= 32) || rpw >= 2 * gmf::kRowGroup) ? 8 : 4;
 }
 
 TuneKey tune_key(const gmf_config* c) {
@@ -236,13 +249,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
     P.nrr[r] = (nr + rpw - 1) / rpw;
   }
   P.rr_max = *std::max_element(P.nrr.begin(), P.nrr.end());
-  // 8-wavefront tiles halve each wavefront's share of a row group: they pay
-  // off when tiles hold several row groups or when the 4-wavefront FP32 tile
-  // would spill registers (stride 32); single-group tiles of small blocks are
-  // latency-bound and run faster with 4.
-  if (c->tile_waves == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) P.nw = 4;
-  else if (c->tile_waves == 8) P.nw = 8;
-  else P.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || P.rpw[0] >= 2 * gmf::kRowGroup) ? 8 : 4;
+  P.nw = tile_waves_for(P.prec, P.KP, P.rpw[0], c->tile_waves);
   P.ct_max = nct_max;
   P.slot_u = P.slot_v = P.slot_dev = 0; P.dev_tiles = 0;
   for (int r = 0; r < P.R; ++r)
@@ -787,15 +794,16 @@ int gmf_set_precision(void* ctx, int32_t precision) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   Ctx* c = as_ctx(ctx);
   Plan& P = c->P;
-  if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16) return fail(GMF_EINVAL, "unknown precision");
-  const bool ok = (precision == GMF_PREC_BF16) ? (P.KP == 32 || P.KP == 64) : true;
+  if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16 && precision != GMF_PREC_BF16X3)
+    return fail(GMF_EINVAL, "unknown precision");
+  const bool ok = (precision != GMF_PREC_FP32) ? (P.KP == 32 || P.KP == 64) : true;
   if (!ok) return fail(GMF_EINVAL, "BF16 steps need panel stride 32 or 64 (set panel_stride at init)");
+  const int tw = c->cfg.tile_waves;
+  if (tw == 8 && !gmf::level_supports_nw8(precision, P.KP))
+    return fail(GMF_EINVAL, "tile_waves = 8 is not available for this precision and panel stride");
   P.prec = precision;
   c->cfg.precision = precision;
-  const int tw = c->cfg.tile_waves;
-  if (tw == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) P.nw = 4;
-  else if (tw == 8) P.nw = 8;
-  else P.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || P.rpw[0] >= 2 * gmf::kRowGroup) ? 8 : 4;
+  P.nw = tile_waves_for(P.prec, P.KP, P.rpw[0], tw);
   return GMF_OK;
 }
 
@@ -990,10 +998,7 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
   Q.nrr = (int)((n_new + Q.rpw - 1) / Q.rpw);
   // wavefronts per tile by the rule of the fit's plan, for the projection's tiles
-  const int tw = c->cfg.tile_waves;
-  if (tw == 4 || !gmf::level_supports_nw8(P.prec, P.KP)) Q.nw = 4;
-  else if (tw == 8) Q.nw = 8;
-  else Q.nw = ((P.prec == GMF_PREC_FP32 && P.KP >= 32) || Q.rpw >= 2 * gmf::kRowGroup) ? 8 : 4;
+  Q.nw = tile_waves_for(P.prec, P.KP, Q.rpw, c->cfg.tile_waves);
   Q.dev_rpw = dev_rows_per_wg((int)std::min<int64_t>(n_new, 1 << 30));
   Q.dev_tiles = 0;
   for (int s = 0; s < P.S; ++s) Q.dev_tiles += (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];

@@ -20,7 +20,9 @@ constexpr int kTileCols = kWaveCols * kTileWaves;
 constexpr int kRowGroup = 32;
 
 enum Family { kPoisson = 0, kNegBin = 1, kGaussian = 2 };
-enum Prec { kF32 = 0, kBF16 = 1 };
+// kBF16X3: bfloat16 MFMA on operands split into a high and a low bfloat16
+// part (x = hi + lo), three products per contraction (hi*hi + hi*lo + lo*hi).
+enum Prec { kF32 = 0, kBF16 = 1, kBF16X3 = 2 };
 
 struct FamilyArgs {
   float phi_inv;       // 1 / phi

@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libgmf.so")
 GMF_OK, GMF_EINVAL, GMF_EWORKSPACE, GMF_EDEVICE, GMF_ENUMERIC, GMF_ENOTCONV = 0, -1, -2, -3, -4, -5
 GMF_POISSON, GMF_NEGBIN, GMF_GAUSSIAN = 0, 1, 2
 GMF_LINK_LOG, GMF_LINK_IDENTITY = 0, 1
-GMF_PREC_FP32, GMF_PREC_BF16 = 0, 1
+GMF_PREC_FP32, GMF_PREC_BF16, GMF_PREC_BF16X3 = 0, 1, 2
 GMF_Y_INT32, GMF_Y_FLOAT32 = 0, 1
 
 FAMILY_CODES = {"poisson": GMF_POISSON, "negbin": GMF_NEGBIN, "gaussian": GMF_GAUSSIAN}
 LINK_CODES = {"log": GMF_LINK_LOG, "identity": GMF_LINK_IDENTITY}
-PREC_CODES = {"fp32": GMF_PREC_FP32, "bf16": GMF_PREC_BF16}
+PREC_CODES = {"fp32": GMF_PREC_FP32, "bf16": GMF_PREC_BF16, "bf16x3": GMF_PREC_BF16X3}
 
 
 class gmf_config(C.Structure):
@@ -386,7 +386,8 @@ class GMF:
         return gmf_fit(self.ctx, max_epochs, tol, eval_every)
 
     def set_precision(self, precision):
-        """gmf_set_precision: 'fp32' or 'bf16' for the following steps."""
+        """gmf_set_precision: 'fp32', 'bf16' or 'bf16x3' for the following steps
+        and projections."""
         _check(load_library().gmf_set_precision(self.ctx, PREC_CODES[precision]))
 
     def run(self, epochs, eval_every=1, trace=True):

@@ -10,6 +10,14 @@ Tolerances (norm-wise relative error, max|x - ref| / max|ref|):
   * Final deviance after several epochs: 1e-4.
   * BF16 path: errors are reported per output; the final deviance is gated
     at 1e-3 relative on the small Poisson case.
+  * Split BF16 path (BF16X3): every operand keeps about 16 mantissa bits
+    (|x - hi - lo| <= 2^-18 |x|) and only the lo*lo product is dropped, so a
+    product is off by at most about 2^-17 relative, 128 times float32's
+    operand rounding.  Parameters after one step: 1e-4 (10x the FP32 gate).
+    Moments: the gradient sums cancel (signed D1), so their error is relative
+    to sum |D1 P|, which exceeds max |G| by about sqrt(K) for K summed
+    entries (16 at K = 260): 5e-4.  One epoch: 2e-3 (10x the FP32 trajectory
+    gate).  Final deviance after several epochs: 1e-4, as for FP32.
 """
 import sys
 
@@ -253,7 +261,7 @@ def test_run_with_overlapped_deviance_equals_step_then_deviance():
     g2.close()
 
 
-@pytest.mark.parametrize("precision,d", [("fp32", 10), ("fp32", 20), ("bf16", 10)])
+@pytest.mark.parametrize("precision,d", [("fp32", 10), ("fp32", 20), ("bf16", 10), ("bf16x3", 10)])
 def test_eight_wave_tiles_equal_four_wave_tiles(precision, d):
     """The 8-wavefront tile splits each 32-row group between two wavefronts
     but keeps every product and sum of the step in the same order: the
@@ -292,3 +300,44 @@ def test_precision_switch():
         g16.set_precision("bf16")
     for g in (gb, gf, g16):
         g.close()
+
+
+@pytest.mark.parametrize("family,n,m,d,R,S", [
+    ("poisson", 1000, 700, 5, 3, 2),     # several row ranges and a ragged column strip
+    ("negbin", 517, 389, 12, 2, 3),      # ragged everything
+    ("gaussian", 300, 260, 20, 2, 2),
+    ("negbin", 260, 200, 40, 2, 2),      # k = 44 -> panel stride 64
+])
+def test_bf16x3_first_step(family, n, m, d, R, S):
+    pr = gen_tiny(family, n=n, m=m, d=d, p=2, q=2, R=R, S=S, seed=1701, weights=True)
+    say(f"bf16x3 first step {family} n={n} m={m} d={d}")
+    lam = (0.2, 0.3, 0.7, 0.5)
+    o = oracle_for(pr, lam=lam)
+    g = gpu_for(pr, precision="bf16x3", lam=lam)
+    dev_o = o.step()
+    g.step(1)
+    errs = compare_state(g, o, 5e-4, f"bf16x3 {family}")
+    print("bf16x3 one-step relative errors:", errs)
+    for k in ("B", "Gamma", "U", "V"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert rel_err([g.block_deviance(1)[0]], [dev_o]) <= 1e-4
+    g.close()
+
+
+def test_bf16x3_reaches_oracle_deviance():
+    pr = gen_poisson_small()
+    say("bf16x3 c1: one epoch, final deviance after 20 epochs")
+    o = oracle_for(pr)
+    g = gpu_for(pr, precision="bf16x3")
+    o.epoch()
+    g.step(pr.R * pr.S)
+    errs = compare_state(g, o, 2e-3, "bf16x3 c1 epoch")
+    print("bf16x3 one-epoch relative errors:", errs)
+    for _ in range(19):
+        o.epoch()
+    g.step(19 * pr.R * pr.S)
+    dg, _ = g.deviance()
+    d_o = o.full_deviance()
+    print("bf16x3 final deviance rel err:", abs(dg - d_o) / d_o)
+    assert abs(dg - d_o) / d_o <= 1e-4
+    g.close()
