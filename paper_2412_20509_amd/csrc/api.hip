@@ -982,9 +982,8 @@ namespace {
 
 struct ProjPlan {
   int64_t n_new = 0;
-  int rpw = 0, nrr = 0, dev_rpw = 0, dev_tiles = 0, upd_sub = 1, upd_per_step = 0, nw = 4;
-  int64_t slot_u = 0;
-  size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_Upart, o_devpart, o_iota, o_zero, o_rowbase,
+  int dev_rpw = 0, dev_tiles = 0;
+  size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
       o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, o_pcolorig, total;
 };
@@ -993,22 +992,9 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   const Plan& P = c->P;
   if (n_new < 1 || n_new > ((int64_t)1 << 31) - 1) return false;
   Q.n_new = n_new;
-  int rpw = round_up((int)std::min<double>(2048.0, std::ceil((double)n_new * P.ct_max / kTilesPerStepTarget)),
-                     gmf::kRowGroup);
-  Q.rpw = std::max(gmf::kRowGroup, std::min(rpw, 2048));
-  Q.nrr = (int)((n_new + Q.rpw - 1) / Q.rpw);
-  // wavefronts per tile by the rule of the fit's plan, for the projection's tiles
-  Q.nw = tile_waves_for(P.prec, P.KP, Q.rpw, c->cfg.tile_waves);
   Q.dev_rpw = dev_rows_per_wg((int)std::min<int64_t>(n_new, 1 << 30));
   Q.dev_tiles = 0;
   for (int s = 0; s < P.S; ++s) Q.dev_tiles += (int)((n_new + Q.dev_rpw - 1) / Q.dev_rpw) * P.nct[s];
-  Q.slot_u = ((int64_t)P.ct_max * n_new * 2 * P.KU + 63) / 64 * 64;
-  {
-    const int64_t chunks = (n_new + P.row_chunk - 1) / P.row_chunk;
-    const int64_t per = (int64_t)kUpdPerTile * Q.nrr * P.ct_max;
-    Q.upd_sub = (int)std::max<int64_t>(1, (chunks + per - 1) / per);
-    Q.upd_per_step = upd_workgroups((int)n_new, 0, P.row_chunk, P.col_chunk, Q.upd_sub, true);
-  }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   Q.o_Yb = take(sizeof(float) * (size_t)n_new * P.LDtot);
@@ -1016,8 +1002,6 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.o_Pcol = take(sizeof(float) * (size_t)P.m * P.KP);
   Q.o_Grow = take(sizeof(double) * (size_t)n_new * P.KU);
   Q.o_Hrow = take(sizeof(double) * (size_t)n_new * P.KU);
-  Q.o_Upart = take(sizeof(float) * (size_t)Q.slot_u * 2);
-  Q.o_devpart = take(sizeof(double) * 64);
   Q.o_iota = take(sizeof(int) * (size_t)n_new);
   Q.o_zero = take(sizeof(int) * (size_t)n_new);
   Q.o_rowbase = take(sizeof(int64_t));
@@ -1215,36 +1199,23 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
     if (epoch_ms_host) epoch_ms_host[0] = ms_since(t_start);
   }
 
-  // ---- the row-side steps: tiles of step t, then its row updates
-  gmf::LevelArgs a = level_args(c);
-  a.Y = Yb; a.W = nullptr; a.Prow = Prow; a.Pcol = Pcol;
-  a.Grow = Grow; a.Hrow = Hrow; a.Gcol = nullptr; a.Hcol = nullptr;
-  a.Upart = reinterpret_cast<float*>(at(Q.o_Upart));
-  a.Vpart = nullptr;
-  a.devpart = reinterpret_cast<double*>(at(Q.o_devpart));
-  a.slot_u_elems = Q.slot_u; a.slot_v_elems = 0; a.slot_dev_elems = 0;
-  a.rr_max = Q.nrr;
-  a.upd_sub = Q.upd_sub;
-  a.upd_per_step = Q.upd_per_step;
-  a.row_only = 1;
-  a.trace = nullptr;
-  const int T = Q.nrr * P.ct_max;
+  // ---- the row-side steps: one launch per step, each wavefront steps its own
+  // rows over the whole column block (project.hip)
+  const gmf::LevelArgs la = level_args(c);
+  gmf::ProjStepArgs pa{};
+  pa.Prow = Prow; pa.Grow = Grow; pa.Hrow = Hrow; pa.n = n_new;
+  pa.p = P.p; pa.q = P.q; pa.KU = P.KU;
+  pa.lam_A = la.lam_A; pa.lam_U = la.lam_U; pa.a1 = la.a1; pa.a2 = la.a2; pa.damping = la.damping;
+  pa.f = la.f; pa.err_flag = la.err_flag;
   for (int e = 0; e < epochs; ++e) {
     for (int k = 0; k < P.S; ++k) {
       const int64_t t = (int64_t)e * P.S + k + 1;
-      gmf::LevelStep stp;
-      stp.r = 0; stp.s = k; stp.slot = (int)(t & 1);
-      stp.n_b = (int)n_new; stp.m_b = P.mcols[k];
-      stp.n_rr = Q.nrr; stp.n_ct = P.nct[k]; stp.rpw = Q.rpw;
-      stp.ldy = P.ld[k]; stp.ro = 0; stp.co = P.co[k]; stp.pad = 0;
-      stp.yoff = (int64_t)n_new * P.coP[k];
-      stp.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
-      stp.t = t;
-      a.steps[0] = stp;
-      a.n_tile_steps = 1; a.n_upd_steps = 0;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, Q.nw, a, T, st));
-      a.n_tile_steps = 0; a.n_upd_steps = 1;
-      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, false, Q.nw, a, Q.upd_per_step, st));
+      pa.Y = Yb + (int64_t)n_new * P.coP[k];
+      pa.ldy = P.ld[k]; pa.m_b = P.mcols[k];
+      pa.Pcol = Pcol + (int64_t)P.co[k] * P.KP;
+      pa.scale_m = (double)P.m / P.mcols[k];
+      pa.stepsize = learning_rate(c->cfg, t) * bias_factor(c->cfg, t);
+      HIP_TRY(gmf::launch_project_step(P.prec, P.fam, P.KP, pa, st));
     }
     if (dev_trace_host) {
       const int rc = proj_dev(dev_trace_host + e + 1);

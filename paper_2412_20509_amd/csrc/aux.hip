@@ -410,9 +410,13 @@ static hipError_t launch_dev_kp(int KP, const DevArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------ count-only part --
+// c(y) for the integer counts below kTileThreads comes from a table formed by
+// the workgroup (one float64 evaluation per thread, the same function, so the
+// values are identical); other counts are evaluated directly.
 template <int FAM>
 __global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
   __shared__ double red[kTileThreads];
+  __shared__ double ctab[kTileThreads];
   const int tile = blockIdx.x;
   const int blk = a.tile_block[tile];
   const int local = tile - a.tile_first[blk];
@@ -426,6 +430,8 @@ __global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
   const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
   const int col0 = ct * kTileCols, col_end = min(m_b, col0 + kTileCols);
   const double alpha = (double)a.f.nb_alpha;
+  ctab[threadIdx.x] = count_part<FAM>((double)threadIdx.x, alpha);
+  __syncthreads();
   double acc = 0.0;
   // thread t: column col0 + t % 128 of rows row0 + t / 128, row0 + t / 128 + 2, ...
   const int c = col0 + (int)(threadIdx.x % kTileCols);
@@ -433,7 +439,11 @@ __global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
     for (int r = row0 + (int)(threadIdx.x / kTileCols); r < row_end; r += kTileThreads / kTileCols) {
       const int64_t idx = (int64_t)r * ldy + c;
       const double w = W ? (double)W[idx] : 1.0;
-      acc += w * count_part<FAM>((double)Y[idx], alpha);
+      const float y = Y[idx];
+      const int yi = (int)y;
+      const double cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
+                                                                        : count_part<FAM>((double)y, alpha);
+      acc += w * cy;
     }
   red[threadIdx.x] = acc;
   __syncthreads();

@@ -138,6 +138,25 @@ hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const 
                         hipEvent_t ev_stop = nullptr);
 bool level_supports_nw8(int prec, int KP);
 
+// One row-only step of the projection (project.hip): column block J_s of the
+// new rows.  Y: the block's counts (n rows, stride ldy, m_b columns; columns
+// m_b .. ldy-1 are zero); Prow: the new rows' panel (n x KP, updated in place);
+// Pcol: the block's frozen column panel rows (m_b x KP); Grow, Hrow: the rows'
+// EMAs (n x KU, KU = q + d); scale_m = m / m_b; stepsize = rho_t alpha_t.
+struct ProjStepArgs {
+  const float* Y;
+  int ldy, m_b;
+  float* Prow;
+  const float* Pcol;
+  double* Grow; double* Hrow;
+  int64_t n;
+  int p, q, KU;
+  double scale_m, lam_A, lam_U, a1, a2, damping, stepsize;
+  FamilyArgs f;
+  int* err_flag;
+};
+hipError_t launch_project_step(int prec, int fam, int KP, const ProjStepArgs& a, hipStream_t s);
+
 struct DevArgs {
   const float* Y; const float* W;
   const float* Prow; const float* Pcol;
