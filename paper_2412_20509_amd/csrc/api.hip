@@ -207,11 +207,11 @@ int tune_lookup(const gmf_config* c) {
   return it == g_tune.end() ? 0 : it->second.tile_rows;
 }
 
-// Update workgroups of one step: row part, column part (none for row-only
-// projection steps) and the block-deviance workgroup.
-int upd_workgroups(int n_b, int m_b, int row_chunk, int col_chunk, int sub, bool row_only) {
+// Update workgroups of one step: row part, column part and the
+// block-deviance workgroup.
+int upd_workgroups(int n_b, int m_b, int row_chunk, int col_chunk, int sub) {
   const int rw = ((n_b + row_chunk - 1) / row_chunk + sub - 1) / sub;
-  const int cw = row_only ? 0 : ((m_b + col_chunk - 1) / col_chunk + sub - 1) / sub;
+  const int cw = ((m_b + col_chunk - 1) / col_chunk + sub - 1) / sub;
   return rw + cw + 1;
 }
 
@@ -340,7 +340,7 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   for (int r = 0; r < P.R; ++r)
     for (int s = 0; s < P.S; ++s)
       P.upd_per_step = std::max(P.upd_per_step, upd_workgroups(P.nrows[r], P.mcols[s], P.row_chunk,
-                                                              P.col_chunk, P.upd_sub, false));
+                                                              P.col_chunk, P.upd_sub));
   P.total = o;
 }
 
@@ -461,7 +461,6 @@ gmf::LevelArgs level_args(const Ctx* c) {
   a.trace_cap = c->trace_cap;
   a.trace_base = 0;
   a.launch_id = 0;
-  a.row_only = 0;
   a.n_tile_steps = a.n_upd_steps = 0;
   return a;
 }

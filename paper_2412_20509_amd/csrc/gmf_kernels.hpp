@@ -97,7 +97,6 @@ struct LevelArgs {
   // optional per-workgroup trace: 8 x u64 per workgroup (see gmf_set_trace)
   unsigned long long* trace; long long trace_cap; unsigned long long trace_base;
   unsigned long long launch_id;
-  int row_only;        // projection: no column-side sums or updates
   // the steps of this launch: [0, n_tile_steps) run tiles, the next
   // n_upd_steps run their updates
   int n_tile_steps, n_upd_steps;

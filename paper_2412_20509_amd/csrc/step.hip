@@ -85,7 +85,6 @@ struct TileView {
   float* Upart;                    // this strip's partial rows: [n_b][2KU]
   float* Vpart;                    // this range's partial cols: [m_b][2KV]
   unsigned long long* stamps;      // optional: 3 timestamps (profiling), or null
-  bool row_only;                   // skip the column-side (V) sums
 };
 
 template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool HAS_W>
@@ -288,16 +287,15 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         }
       }
       // transposed copies for the V side: sT[h][col][row]
-      if (!tv.row_only)
-        for (int C = 0; C < 2; ++C)
-          for (int v = 0; v < 4; ++v) {
-            const int cc = 16 * C + 4 * g + v;
-            const TE h1 = (TE)d1[C][v], h2 = (TE)d2[C][v];
-            sT[0][cc][lrow] = h1;
-            sT[1][cc][lrow] = h2;
-            if constexpr (SPLIT) sT[2][cc][lrow] = lo_bf16(d1[C][v], h1);
-            if constexpr (SPLIT_H) sT[SPLIT_H ? 3 : 2][cc][lrow] = lo_bf16(d2[C][v], h2);
-          }
+      for (int C = 0; C < 2; ++C)
+        for (int v = 0; v < 4; ++v) {
+          const int cc = 16 * C + 4 * g + v;
+          const TE h1 = (TE)d1[C][v], h2 = (TE)d2[C][v];
+          sT[0][cc][lrow] = h1;
+          sT[1][cc][lrow] = h2;
+          if constexpr (SPLIT) sT[2][cc][lrow] = lo_bf16(d1[C][v], h1);
+          if constexpr (SPLIT_H) sT[SPLIT_H ? 3 : 2][cc][lrow] = lo_bf16(d2[C][v], h2);
+        }
       // U side: G_U[row][o] = sum over this wavefront's cols of D1[row][col] P[col][o]
       for (int ob = 0; ob < NB; ++ob) {
         ug[rr][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -335,7 +333,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     if constexpr (WANT_DEV) dev_acc += (double)dev_grp;
     if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
-    for (int cc = 0; cc < NC && !tv.row_only; ++cc) {
+    for (int cc = 0; cc < NC; ++cc) {
       const int C = (NW == 8) ? R0 : cc;
       if constexpr (PREC == kF32) {
         const float4 ta = *reinterpret_cast<const float4*>(&sT[0][16 * C + l16][8 * g]);
@@ -404,7 +402,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
 
   if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
   // ---- V-side partial of this row range
-  for (int cc = 0; cc < NC && !tv.row_only; ++cc) {
+  for (int cc = 0; cc < NC; ++cc) {
     const int C = (NW == 8) ? R0 : cc;
     for (int v = 0; v < 4; ++v) {
       const int col = colw + 16 * C + 4 * g + v;
@@ -559,7 +557,6 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     tv.Upart = a.Upart + (int64_t)st.slot * a.slot_u_elems + (int64_t)ct * n_b * (2 * a.KU);
     tv.Vpart = a.Vpart + (int64_t)st.slot * a.slot_v_elems + (int64_t)rr * m_b * (2 * a.KV);
     tv.stamps = stamps;
-    tv.row_only = a.row_only != 0;
     const FamilyConst fc = family_const(a.f);
     const double dev =
         tv.W ? compute_tile<PREC, FAM, KP, WANT_DEV, NW, true>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile)
@@ -573,7 +570,7 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
   const int sub = a.upd_sub;
   const int rspan = a.row_chunk * sub, cspan = a.col_chunk * sub;
   const int nrw = (n_b + rspan - 1) / rspan;
-  const int ncw = a.row_only ? 0 : (m_b + cspan - 1) / cspan;
+  const int ncw = (m_b + cspan - 1) / cspan;
   if (u < nrw) {
     const int end = min(n_b, (u + 1) * rspan);
     for (int r0 = u * rspan; r0 < end; r0 += a.row_chunk) {
