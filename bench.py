@@ -71,7 +71,7 @@ def make_gmf(pr, precision):
 def recorded_traffic():
     """HBM bytes per launch of the headline step kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
-    changed since those counters were taken."""
+    (step.hip, family.hpp, mfma.hpp) changed since those counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_traffic_level_kernel_nb10000x2000_nb100000x5000.md")
@@ -81,7 +81,7 @@ def recorded_traffic():
     if not m:
         return None
     h = hashlib.sha256()
-    for f in ("step.hip", "family.hpp"):
+    for f in ("step.hip", "family.hpp", "mfma.hpp"):
         with open(os.path.join(ROOT, "paper_2412_20509_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return float(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
