@@ -17,8 +17,8 @@ Printed JSON line:
                     full deviance that is first within 1e-4 (relative) of D*,
                     the FP64 oracle's deviance after 200 epochs of the same
                     seeded schedule (tests/golden), completed on the device;
-                    the deviance of every epoch is evaluated on a second
-                    stream overlapped with the next epoch's steps
+                    the deviance of every epoch is evaluated on the device
+                    after the epoch's steps, in order on the same stream
   roofline          dominant kernel (the fused tile kernel): algorithmic
                     bytes per launch / mean launch time from HIP events stamped
                     by the launches themselves on the library's stream, against
@@ -110,7 +110,7 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch, polish=0):
     g = make_gmf(pr, precision)
     torch.cuda.synchronize()
     # the timed region: `epochs` epochs, the full deviance of every epoch
-    # evaluated on a second stream from a snapshot of the panels (gmf_run)
+    # evaluated after the epoch's steps on the same stream (gmf_run)
     t0 = time.perf_counter()
     if polish > 0:
         devs, ms = g.run(epochs - polish, eval_every=1)

@@ -90,16 +90,20 @@ typedef struct gmf_config {
   int32_t tile_waves;   /* wavefronts per step tile: 4 (each takes 32 rows x 32
                            columns of a 32-row group) or 8 (16 rows x 32
                            columns each, half the per-wavefront work; FP32
-                           stride 16/32, BF16 32 only); 0 = automatic: 8 when
-                           available and tiles span several 32-row groups or
-                           the FP32 stride is 32, else 4                     */
+                           stride 16/32, BF16 32 only); 0 = automatic: 8 for
+                           the FP32 stride 32 and for split BF16 tiles of
+                           several 32-row groups, else 4                     */
+  int32_t eval_overlap; /* gmf_run's deviance evaluations: 0 = on the
+                           context's stream after the epoch's steps (full
+                           grid); 1 = on a second stream from a copy of the
+                           panels, overlapped with the following steps       */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
  * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0,
- * tile_waves=0. */
+ * tile_waves=0, eval_overlap=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -158,8 +162,10 @@ int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
 
 /* gmf_run -- run `epochs` epochs (R*S steps each) and, every eval_every
  * epochs when dev_trace_host is not NULL, the full deviance (as gmf_deviance)
- * of the iterate at that point, evaluated on a second stream from a copy of
- * the panels so that it overlaps the following steps.  dev_trace_host
+ * of the iterate at that point: on the context's stream between the epochs
+ * (cfg.eval_overlap = 0), or on a second stream from a copy of the panels so
+ * that it overlaps the following steps (cfg.eval_overlap = 1); the values are
+ * the same.  Either way nothing waits for the host.  dev_trace_host
  * receives epochs/eval_every values; eval_ms_host (may be NULL) the time at
  * which each evaluation finished on the device, in ms since the call's work
  * began.  No early stop.  Needs no more workspace than gmf_workspace_bytes

@@ -139,6 +139,7 @@ std::string check_config(const gmf_config* c) {
     return "tile_rows must be 0 or a multiple of 32 up to 4096";
   if (c->tile_waves != 0 && c->tile_waves != 4 && c->tile_waves != 8)
     return "tile_waves must be 0, 4 or 8";
+  if (c->eval_overlap != 0 && c->eval_overlap != 1) return "eval_overlap must be 0 or 1";
   if (c->tile_waves == 8 &&
       !gmf::level_supports_nw8(c->precision, panel_stride_of(c)))
     return "tile_waves = 8 needs panel stride 16 or 32 (FP32) or 32 (BF16, split BF16)";
@@ -186,14 +187,18 @@ int panel_stride_of(const gmf_config* c) {
 }
 
 // Wavefronts per tile workgroup.  8-wavefront tiles halve each wavefront's
-// share of a row group: they pay off when tiles hold several row groups or
-// when the 4-wavefront FP32 tile would spill registers (stride 32);
-// single-group tiles of small blocks are latency-bound and run faster with 4.
-// tile_waves (4 or 8) overrides the rule.
+// share of a row group and need fewer registers per wavefront: they pay off
+// where the 4-wavefront tile would spill (FP32 stride 32, split BF16 on tiles
+// of several row groups).  Elsewhere 4 run faster: single-group tiles of small
+// blocks are latency-bound, and the 4-wavefront BF16 tile of the
+// 100000 x 5000 fit runs 584 epochs/s against 454 with 8.  tile_waves (4 or
+// 8) overrides the rule.
 int tile_waves_for(int prec, int KP, int rpw, int tile_waves) {
   if (tile_waves == 4 || !gmf::level_supports_nw8(prec, KP)) return 4;
   if (tile_waves == 8) return 8;
-  return ((prec == GMF_PREC_FP32 && KP >= 32) || rpw >= 2 * gmf::kRowGroup) ? 8 : 4;
+  const bool spill = (prec == GMF_PREC_FP32 && KP >= 32) ||
+                     (prec == GMF_PREC_BF16X3 && rpw >= 2 * gmf::kRowGroup);
+  return spill ? 8 : 4;
 }
 
 TuneKey tune_key(const gmf_config* c) {
@@ -1317,11 +1322,14 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
   const Plan& P = c->P;
   const int64_t per_epoch = (int64_t)P.R * P.S;
   const int nev = dev_trace_host ? epochs / eval_every : 0;
+  const bool overlap = c->cfg.eval_overlap != 0;
+  hipStream_t es = overlap ? c->side : c->st;   // the evaluations' stream
   if (nev > 0) {
-    if (!c->side) {
+    if (overlap && !c->side) {
       HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-      HIP_TRY(hipEventCreate(&c->ev_start));
+      es = c->side;
     }
+    if (!c->ev_start) HIP_TRY(hipEventCreate(&c->ev_start));
     while ((int)c->ev_done.size() < nev) {
       hipEvent_t a = nullptr, b = nullptr;
       HIP_TRY(hipEventCreateWithFlags(&a, hipEventDisableTiming));
@@ -1339,7 +1347,7 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
   int ev_i = 0, drained = 0;
   auto drain = [&](int upto) -> int {   // copy evaluations [drained, upto) to the host
     if (upto <= drained) return GMF_OK;
-    HIP_TRY(hipStreamSynchronize(c->side));
+    HIP_TRY(hipStreamSynchronize(es));
     for (int i = drained; i < upto; ++i)
       HIP_TRY(hipMemcpy(&res[8 * (size_t)i], evring + 8 * (i % kEvRing), 8 * sizeof(double),
                         hipMemcpyDeviceToHost));
@@ -1350,12 +1358,22 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
     int rc = enqueue_steps(c, per_epoch);
     if (rc != GMF_OK) return rc;
     if (nev == 0 || e % eval_every != 0 || ev_i >= nev) continue;
-    const int slot = ev_i & 1;
-    if (ev_i >= 2) HIP_TRY(hipStreamWaitEvent(c->st, c->ev_done[ev_i - 2], 0));
     if (ev_i - drained >= kEvRing) {
       rc = drain(ev_i - kEvRing + 1);
       if (rc != GMF_OK) return rc;
     }
+    if (!overlap) {   // in order after the epoch's steps, the whole device
+      gmf::DevArgs da = dev_args(c);
+      da.partial = part2;
+      HIP_TRY(gmf::launch_deviance(P.fam, P.KP, da, c->st));
+      HIP_TRY(gmf::launch_finalize(da.partial, P.dev_tiles, nullptr, 0, c->at<int>(P.o_flag),
+                                   evring + 8 * (ev_i % kEvRing), c->st));
+      HIP_TRY(hipEventRecord(c->ev_done[ev_i], c->st));
+      ++ev_i;
+      continue;
+    }
+    const int slot = ev_i & 1;
+    if (ev_i >= 2) HIP_TRY(hipStreamWaitEvent(c->st, c->ev_done[ev_i - 2], 0));
     float* srow = snap + slot * snap_elems;
     float* scol = srow + (size_t)P.n * P.KP;
     HIP_TRY(hipMemcpyAsync(srow, c->at<float>(P.o_Prow), sizeof(float) * (size_t)P.n * P.KP,

@@ -42,7 +42,7 @@ class gmf_config(C.Structure):
         ("damping", C.c_double), ("eps", C.c_double), ("eta_max", C.c_double),
         ("seed", C.c_uint64),
         ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
-        ("panel_stride", C.c_int32), ("tile_waves", C.c_int32),
+        ("panel_stride", C.c_int32), ("tile_waves", C.c_int32), ("eval_overlap", C.c_int32),
     ]
 
 
@@ -314,6 +314,7 @@ class FitConfig:
     skip_block_deviance: int = 0
     panel_stride: int = 0
     tile_waves: int = 0
+    eval_overlap: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -334,6 +335,7 @@ class FitConfig:
         c.skip_block_deviance = self.skip_block_deviance
         c.panel_stride = self.panel_stride
         c.tile_waves = self.tile_waves
+        c.eval_overlap = self.eval_overlap
         return c
 
 

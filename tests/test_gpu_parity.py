@@ -234,14 +234,16 @@ def test_gaussian_full_batch_reaches_truncated_svd():
     g.close()
 
 
-def test_run_with_overlapped_deviance_equals_step_then_deviance():
-    """gmf_run evaluates the deviance from a snapshot on a second stream; the
-    values equal gmf_deviance after the same epochs, the iterate equals plain
-    stepping, and the device completion times increase."""
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_run_with_deviance_equals_step_then_deviance(overlap):
+    """gmf_run evaluates the deviance in order on the context's stream, or from
+    a snapshot on a second stream; the values equal gmf_deviance after the same
+    epochs, the iterate equals plain stepping, and the device completion times
+    increase."""
     from synth import make_problem
-    print("[case] gmf_run vs step + deviance, Poisson 1000x500", flush=True)
+    print(f"[case] gmf_run (overlap={overlap}) vs step + deviance, Poisson 1000x500", flush=True)
     pr = make_problem("c1")
-    g1 = gpu_for(pr)
+    g1 = gpu_for(pr, eval_overlap=overlap)
     g2 = gpu_for(pr)
     tr, ms = g1.run(5, eval_every=2)
     ref = []
