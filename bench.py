@@ -34,7 +34,7 @@ Printed JSON line:
   warm_start        learned warm start of 1,000,000 new rows: epochs and
                     seconds to 1e-4 of the converged projection deviance for a
                     cold start and for the encoder's bfloat16 predictions, with
-                    FP32 and with split-BF16 projection steps
+                    FP32, split-BF16 and BF16 projection steps
 """
 import argparse
 import json
@@ -243,16 +243,21 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     _, _, trw, msw, fb = g.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
-    # the same warm start with split-bfloat16 projection steps, on a context
-    # holding the same fitted parameters
-    log("warm start: warm arm, split bfloat16 steps")
-    gx = make_gmf(pr, "bf16x3")
-    gx.set_params(*g.params())
-    _, _, trx, msx, fbx = gx.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
-    gx.close()
+    # the same warm start with split-bfloat16 and bfloat16 projection steps on
+    # the same fitted context (panel stride 16: 16x16x16 bfloat16 products)
+    bfa = {}
+    for prec in ("bf16x3", "bf16"):
+        log(f"warm start: warm arm, {prec} steps")
+        g.set_precision(prec)
+        _, _, trx, msx, fbx = g.project_warm(Yd, Xd, cand, max_epochs, frozen=1, trace=True)
+        g.set_precision("fp32")
+        ex, tx = first_hit(trx, msx, dstar)
+        bfa[prec] = dict(epochs_to_1e4=ex, s_to_1e4=None if tx is None else tx / 1e3 + t_inf,
+                         deviance_start=trx[0], fallback_rows=fbx,
+                         final_rel_to_reference=abs(trx[-1] - dstar) / dstar,
+                         ms_per_epoch=(msx[-1] - msx[0]) / max_epochs)
     ec, tc = first_hit(trc, msc, dstar)
     ew, tw = first_hit(trw, msw, dstar)
-    ex, tx = first_hit(trx, msx, dstar)
     enc.close()
     g.close()
     return dict(
@@ -269,11 +274,8 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
                   s_to_1e4=None if tw is None else tw / 1e3 + t_inf,
                   deviance_start=trw[0], fallback_rows=fb,
                   ms_per_epoch=(msw[-1] - msw[0]) / max_epochs),
-        warm_bf16x3=dict(epochs_to_1e4=ex,
-                         s_to_1e4=None if tx is None else tx / 1e3 + t_inf,
-                         deviance_start=trx[0], fallback_rows=fbx,
-                         final_rel_to_reference=abs(trx[-1] - dstar) / dstar,
-                         ms_per_epoch=(msx[-1] - msx[0]) / max_epochs),
+        warm_bf16x3=bfa["bf16x3"],
+        warm_bf16=bfa["bf16"],
     )
 
 
@@ -466,6 +468,7 @@ def main():
         log(f"warm start: cold {warm['cold']['epochs_to_1e4']} epochs, "
             f"warm {warm['warm']['epochs_to_1e4']} epochs, "
             f"warm bf16x3 {warm['warm_bf16x3']['epochs_to_1e4']} epochs, "
+            f"warm bf16 {warm['warm_bf16']['epochs_to_1e4']} epochs, "
             f"{warm['warm']['fallback_rows']} fallback rows")
     batched = None
     if not args.no_batched:

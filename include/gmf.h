@@ -145,10 +145,13 @@ int gmf_step(void* ctx, int64_t nsteps);
 /* gmf_set_precision -- switch the arithmetic of the following steps and
  * projections (GMF_PREC_FP32 / GMF_PREC_BF16 / GMF_PREC_BF16X3) on the same
  * iterate and moments, e.g. a context fitted in FP32 that projects new rows
- * in BF16X3.  The bfloat16 precisions need a panel stride of 32 or 64
- * (automatic for a context created with one, or cfg.panel_stride).
- * Errors: GMF_EINVAL (unknown precision, panel stride, tile_waves = 8 not
- * available for it). */
+ * in BF16X3.  Block steps in the bfloat16 precisions need a panel stride of
+ * 32 or 64 (automatic for a context created with one, or cfg.panel_stride);
+ * at stride 16 (an FP32 context with p+q+d <= 16) a bfloat16 precision serves
+ * gmf_project / gmf_project_warm only (16x16x16 bfloat16 products), and
+ * gmf_step, gmf_fit, gmf_run and gmf_batch_init return GMF_EINVAL until the
+ * context is switched back to FP32.  Errors: GMF_EINVAL (unknown precision,
+ * panel stride, tile_waves = 8 not available for it). */
 int gmf_set_precision(void* ctx, int32_t precision);
 
 /* gmf_fit -- run epochs of R*S steps (one epoch = R sweeps over J_1..J_S) up

@@ -186,6 +186,11 @@ int panel_stride_of(const gmf_config* c) {
   return (c->precision != GMF_PREC_FP32) ? round_up(k, 32) : round_up(k, 16);
 }
 
+// Block steps exist for FP32 at every panel stride and for the bfloat16
+// precisions at strides 32 and 64; a context switched to a bfloat16 precision
+// at stride 16 projects rows only.
+bool steps_available(int prec, int KP) { return prec == GMF_PREC_FP32 || KP == 32 || KP == 64; }
+
 // Wavefronts per tile workgroup.  8-wavefront tiles halve each wavefront's
 // share of a row group and need fewer registers per wavefront: they pay off
 // where the 4-wavefront tile would spill (FP32 stride 32, split BF16 on tiles
@@ -501,6 +506,8 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
   const Plan& P = c->P;
   const bool want_dev = c->want_block_dev != 0;
   if (nsteps <= 0) return GMF_OK;
+  if (!steps_available(P.prec, P.KP))
+    return fail(GMF_EINVAL, "BF16 block steps need panel stride 32 or 64 (this context projects only)");
   std::vector<gmf::LevelStep> steps(nsteps);
   std::vector<int> level(nsteps);
   std::vector<int> lr(P.R, -1), ls(P.S, -1), lslot(P.nslot, -1);
@@ -800,10 +807,10 @@ int gmf_set_precision(void* ctx, int32_t precision) {
   Plan& P = c->P;
   if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16 && precision != GMF_PREC_BF16X3)
     return fail(GMF_EINVAL, "unknown precision");
-  const bool ok = (precision != GMF_PREC_FP32) ? (P.KP == 32 || P.KP == 64) : true;
-  if (!ok) return fail(GMF_EINVAL, "BF16 steps need panel stride 32 or 64 (set panel_stride at init)");
+  const bool ok = (precision != GMF_PREC_FP32) ? (P.KP == 16 || P.KP == 32 || P.KP == 64) : true;
+  if (!ok) return fail(GMF_EINVAL, "BF16 needs panel stride 16 (projections only), 32 or 64");
   const int tw = c->cfg.tile_waves;
-  if (tw == 8 && !gmf::level_supports_nw8(precision, P.KP))
+  if (tw == 8 && steps_available(precision, P.KP) && !gmf::level_supports_nw8(precision, P.KP))
     return fail(GMF_EINVAL, "tile_waves = 8 is not available for this precision and panel stride");
   P.prec = precision;
   c->cfg.precision = precision;
@@ -1546,6 +1553,8 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
     return fail(GMF_EWORKSPACE, "batch workspace NULL, misaligned or smaller than " +
                                     std::to_string(z.total) + " bytes");
   const Plan& P0 = as_ctx(ctxs[0])->P;
+  if (!steps_available(P0.prec, P0.KP))
+    return fail(GMF_EINVAL, "BF16 block steps need panel stride 32 or 64");
   for (int f = 0; f < nfits; ++f) {
     const Plan& P = as_ctx(ctxs[f])->P;
     if (P.prec != P0.prec || P.KP != P0.KP)

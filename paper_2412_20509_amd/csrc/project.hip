@@ -33,12 +33,23 @@ namespace {
 constexpr int kWaves = 4;      // wavefronts per workgroup
 constexpr int kChunk = 32;     // columns per chunk
 
+// D(16x16) += A(16x16) B(16x16), bfloat16 operands, float32 accumulation: lane
+// (i, g) holds A[i][4g .. 4g+3] and B[4g .. 4g+3][i] (the bfloat16 products
+// at panel stride 16).
+__device__ __forceinline__ floatx4 mfma_bf16_k16(bf16x4 a, bf16x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x4 to_bf16x4(floatx4 x) { return __builtin_convertvector(x, bf16x4); }
+__device__ __forceinline__ bf16x4 lo_bf16x4(floatx4 x, bf16x4 hi) {
+  return to_bf16x4(x - __builtin_convertvector(hi, floatx4));
+}
+
 // One chunk's loads: column panel rows and counts (float32, converted when used).
 template <int PREC, int KP, int RT>
 struct Chunk {
   static constexpr int NB = KP / 16;
   // eta's A operand: column c0 + 16C + l16, panel entries k (FP32: 4kk + g;
-  // bfloat16: 32kk + 8g .. +7)
+  // bfloat16: 32kk + 8g .. +7; bfloat16 at stride 16: 4g .. 4g+3)
   float pa[2][KP / 4];
   // U side B operand: column c0 + 16C + 4g + v, panel entry 16ob + l16
   float ub[2][4][NB];
@@ -55,6 +66,9 @@ __device__ __forceinline__ void load_chunk(const ProjStepArgs& a, int c0, int64_
     const float* pc = a.Pcol + (int64_t)col * KP;
     if constexpr (PREC == kF32) {
       for (int kk = 0; kk < KP / 4; ++kk) ch.pa[C][kk] = ok ? pc[4 * kk + g] : 0.f;
+    } else if constexpr (KP == 16) {
+      const float4 u = ok ? *reinterpret_cast<const float4*>(pc + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+      ch.pa[C][0] = u.x; ch.pa[C][1] = u.y; ch.pa[C][2] = u.z; ch.pa[C][3] = u.w;
     } else {
       for (int kk = 0; kk < KP / 32; ++kk) {
         float4 u = make_float4(0.f, 0.f, 0.f, 0.f), w = u;
@@ -96,14 +110,21 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
   if (r0 >= a.n) return;   // uniform over the wavefront
 
   // eta's B operand: the row panel of row r0 + 16 rt + l16, pre-step values
+  constexpr bool K16 = BF && KP == 16;   // bfloat16 products of K = 16
   float pb32[RT][(PREC == kF32) ? KP / 4 : 1];
-  bf16x8 pb16[RT][BF ? KP / 32 : 1], pb16l[RT][SPLIT ? KP / 32 : 1];
+  bf16x8 pb16[RT][(BF && !K16) ? KP / 32 : 1], pb16l[RT][(SPLIT && !K16) ? KP / 32 : 1];
+  bf16x4 pk[RT], pkl[RT];
   for (int rt = 0; rt < RT; ++rt) {
     const int64_t row = r0 + 16 * rt + l16;
     const bool row_ok = row < a.n;
     const float* pr = a.Prow + row * KP;
     if constexpr (PREC == kF32) {
       for (int kk = 0; kk < KP / 4; ++kk) pb32[rt][kk] = row_ok ? pr[4 * kk + g] : 0.f;
+    } else if constexpr (K16) {
+      const float4 u = row_ok ? *reinterpret_cast<const float4*>(pr + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const floatx4 x = {u.x, u.y, u.z, u.w};
+      pk[rt] = to_bf16x4(x);
+      if constexpr (SPLIT) pkl[rt] = lo_bf16x4(x, pk[rt]);
     } else {
       for (int kk = 0; kk < KP / 32; ++kk) {
         float4 u = make_float4(0.f, 0.f, 0.f, 0.f), w = u;
@@ -128,9 +149,25 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
   for (int c0 = 0; c0 < a.m_b; c0 += kChunk) {
     if (c0 + kChunk < a.m_b) load_chunk<PREC, KP, RT>(a, c0 + kChunk, r0, l16, g, nxt);
     // the chunk's column operands, converted once for all row tiles
-    bf16x8 ah[2][BF ? KP / 32 : 1], al[2][SPLIT ? KP / 32 : 1];
-    bf16x8 bh[BF ? NB : 1], bq[BF ? NB : 1], bhl[SPLIT ? NB : 1], bql[SPLIT_H ? NB : 1];
-    if constexpr (BF) {
+    bf16x8 ah[2][(BF && !K16) ? KP / 32 : 1], al[2][(SPLIT && !K16) ? KP / 32 : 1];
+    bf16x8 bh[(BF && !K16) ? NB : 1], bq[(BF && !K16) ? NB : 1], bhl[(SPLIT && !K16) ? NB : 1],
+        bql[(SPLIT_H && !K16) ? NB : 1];
+    // stride 16: per 16 columns C, A = the panel entries 4g .. 4g+3 of column
+    // c0 + 16C + l16 (eta), B = entry l16 of columns c0 + 16C + 4g .. +3 (G, H)
+    bf16x4 kah[2], kal[2], kbh[2], kbl[2], kqh[2], kql[2];
+    if constexpr (K16) {
+      for (int C = 0; C < 2; ++C) {
+        const floatx4 x = {cur.pa[C][0], cur.pa[C][1], cur.pa[C][2], cur.pa[C][3]};
+        kah[C] = to_bf16x4(x);
+        if constexpr (SPLIT) kal[C] = lo_bf16x4(x, kah[C]);
+        const floatx4 b = {cur.ub[C][0][0], cur.ub[C][1][0], cur.ub[C][2][0], cur.ub[C][3][0]};
+        const floatx4 bb = b * b;
+        kbh[C] = to_bf16x4(b);
+        kqh[C] = to_bf16x4(bb);
+        if constexpr (SPLIT) kbl[C] = lo_bf16x4(b, kbh[C]);
+        if constexpr (SPLIT_H) kql[C] = lo_bf16x4(bb, kqh[C]);
+      }
+    } else if constexpr (BF) {
       for (int C = 0; C < 2; ++C)
         for (int kk = 0; kk < KP / 32; ++kk) {
           const float* s = &cur.pa[C][8 * kk];
@@ -156,6 +193,12 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
         if constexpr (PREC == kF32) {
           for (int kk = 0; kk < KP / 4; ++kk) e = mfma_f32(cur.pa[C][kk], pb32[rt][kk], e);
+        } else if constexpr (K16) {
+          if constexpr (SPLIT) {   // the small products first
+            e = mfma_bf16_k16(kal[C], pk[rt], e);
+            e = mfma_bf16_k16(kah[C], pkl[rt], e);
+          }
+          e = mfma_bf16_k16(kah[C], pk[rt], e);
         } else {
           for (int kk = 0; kk < KP / 32; ++kk) {
             if constexpr (SPLIT) {   // the small products first
@@ -180,6 +223,23 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
               ug[rt][ob] = mfma_f32(d1[C][v], b, ug[rt][ob]);
               uh[rt][ob] = mfma_f32(d2[C][v], b * b, uh[rt][ob]);
             }
+      } else if constexpr (K16) {
+        // A = D1 (D2) of row l16, columns c0 + 16C + 4g .. +3 from the accumulators
+        for (int C = 0; C < 2; ++C) {
+          const floatx4 f1 = {d1[C][0], d1[C][1], d1[C][2], d1[C][3]};
+          const floatx4 f2 = {d2[C][0], d2[C][1], d2[C][2], d2[C][3]};
+          const bf16x4 b1 = to_bf16x4(f1), b2 = to_bf16x4(f2);
+          if constexpr (SPLIT) {
+            ug[rt][0] = mfma_bf16_k16(lo_bf16x4(f1, b1), kbh[C], ug[rt][0]);
+            ug[rt][0] = mfma_bf16_k16(b1, kbl[C], ug[rt][0]);
+          }
+          if constexpr (SPLIT_H) {
+            uh[rt][0] = mfma_bf16_k16(lo_bf16x4(f2, b2), kqh[C], uh[rt][0]);
+            uh[rt][0] = mfma_bf16_k16(b2, kql[C], uh[rt][0]);
+          }
+          ug[rt][0] = mfma_bf16_k16(b1, kbh[C], ug[rt][0]);
+          uh[rt][0] = mfma_bf16_k16(b2, kqh[C], uh[rt][0]);
+        }
       } else {
         const floatx8 f1 = {d1[0][0], d1[0][1], d1[0][2], d1[0][3], d1[1][0], d1[1][1], d1[1][2], d1[1][3]};
         const floatx8 f2 = {d2[0][0], d2[0][1], d2[0][2], d2[0][3], d2[1][0], d2[1][1], d2[1][2], d2[1][3]};
@@ -236,7 +296,7 @@ const void* kernel_ptr() {
 template <int PREC, int FAM>
 const void* kernel_for_kp(int KP) {
   switch (KP) {
-    case 16: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 16>(); else break;
+    case 16: return kernel_ptr<PREC, FAM, 16>();
     case 32: return kernel_ptr<PREC, FAM, 32>();
     case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(); else break;
     case 64: return kernel_ptr<PREC, FAM, 64>();

@@ -197,3 +197,32 @@ def test_projection_split_bf16_matches_oracle():
                            B, Ao, Uo, V).sum()
     assert abs(tr[-1] - dev_o) <= 1e-4 * dev_o
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16"])
+def test_projection_bfloat16_at_stride_16(precision):
+    """An FP32 context at panel stride 16 projecting in a bfloat16 precision
+    (16x16x16 bfloat16 products).  Split BF16: products off by about 2^-17
+    relative, gated like the stride-32 case (2e-3 on the scores, 1e-4 on the
+    deviance).  BF16: operands rounded to 8 bits (2^-9 relative), gated like
+    the BF16 fit (5e-2 on the scores) and 1e-3 on the deviance of the
+    projected rows (the rows converge to a nearby optimum)."""
+    print(f"[case] projection {precision} at stride 16", flush=True)
+    pr, new, g = _fit_and_new_rows(1044)
+    B, A, U, V = g.params(0)
+    B, _, _, V = G.postprocess_A_B1(pr.X, pr.Z, B, A, U, V)
+    g.set_precision(precision)
+    A0 = np.zeros((new.n, pr.q))
+    U0 = np.zeros((new.n, pr.d))
+    Ag, Ug, tr = g.project(new.Y, new.X, A0, U0, 4, frozen=1, trace=True)
+    Ao, Uo = _oracle_project(pr, new, B, V, 4)
+    ea, eu = rel_err(Ag.cpu().numpy(), Ao), rel_err(Ug.cpu().numpy(), Uo)
+    dev_o = G.row_deviance(G.Config(family="negbin", nb_alpha=pr.nb_alpha), new.Y, new.X, pr.Z,
+                           B, Ao, Uo, V).sum()
+    ed = abs(tr[-1] - dev_o) / dev_o
+    print(f"{precision} stride-16 projection errors: A {ea:.2e} U {eu:.2e} deviance {ed:.2e}")
+    tol, tol_d = (2e-3, 1e-4) if precision == "bf16x3" else (5e-2, 1e-3)
+    assert ea <= tol and eu <= tol
+    assert ed <= tol_d
+    g.set_precision("fp32")
+    g.close()
