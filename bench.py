@@ -199,9 +199,10 @@ def first_hit(trace, ms, target, rel=1e-4):
 def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
     """Learned warm start of new rows: fit the workload, train the encoder on
     (log1p counts, projected scores) of its rows (90/10 split), then project
-    n_new fresh rows from the same generator twice, cold (U0 = 0) and warm (U0 =
-    encoder output in bfloat16, per-row fallback to 0), both with the row
-    intercept start, and time each to 1e-4 of the converged projection deviance."""
+    n_new fresh rows from the same generator cold (U0 = 0) and warm (U0 =
+    encoder output in bfloat16, per-row fallback to 0), all with the row
+    intercept start, the warm start with FP32, split-BF16 and BF16 projection
+    steps, and time each to 1e-4 of the converged projection deviance."""
     import numpy as np
     from paper_2412_20509_amd.gmf import Encoder
     from synth import gen_nb_rows, mlp_init
