@@ -19,7 +19,8 @@
 // The next chunk's counts and column panel rows are loaded before the current
 // chunk is computed.  The precisions are those of the fit steps: float32
 // products, bfloat16 operands, or split bfloat16 (high and low parts, three
-// products per contraction).
+// products per contraction), with 16x16x32 bfloat16 products, or 16x16x16 at
+// panel stride 16.
 #include <hip/hip_runtime.h>
 
 #include "family.hpp"
