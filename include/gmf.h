@@ -84,9 +84,11 @@ typedef struct gmf_config {
   int32_t tile_rows;  /* rows per step tile (multiple of 32), 0 = automatic   */
   int32_t skip_block_deviance; /* 1: steps do not form the block deviance   */
   int32_t panel_stride; /* floats per panel row: 0 = automatic (p+q+d rounded
-                           up to 16, or 32 for BF16); else 16, 32, 48 or 64
-                           (BF16: 32 or 64) and >= p+q+d.  Fits run together
-                           by gmf_batch_* must share it.                       */
+                           up to 16; for BF16 and BF16X3 above 16 up to 32);
+                           else 16, 32, 48 or 64 (BF16, BF16X3: 16, 32 or 64)
+                           and >= p+q+d.  Fits run together by gmf_batch_*
+                           must share it.  At stride 16 the bfloat16 products
+                           are 16x16x16, above it 16x16x32.                    */
   int32_t tile_waves;   /* wavefronts per step tile: 4 (each takes 32 rows x 32
                            columns of a 32-row group) or 8 (16 rows x 32
                            columns each, half the per-wavefront work; FP32
@@ -145,13 +147,9 @@ int gmf_step(void* ctx, int64_t nsteps);
 /* gmf_set_precision -- switch the arithmetic of the following steps and
  * projections (GMF_PREC_FP32 / GMF_PREC_BF16 / GMF_PREC_BF16X3) on the same
  * iterate and moments, e.g. a context fitted in FP32 that projects new rows
- * in BF16X3.  Block steps in the bfloat16 precisions need a panel stride of
- * 32 or 64 (automatic for a context created with one, or cfg.panel_stride);
- * at stride 16 (an FP32 context with p+q+d <= 16) a bfloat16 precision serves
- * gmf_project / gmf_project_warm only (16x16x16 bfloat16 products), and
- * gmf_step, gmf_fit, gmf_run and gmf_batch_init return GMF_EINVAL until the
- * context is switched back to FP32.  Errors: GMF_EINVAL (unknown precision,
- * panel stride, tile_waves = 8 not available for it). */
+ * in BF16X3.  The bfloat16 precisions need a panel stride of 16, 32 or 64
+ * (an FP32 context at stride 48 cannot switch).  Errors: GMF_EINVAL (unknown
+ * precision, panel stride, tile_waves = 8 not available for it). */
 int gmf_set_precision(void* ctx, int32_t precision);
 
 /* gmf_fit -- run epochs of R*S steps (one epoch = R sweeps over J_1..J_S) up

@@ -145,9 +145,9 @@ std::string check_config(const gmf_config* c) {
     return "tile_waves = 8 needs panel stride 16 or 32 (FP32) or 32 (BF16, split BF16)";
   if (c->panel_stride != 0) {
     const int ps = c->panel_stride;
-    const bool ok = (c->precision != GMF_PREC_FP32) ? (ps == 32 || ps == 64)
+    const bool ok = (c->precision != GMF_PREC_FP32) ? (ps == 16 || ps == 32 || ps == 64)
                                                     : (ps == 16 || ps == 32 || ps == 48 || ps == 64);
-    if (!ok) return "panel_stride must be 0, 16, 32, 48 or 64 (BF16, split BF16: 32 or 64)";
+    if (!ok) return "panel_stride must be 0, 16, 32, 48 or 64 (BF16, split BF16: 16, 32 or 64)";
     if (ps < c->p + c->q + c->d) return "panel_stride must be >= p + q + d";
   }
   return "";
@@ -183,13 +183,9 @@ int ilog2_ceil(int64_t x) {
 int panel_stride_of(const gmf_config* c) {
   const int k = c->p + c->q + c->d;
   if (c->panel_stride > 0) return c->panel_stride;
-  return (c->precision != GMF_PREC_FP32) ? round_up(k, 32) : round_up(k, 16);
+  if (c->precision == GMF_PREC_FP32 || k <= 16) return round_up(k, 16);
+  return round_up(k, 32);   // bfloat16 products of K = 32 above stride 16
 }
-
-// Block steps exist for FP32 at every panel stride and for the bfloat16
-// precisions at strides 32 and 64; a context switched to a bfloat16 precision
-// at stride 16 projects rows only.
-bool steps_available(int prec, int KP) { return prec == GMF_PREC_FP32 || KP == 32 || KP == 64; }
 
 // Wavefronts per tile workgroup.  8-wavefront tiles halve each wavefront's
 // share of a row group and need fewer registers per wavefront: they pay off
@@ -506,8 +502,6 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
   const Plan& P = c->P;
   const bool want_dev = c->want_block_dev != 0;
   if (nsteps <= 0) return GMF_OK;
-  if (!steps_available(P.prec, P.KP))
-    return fail(GMF_EINVAL, "BF16 block steps need panel stride 32 or 64 (this context projects only)");
   std::vector<gmf::LevelStep> steps(nsteps);
   std::vector<int> level(nsteps);
   std::vector<int> lr(P.R, -1), ls(P.S, -1), lslot(P.nslot, -1);
@@ -808,9 +802,9 @@ int gmf_set_precision(void* ctx, int32_t precision) {
   if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16 && precision != GMF_PREC_BF16X3)
     return fail(GMF_EINVAL, "unknown precision");
   const bool ok = (precision != GMF_PREC_FP32) ? (P.KP == 16 || P.KP == 32 || P.KP == 64) : true;
-  if (!ok) return fail(GMF_EINVAL, "BF16 needs panel stride 16 (projections only), 32 or 64");
+  if (!ok) return fail(GMF_EINVAL, "BF16 needs panel stride 16, 32 or 64 (set panel_stride at init)");
   const int tw = c->cfg.tile_waves;
-  if (tw == 8 && steps_available(precision, P.KP) && !gmf::level_supports_nw8(precision, P.KP))
+  if (tw == 8 && !gmf::level_supports_nw8(precision, P.KP))
     return fail(GMF_EINVAL, "tile_waves = 8 is not available for this precision and panel stride");
   P.prec = precision;
   c->cfg.precision = precision;
@@ -1553,8 +1547,6 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
     return fail(GMF_EWORKSPACE, "batch workspace NULL, misaligned or smaller than " +
                                     std::to_string(z.total) + " bytes");
   const Plan& P0 = as_ctx(ctxs[0])->P;
-  if (!steps_available(P0.prec, P0.KP))
-    return fail(GMF_EINVAL, "BF16 block steps need panel stride 32 or 64");
   for (int f = 0; f < nfits; ++f) {
     const Plan& P = as_ctx(ctxs[f])->P;
     if (P.prec != P0.prec || P.KP != P0.KP)

@@ -39,6 +39,18 @@
 
 namespace gmf {
 
+// D(16x16) += A(16x16) B(16x16), bfloat16 operands, float32 accumulation:
+// lane (i, g) holds A[i][4g .. 4g+3] and B[4g .. 4g+3][i] (the bfloat16
+// products at panel stride 16).
+__device__ __forceinline__ floatx4 mfma_bf16_k16(bf16x4 a, bf16x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x4 to_bf16x4(floatx4 x) { return __builtin_convertvector(x, bf16x4); }
+__device__ __forceinline__ bf16x4 lo_bf16x4(floatx4 x, bf16x4 hi) {
+  return to_bf16x4(x - __builtin_convertvector(hi, floatx4));
+}
+__device__ __forceinline__ bf16x4 lds4(const __bf16* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
 template <int PREC> struct TStride { static constexpr int v = (PREC == kF32) ? 36 : 40; };
 template <int PREC>
 using TElem = typename std::conditional<PREC == kF32, float, __bf16>::type;
@@ -98,6 +110,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   constexpr bool BF = PREC != kF32;       // bfloat16 MFMA
   constexpr bool SPLIT = PREC == kBF16X3; // with high and low operand parts
   constexpr bool SPLIT_H = SPLIT && kSplitCurvature;
+  constexpr bool K16 = BF && KP == 16;    // bfloat16 products of K = 16 (16x16x16)
   using TE = TElem<PREC>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -113,16 +126,35 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       : reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[cg]);
   // ---- column-panel operands of this wavefront (fixed over the tile)
   float pa32[2][(PREC == kF32) ? KP / 4 : 1];
-  bf16x8 pa16[2][BF ? KP / 32 : 1], pa16l[2][SPLIT ? KP / 32 : 1];
+  bf16x8 pa16[2][(BF && !K16) ? KP / 32 : 1], pa16l[2][(SPLIT && !K16) ? KP / 32 : 1];
   float ub32[2][4][(PREC == kF32) ? NB : 1], ub32q[2][4][(PREC == kF32) ? NB : 1];
-  bf16x8 ub16[BF ? NB : 1], ub16q[BF ? NB : 1];
-  bf16x8 ub16l[SPLIT ? NB : 1], ub16ql[SPLIT_H ? NB : 1];
+  bf16x8 ub16[(BF && !K16) ? NB : 1], ub16q[(BF && !K16) ? NB : 1];
+  bf16x8 ub16l[(SPLIT && !K16) ? NB : 1], ub16ql[(SPLIT_H && !K16) ? NB : 1];
+  // stride 16: eta's A = entries 4g .. 4g+3 of column colw + 16c + l16; the U
+  // side's B = entry l16 of columns colw + 16c + 4g .. +3 (plain and squared)
+  bf16x4 ka[2], kal[2], kb[2], kbl[2], kq[2], kql[2];
   for (int c = 0; c < 2; ++c) {
     const int col = colw + 16 * c + l16;
     const bool ok = col < tv.m_b;
     const float* pc = tv.Pcol + (int64_t)col * KP;
     if constexpr (PREC == kF32) {
       for (int kk = 0; kk < KP / 4; ++kk) pa32[c][kk] = ok ? pc[4 * kk + g] : 0.f;
+    } else if constexpr (K16) {
+      const float4 u = ok ? *reinterpret_cast<const float4*>(pc + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const floatx4 x = {u.x, u.y, u.z, u.w};
+      ka[c] = to_bf16x4(x);
+      if constexpr (SPLIT) kal[c] = lo_bf16x4(x, ka[c]);
+      float xs[4];
+      for (int v = 0; v < 4; ++v) {
+        const int cu = colw + 16 * c + 4 * g + v;
+        xs[v] = (cu < tv.m_b) ? tv.Pcol[(int64_t)cu * KP + l16] : 0.f;
+      }
+      const floatx4 b = {xs[0], xs[1], xs[2], xs[3]};
+      const floatx4 bb = b * b;
+      kb[c] = to_bf16x4(b);
+      kq[c] = to_bf16x4(bb);
+      if constexpr (SPLIT) kbl[c] = lo_bf16x4(b, kb[c]);
+      if constexpr (SPLIT_H) kql[c] = lo_bf16x4(bb, kq[c]);
     } else {
       for (int kk = 0; kk < KP / 32; ++kk) {
         floatx8 x = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -147,7 +179,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           ub32q[c][v][ob] = x * x;
         }
       }
-  } else {
+  } else if constexpr (!K16) {
     for (int ob = 0; ob < NB; ++ob) {
       float xs[8];
       for (int u = 0; u < 8; ++u) {
@@ -258,6 +290,13 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
         if constexpr (PREC == kF32) {
           for (int kk = 0; kk < KP / 4; ++kk) e = mfma_f32(pa32[C][kk], L.sP[lrow][4 * kk + g], e);
+        } else if constexpr (K16) {
+          const bf16x4 bh = lds4(&L.sPb[lrow][4 * g]);
+          if constexpr (SPLIT) {   // the small products first
+            e = mfma_bf16_k16(kal[C], bh, e);
+            e = mfma_bf16_k16(ka[C], lds4(&L.sPbl[lrow][4 * g]), e);
+          }
+          e = mfma_bf16_k16(ka[C], bh, e);
         } else {
           for (int kk = 0; kk < KP / 32; ++kk) {
             const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&L.sPb[lrow][32 * kk + 8 * g]);
@@ -308,6 +347,23 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
               ug[rr][ob] = mfma_f32(d1[C][v], ub32[C][v][ob], ug[rr][ob]);
               uh[rr][ob] = mfma_f32(d2[C][v], ub32q[C][v][ob], uh[rr][ob]);
             }
+      } else if constexpr (K16) {
+        // A = D1 (D2) of row lrow, columns colw + 16C + 4g .. +3 from the accumulators
+        for (int C = 0; C < 2; ++C) {
+          const floatx4 f1 = {d1[C][0], d1[C][1], d1[C][2], d1[C][3]};
+          const floatx4 f2 = {d2[C][0], d2[C][1], d2[C][2], d2[C][3]};
+          const bf16x4 b1 = to_bf16x4(f1), b2 = to_bf16x4(f2);
+          if constexpr (SPLIT) {
+            ug[rr][0] = mfma_bf16_k16(lo_bf16x4(f1, b1), kb[C], ug[rr][0]);
+            ug[rr][0] = mfma_bf16_k16(b1, kbl[C], ug[rr][0]);
+          }
+          if constexpr (SPLIT_H) {
+            uh[rr][0] = mfma_bf16_k16(lo_bf16x4(f2, b2), kq[C], uh[rr][0]);
+            uh[rr][0] = mfma_bf16_k16(b2, kql[C], uh[rr][0]);
+          }
+          ug[rr][0] = mfma_bf16_k16(b1, kb[C], ug[rr][0]);
+          uh[rr][0] = mfma_bf16_k16(b2, kq[C], uh[rr][0]);
+        }
       } else {
         const floatx8 f1 = {d1[0][0], d1[0][1], d1[0][2], d1[0][3], d1[1][0], d1[1][1], d1[1][2], d1[1][3]};
         const floatx8 f2 = {d2[0][0], d2[0][1], d2[0][2], d2[0][3], d2[1][0], d2[1][1], d2[1][2], d2[1][3]};
@@ -348,6 +404,24 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
             vacc[cc][ob][0] = mfma_f32(t1[s], pb, vacc[cc][ob][0]);
             vacc[cc][ob][1] = mfma_f32(t2[s], pb * pb, vacc[cc][ob][1]);
           }
+      } else if constexpr (K16) {
+        // two K = 16 halves of the group's rows: A = D1^T of column 16C + l16,
+        // rows 16h + 4g .. +3; B = the row panel entry l16 of those rows
+        for (int h = 0; h < 2; ++h) {
+          const int r4 = 16 * h + 4 * g;
+          const bf16x4 t1 = lds4(&sT[0][16 * C + l16][r4]), t2 = lds4(&sT[1][16 * C + l16][r4]);
+          const bf16x4 xb = lds4(&L.sPT[0][l16][r4]), xq = lds4(&L.sPT[1][l16][r4]);
+          if constexpr (SPLIT) {
+            vacc[cc][0][0] = mfma_bf16_k16(lds4(&sT[2][16 * C + l16][r4]), xb, vacc[cc][0][0]);
+            vacc[cc][0][0] = mfma_bf16_k16(t1, lds4(&L.sPTl[0][l16][r4]), vacc[cc][0][0]);
+          }
+          if constexpr (SPLIT_H) {
+            vacc[cc][0][1] = mfma_bf16_k16(lds4(&sT[SPLIT_H ? 3 : 2][16 * C + l16][r4]), xq, vacc[cc][0][1]);
+            vacc[cc][0][1] = mfma_bf16_k16(t2, lds4(&L.sPTl[SPLIT_H ? 1 : 0][l16][r4]), vacc[cc][0][1]);
+          }
+          vacc[cc][0][0] = mfma_bf16_k16(t1, xb, vacc[cc][0][0]);
+          vacc[cc][0][1] = mfma_bf16_k16(t2, xq, vacc[cc][0][1]);
+        }
       } else {
         const bf16x8 t1 = *reinterpret_cast<const bf16x8*>(&sT[0][16 * C + l16][8 * g]);
         const bf16x8 t2 = *reinterpret_cast<const bf16x8*>(&sT[1][16 * C + l16][8 * g]);
@@ -682,7 +756,7 @@ static const void* kernel_ptr(bool want_dev, int nw) {
 template <int PREC, int FAM>
 static const void* kernel_ptr_kp(int KP, bool want_dev, int nw) {
   switch (KP) {
-    case 16: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 16>(want_dev, nw); else break;
+    case 16: return kernel_ptr<PREC, FAM, 16>(want_dev, nw);
     case 32: return kernel_ptr<PREC, FAM, 32>(want_dev, nw);
     case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(want_dev, nw); else break;
     case 64: return kernel_ptr<PREC, FAM, 64>(want_dev, nw);
@@ -742,11 +816,13 @@ hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStrea
     }
   } else if (prec == kBF16) {
     switch (KP) {
+      case 16: k = reinterpret_cast<const void*>(&batch_kernel<kBF16, 16>); break;
       case 32: k = reinterpret_cast<const void*>(&batch_kernel<kBF16, 32>); break;
       case 64: k = reinterpret_cast<const void*>(&batch_kernel<kBF16, 64>); break;
     }
   } else if (prec == kBF16X3) {
     switch (KP) {
+      case 16: k = reinterpret_cast<const void*>(&batch_kernel<kBF16X3, 16>); break;
       case 32: k = reinterpret_cast<const void*>(&batch_kernel<kBF16X3, 32>); break;
       case 64: k = reinterpret_cast<const void*>(&batch_kernel<kBF16X3, 64>); break;
     }

@@ -272,8 +272,10 @@ def test_eight_wave_tiles_equal_four_wave_tiles(precision, d):
     instead of 16 entries, so it agrees to float32 rounding only."""
     print(f"[case] tile waves 4 vs 8, {precision} d={d}", flush=True)
     pr = gen_nb(n=2600, m=900, d=d, R=4, S=3, seed=1500 + d)
-    g4 = gpu_for(pr, precision=precision, tile_waves=4)
-    g8 = gpu_for(pr, precision=precision, tile_waves=8)
+    # bfloat16 8-wavefront tiles exist at panel stride 32
+    ps = 0 if precision == "fp32" else 32
+    g4 = gpu_for(pr, precision=precision, tile_waves=4, panel_stride=ps)
+    g8 = gpu_for(pr, precision=precision, tile_waves=8, panel_stride=ps)
     g4.step(20)
     g8.step(20)
     for x, y in zip(g4.params() + tuple(g4.moments()), g8.params() + tuple(g8.moments())):
@@ -286,27 +288,25 @@ def test_eight_wave_tiles_equal_four_wave_tiles(precision, d):
 
 def test_precision_switch():
     """A BF16 context switched to FP32 steps exactly like an FP32 context of the
-    same panel stride; BF16 steps need a stride of 32 or 64."""
+    same panel stride (16 here); an FP32 context at stride 48 cannot switch to
+    a bfloat16 precision (its products need stride 16, 32 or 64)."""
     from paper_2412_20509_amd.gmf import GMFError
     print("[case] precision switch", flush=True)
     pr = gen_nb(n=1500, m=600, d=6, R=3, S=2, seed=1601)
-    gb = gpu_for(pr, precision="bf16")                  # stride 32
-    gf = gpu_for(pr, precision="fp32", panel_stride=32)
+    gb = gpu_for(pr, precision="bf16")                   # stride 16
+    gf = gpu_for(pr, precision="fp32")                   # stride 16
     gb.set_precision("fp32")
     gb.step(12)
     gf.step(12)
     for x, y in zip(gb.params() + tuple(gb.moments()), gf.params() + tuple(gf.moments())):
         assert np.array_equal(x, y)
-    # at stride 16 a bfloat16 precision serves projections only: steps refuse
-    g16 = gpu_for(pr, precision="fp32")                  # stride 16
-    g16.set_precision("bf16")
+    pr48 = gen_nb(n=600, m=300, d=40, R=2, S=2, seed=1602)   # p + q + d = 44 -> 48
+    g48 = gpu_for(pr48, precision="fp32")
     with pytest.raises(GMFError):
-        g16.step(1)
-    g16.set_precision("fp32")
-    g16.step(1)
-    for g in (gb, gf, g16):
+        g48.set_precision("bf16")
+    g48.step(2)
+    for g in (gb, gf, g48):
         g.close()
-
 
 @pytest.mark.parametrize("family,n,m,d,R,S", [
     ("poisson", 1000, 700, 5, 3, 2),     # several row ranges and a ragged column strip
