@@ -252,6 +252,10 @@ size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new);
  *   A_out, U_out (device, may alias A0/U0): results.  dev_trace_host (may be
  *   NULL): epochs + 1 values, the deviance of the new rows before the first
  *   step and after every epoch.
+ * The steps run in the context's current precision (gmf_set_precision), one
+ * launch per step: each wavefront steps its own rows over the whole column
+ * block, so the gradient sums accumulate in float32 over the block in matrix-
+ * core order (the fit sums per 128-column strip, then over strips in float64).
  * Enqueued on the context's stream; synchronises when dev_trace_host is set.
  * The context's own iterate is not changed. */
 int gmf_project(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_dtype,
