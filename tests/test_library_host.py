@@ -125,3 +125,33 @@ def test_tune_table_round_trip_and_lookup(lib, tmp_path):
         M.tune_table_load(bad)
     assert M.tune_lookup(cfg) == 128                          # unchanged by the failed load
     M.tune_table_clear()
+
+
+@pytest.mark.parametrize("struct", ["gmf_config", "gmf_mlp_config"])
+def test_header_compiles_and_struct_layout_matches_binding(tmp_path, struct):
+    """include/gmf.h compiles as C and as C++, and the binding's structures
+    have the C structs' sizes and field offsets (the ABI the ctypes calls rely
+    on)."""
+    import shutil
+    import subprocess
+    from paper_2412_20509_amd import gmf as M
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("gcc not found")
+    cls = getattr(M, struct)
+    fields = [f[0] for f in cls._fields_]
+    c_names = {"lambda_": "lambda"}
+    src = tmp_path / "layout.c"
+    body = "\n".join(f'  printf("{f} %zu\\n", offsetof({struct}, {c_names.get(f, f)}));' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "gmf.h"\n'
+                   f'int main(void) {{\n  printf("size %zu\\n", sizeof({struct}));\n' + body +
+                   '\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)], check=True)
+    subprocess.run(["g++", "-fsyntax-only", "-x", "c++", "-I", inc, str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(cls)
+    for f in fields:
+        assert int(out[f]) == getattr(cls, f).offset, f
