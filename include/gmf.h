@@ -181,6 +181,14 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
  * Either host pointer may be NULL.  Synchronises. */
 int gmf_deviance(void* ctx, double* total_host, double* penalized_host);
 
+/* gmf_row_deviance -- the deviance of every row, sum_j w_ij D(y_ij, mu_ij) at
+ * the current parameters (D as in gmf_deviance), into per_row (device, n
+ * doubles, the caller's row order).  Per entry: eta and the mu part of the
+ * unit deviance in float32, the count-only part and the row sums in float64
+ * (fixed order); the rows add up to gmf_deviance's total up to the summation
+ * order.  Asynchronous on the context's stream.  Errors: GMF_EINVAL. */
+int gmf_row_deviance(void* ctx, double* per_row);
+
 /* gmf_block_deviance -- the block deviances of the last `count` steps, oldest
  * first, into host memory (count <= min(steps done, 4096)).  Synchronises. */
 int gmf_block_deviance(void* ctx, double* out_host, int64_t count);

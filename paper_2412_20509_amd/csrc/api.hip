@@ -823,6 +823,33 @@ int gmf_deviance(void* ctx, double* total_host, double* penalized_host) {
   return compute_deviance(as_ctx(ctx), total_host, penalized_host);
 }
 
+int gmf_row_deviance(void* ctx, double* per_row) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  if (!per_row) return fail(GMF_EINVAL, "per_row is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  gmf::RowDevArgs a{};
+  a.Yb = c->at<float>(P.o_Yb);
+  a.Wb = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+  a.Prow = c->at<float>(P.o_Prow);
+  a.Pcol = c->at<float>(P.o_Pcol);
+  a.rowblk = c->at<int>(P.o_rowblk);
+  a.rowloc = c->at<int>(P.o_rowloc);
+  a.ro = c->at<int>(P.o_ro);
+  a.nrows = c->at<int>(P.o_nrows);
+  a.rowbase = c->at<int64_t>(P.o_blkrowbase);
+  a.co = c->at<int>(P.o_co);
+  a.mcols = c->at<int>(P.o_mcols);
+  a.coloff = c->at<int64_t>(P.o_blkcoloff);
+  a.ld = c->at<int>(P.o_ld);
+  a.n = P.n;
+  a.S = P.S;
+  a.f = family_args(c->cfg);
+  a.out = per_row;
+  HIP_TRY(gmf::launch_row_deviance(P.fam, P.KP, a, c->st));
+  return GMF_OK;
+}
+
 int gmf_fit(void* ctx, int32_t max_epochs, double tol, int32_t eval_every,
             double* dev_trace_host, int32_t* epochs_done_host) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");

@@ -12,6 +12,8 @@
 //    ordered sum).
 //  * count_sum_kernel: per deviance tile, sum w c(y) of the count-only part
 //    of the deviance in float64 (constant during a fit).
+//  * row_deviance_kernel: the deviance of every row, sum_j w D(y, mu), in the
+//    caller's row order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -467,6 +469,110 @@ hipError_t launch_count_sum(int fam, const DevArgs& a, hipStream_t s) {
       return hipSuccess;   // Gaussian: no count-only part
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------- per-row deviance --
+// One workgroup per 16 rows (caller's order): the rows' panel entries in LDS;
+// thread t walks the columns j = t, t + 256, ... of every column block, loads
+// the column's panel row once for the 16 rows, forms eta in float32, the mu part
+// of the unit deviance in float32 (as the full deviance) and adds the count-only
+// part c(y) in float64 (a per-workgroup table below 256); the 16 row sums are
+// float64, combined in a fixed order.
+constexpr int kRowDevRows = 16;
+
+template <int FAM, int KP, bool HAS_W>
+__global__ __launch_bounds__(kTileThreads) void row_deviance_kernel(RowDevArgs a) {
+  __shared__ float sP[kRowDevRows][KP + 1];
+  __shared__ double ctab[kTileThreads];
+  __shared__ double red[kTileWaves][kRowDevRows];
+  __shared__ int64_t rbase[kRowDevRows];
+  __shared__ int rnb[kRowDevRows], rli[kRowDevRows];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kRowDevRows;
+  const int nr = (int)min<int64_t>(kRowDevRows, a.n - i0);
+  const double alpha = (double)a.f.nb_alpha;
+  ctab[tid] = count_part<FAM>((double)tid, alpha);
+  if (tid < kRowDevRows) {
+    int rb = 0, li = 0;
+    if (tid < nr) { rb = a.rowblk[i0 + tid]; li = a.rowloc[i0 + tid]; }
+    rbase[tid] = a.rowbase[rb];
+    rnb[tid] = a.nrows[rb];
+    rli[tid] = li;
+  }
+  for (int idx = tid; idx < kRowDevRows * KP; idx += kTileThreads) {
+    const int r = idx / KP, k = idx % KP;
+    float v = 0.f;
+    if (r < nr) {
+      const int pr = a.ro[a.rowblk[i0 + r]] + a.rowloc[i0 + r];
+      v = a.Prow[(int64_t)pr * KP + k];
+    }
+    sP[r][k] = v;
+  }
+  __syncthreads();
+  const FamilyConst fc = family_const(a.f);
+  double acc[kRowDevRows];
+  for (int r = 0; r < kRowDevRows; ++r) acc[r] = 0.0;
+  for (int s = 0; s < a.S; ++s) {
+    const int mb = a.mcols[s], c0 = a.co[s], ld = a.ld[s];
+    const int64_t coff = a.coloff[s];
+    for (int j = tid; j < mb; j += kTileThreads) {
+      float pc[KP];
+      const float4* src = reinterpret_cast<const float4*>(a.Pcol + (int64_t)(c0 + j) * KP);
+      for (int q = 0; q < KP / 4; ++q) {
+        const float4 x = src[q];
+        pc[4 * q] = x.x; pc[4 * q + 1] = x.y; pc[4 * q + 2] = x.z; pc[4 * q + 3] = x.w;
+      }
+      for (int r = 0; r < kRowDevRows; ++r) {
+        if (r >= nr) break;
+        float eta = 0.f;
+        for (int k = 0; k < KP; ++k) eta = fmaf(sP[r][k], pc[k], eta);
+        const int64_t at = rbase[r] + (int64_t)rnb[r] * coff + (int64_t)rli[r] * ld + j;
+        const float y = a.Yb[at];
+        const float w = HAS_W ? a.Wb[at] : 1.f;
+        float d1, d2, dv;
+        family_entry<FAM, true>(eta, y, w, fc, d1, d2, dv);
+        const int yi = (int)y;
+        const double cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
+                                                                          : count_part<FAM>((double)y, alpha);
+        acc[r] += (double)dv + 2.0 * (double)w * cy;
+      }
+    }
+  }
+  for (int r = 0; r < kRowDevRows; ++r) {
+    double x = acc[r];
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave][r] = x;
+  }
+  __syncthreads();
+  if (tid < nr) a.out[i0 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+template <int FAM, bool HAS_W>
+static hipError_t launch_row_dev_kp(int KP, const RowDevArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + kRowDevRows - 1) / kRowDevRows)), block(kTileThreads);
+  switch (KP) {
+    case 16: hipLaunchKernelGGL((row_deviance_kernel<FAM, 16, HAS_W>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((row_deviance_kernel<FAM, 32, HAS_W>), grid, block, 0, s, a); break;
+    case 48: hipLaunchKernelGGL((row_deviance_kernel<FAM, 48, HAS_W>), grid, block, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((row_deviance_kernel<FAM, 64, HAS_W>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int FAM>
+static hipError_t launch_row_dev_w(int KP, const RowDevArgs& a, hipStream_t s) {
+  return a.Wb ? launch_row_dev_kp<FAM, true>(KP, a, s) : launch_row_dev_kp<FAM, false>(KP, a, s);
+}
+
+hipError_t launch_row_deviance(int fam, int KP, const RowDevArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  switch (fam) {
+    case kPoisson: return launch_row_dev_w<kPoisson>(KP, a, s);
+    case kNegBin: return launch_row_dev_w<kNegBin>(KP, a, s);
+    case kGaussian: return launch_row_dev_w<kGaussian>(KP, a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s) {

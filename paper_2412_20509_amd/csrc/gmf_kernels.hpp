@@ -171,6 +171,25 @@ struct DevArgs {
   int grid_cap;                // deviance: at most this many workgroups (0 = one per tile)
 };
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s);
+
+// Per-row deviance (aux.hip).  Yb, Wb: block-major counts and weights (Wb may
+// be null); rowblk, rowloc: caller row i -> row block and row inside it; ro:
+// first permuted row of each row block; nrows: rows per row block; rowbase:
+// offset of each row block in Yb; co, mcols, coloff, ld: first permuted
+// column, width, padded offset and row stride of each column block; out: n
+// doubles in the caller's row order.
+struct RowDevArgs {
+  const float* Yb; const float* Wb;
+  const float* Prow; const float* Pcol;
+  const int* rowblk; const int* rowloc; const int* ro; const int* nrows;
+  const int64_t* rowbase;
+  const int* co; const int* mcols; const int64_t* coloff; const int* ld;
+  int64_t n;
+  int S;
+  FamilyArgs f;
+  double* out;
+};
+hipError_t launch_row_deviance(int fam, int KP, const RowDevArgs& a, hipStream_t s);
 // a.partial[tile] = sum over the tile of w c(y), the count-only part of half
 // the unit deviance (float64; nothing for the Gaussian family).
 hipError_t launch_count_sum(int fam, const DevArgs& a, hipStream_t s);

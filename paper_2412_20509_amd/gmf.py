@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "gmf_deviance": (C.c_int, [vp, f64p, f64p]),
         "gmf_run": (C.c_int, [vp, i32, i32, f64p, f64p]),
         "gmf_set_precision": (C.c_int, [vp, i32]),
+        "gmf_row_deviance": (C.c_int, [vp, vp]),
         "gmf_block_deviance": (C.c_int, [vp, f64p, i64]),
         "gmf_get_params": (C.c_int, [vp, vp, vp, vp, vp, i32]),
         "gmf_set_params": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -400,6 +401,14 @@ class GMF:
 
     def deviance(self):
         return gmf_deviance(self.ctx)
+
+    def row_deviance(self):
+        """gmf_row_deviance: the deviance of every row (float64, n, caller's order)."""
+        t = self.torch
+        out = t.empty(self.n, dtype=t.float64, device=self.device)
+        _check(load_library().gmf_row_deviance(self.ctx, C.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        return out.cpu().numpy()
 
     def block_deviance(self, count):
         return gmf_block_deviance(self.ctx, count)

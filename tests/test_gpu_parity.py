@@ -135,6 +135,32 @@ def test_full_deviance_matches_oracle():
         g.close()
 
 
+@pytest.mark.parametrize("family,weights,d", [("negbin", False, 6), ("poisson", True, 6),
+                                              ("gaussian", True, 4), ("negbin", False, 40)])
+def test_row_deviance_matches_oracle(family, weights, d):
+    """gmf_row_deviance against the oracle's per-row deviance of the same
+    parameters, and its rows add up to gmf_deviance's total (1e-6: float32
+    entries, different order).  Per row the float32 error of eta grows with
+    the number of its products K = p + q + d (the deviance's dependence on eta
+    carries it): 1e-6 norm-relative at K <= 16, as for the full deviance, and
+    1e-6 K / 16 rounded up to 4e-6 at K = 44."""
+    pr = gen_tiny(family, n=700, m=530, d=d, p=2, q=2, R=3, S=4, weights=weights, seed=1801)
+    say(f"row deviance {family} d={d} weights={weights}")
+    o = oracle_for(pr)
+    g = gpu_for(pr)
+    g.step(10)
+    B, A, U, V = g.params()
+    ref = G.row_deviance(o.cfg, pr.Y, pr.X, pr.Z, B, A, U, V, W=pr.W)
+    rows = g.row_deviance()
+    total, _ = g.deviance()
+    print("row deviance error", rel_err(rows, ref), "sum vs total", abs(rows.sum() - total) / total)
+    assert rows.shape == (pr.n,)
+    k = pr.p + pr.q + pr.d
+    assert rel_err(rows, ref) <= (1e-6 if k <= 16 else 4e-6)
+    assert abs(rows.sum() - total) <= 1e-6 * abs(total)
+    g.close()
+
+
 def test_final_deviance_after_epochs_c1():
     pr = gen_poisson_small()
     say("final deviance c1 after 20 epochs")
