@@ -227,6 +227,14 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       }
     }
   };
+  // strip partials: thread -> (output s_oo, rows s_r0, s_r0 + s_rows, ...),
+  // fixed over the tile (2 KU <= 2 KP < NT, so every pass covers >= 2 rows)
+  const int s_rows = NT / (2 * KU);
+  const int s_r0 = tid / (2 * KU);
+  const int s_oo = tid - s_r0 * (2 * KU);
+  const bool s_on = s_r0 < s_rows;
+  const int s_src = (s_oo < KU) ? (p + s_oo) : (KP + p + (s_oo - KU));
+
   float4 ynext[NR][2];
   float4 pnext[PF];
   load_p(tv.row0, pnext);
@@ -456,22 +464,20 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     __syncthreads();
 
     // ---- sum over the 4 column groups (fixed order) and store the strip partial
-    for (int idx = tid; idx < kRowGroup * 2 * KU; idx += NT) {
-      const int r = idx / (2 * KU);
-      const int oo = idx % (2 * KU);
-      const int row = rg + r;
-      if (row < tv.row_end) {
-        const int src = (oo < KU) ? (p + oo) : (KP + p + (oo - KU));
-        float s = 0.f;
-        for (int c = 0; c < 4; ++c) {
-          if constexpr (NW == 8)
-            s += reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? c + 4 * (r & 1) : 0])[r >> 1][src];
-          else
-            s += reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[c])[r][src];
+    if (s_on)
+      for (int r = s_r0; r < kRowGroup; r += s_rows) {
+        const int row = rg + r;
+        if (row < tv.row_end) {
+          float s = 0.f;
+          for (int c = 0; c < 4; ++c) {
+            if constexpr (NW == 8)
+              s += reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? c + 4 * (r & 1) : 0])[r >> 1][s_src];
+            else
+              s += reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[c])[r][s_src];
+          }
+          tv.Upart[(int64_t)row * (2 * KU) + s_oo] = s;
         }
-        tv.Upart[(int64_t)row * (2 * KU) + oo] = s;
       }
-    }
   }
 
   if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
