@@ -92,9 +92,8 @@ typedef struct gmf_config {
   int32_t tile_waves;   /* wavefronts per step tile: 4 (each takes 32 rows x 32
                            columns of a 32-row group) or 8 (16 rows x 32
                            columns each, half the per-wavefront work; FP32
-                           stride 16/32, BF16 32 only); 0 = automatic: 8 for
-                           the FP32 stride 32 and for split BF16 tiles of
-                           several 32-row groups, else 4                     */
+                           stride 16/32, BF16 32 only); 0 = automatic: 4,
+                           the faster one at every measured shape            */
   int32_t eval_overlap; /* gmf_run's deviance evaluations: 0 = on the
                            context's stream after the epoch's steps (full
                            grid); 1 = on a second stream from a copy of the

@@ -187,19 +187,16 @@ int panel_stride_of(const gmf_config* c) {
   return round_up(k, 32);   // bfloat16 products of K = 32 above stride 16
 }
 
-// Wavefronts per tile workgroup.  8-wavefront tiles halve each wavefront's
-// share of a row group and need fewer registers per wavefront: they pay off
-// where the 4-wavefront tile would spill (FP32 stride 32, split BF16 on tiles
-// of several row groups).  Elsewhere 4 run faster: single-group tiles of small
-// blocks are latency-bound, and the 4-wavefront BF16 tile of the
-// 100000 x 5000 fit runs 584 epochs/s against 454 with 8.  tile_waves (4 or
-// 8) overrides the rule.
+// Wavefronts per tile workgroup: 4 unless tile_waves asks for 8.  Since the
+// tile forms each entry's deviance before its contractions (fewer live
+// registers), the 4-wavefront tile is the faster one at every measured shape:
+// per 10000 x 1000 step at panel stride 32, FP32 58.1 against 66.2 us with 8,
+// split BF16 44.0 against 52.5, BF16 34.4 against 43.8 (before its
+// three-per-unit occupancy bound).
 int tile_waves_for(int prec, int KP, int rpw, int tile_waves) {
-  if (tile_waves == 4 || !gmf::level_supports_nw8(prec, KP)) return 4;
-  if (tile_waves == 8) return 8;
-  const bool spill = (prec == GMF_PREC_FP32 && KP >= 32) ||
-                     (prec == GMF_PREC_BF16X3 && rpw >= 2 * gmf::kRowGroup);
-  return spill ? 8 : 4;
+  (void)rpw;
+  if (tile_waves == 8 && gmf::level_supports_nw8(prec, KP)) return 8;
+  return 4;
 }
 
 TuneKey tune_key(const gmf_config* c) {

@@ -333,6 +333,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
           if constexpr (WANT_DEV) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
         }
       }
+      // the deviance is formed here, not deferred past the contractions (the
+      // per-entry values would stay live and cost registers)
+      if constexpr (WANT_DEV) asm volatile("" ::"v"(dev_grp));
       // transposed copies for the V side: sT[h][col][row]
       for (int C = 0; C < 2; ++C)
         for (int v = 0; v < 4; ++v) {
@@ -674,8 +677,11 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
   return -1;
 }
 
+// Occupancy: two 4-wavefront tiles per compute unit, three for the bfloat16
+// tile at panel stride 32 (168 registers, a few spilled outside the row-group
+// loop; 29.8 against 34.4 us per 10000 x 1000 step with two).
 template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
-__global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : 2) void level_kernel(LevelArgs a) {
+__global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : ((PREC == kBF16 && KP == 32) ? 3 : 2)) void level_kernel(LevelArgs a) {
   __shared__ LevelLds<PREC, KP, NW> L;
   const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
   __shared__ unsigned long long stamps[3];
