@@ -409,13 +409,17 @@ void gmf_encoder_destroy(void* enc);
 /* Message for the last failing encoder call on this thread. */
 const char* gmf_encoder_last_error(void);
 
-/* gmf_set_trace -- record a timeline of the step tasks into a caller device
- * buffer of `records` x 8 uint64 (NULL disables): per task of the following
- * launches, in claim order across launches: [0] step t, [1] (workgroup << 32)
- * | tile, [2..6] s_memrealtime stamps (100 MHz) at claim, dependencies met,
- * tile computed, arrival counted, done, [7] bit 0/1/2 = this task ran the
- * row-range update / column-strip update / block-deviance sum.  Records past
- * the capacity are dropped.  For profiling only. */
+/* gmf_set_trace -- record a timeline of the step launches into a caller
+ * device buffer of `records` x 8 uint64 (NULL disables).  Every workgroup of
+ * the following level launches that has work writes one record at index
+ * (workgroups of earlier traced launches) + its workgroup index:
+ * [0] launch number, [1] (workgroup << 32) | kind (0 tile, 1 row update,
+ * 2 column update, 3 block-deviance sum), [2] start and [3] end stamp
+ * (s_memrealtime, 100 MHz), [4] hardware compute-unit id, [5..7] for tiles
+ * the stamps after its operand loads, after its first row group's U side and
+ * after its last row group (else 0).  Workgroups without work leave their
+ * record untouched; records past the capacity are dropped.  For profiling
+ * only. */
 int gmf_set_trace(void* ctx, void* buffer, int64_t records);
 
 /* Steps run so far (the global counter t of the last step). */

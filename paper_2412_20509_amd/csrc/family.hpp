@@ -78,8 +78,10 @@ __device__ __forceinline__ double count_part(double y, double a) {
 
 // eta: linear predictor, y: response, w: weight (1 when there are none).
 // dev (WANT_DEV): the mu part of the unit deviance times w -- the full unit
-// deviance for the Gaussian family, 2 w [D/2 - c(y)] for Poisson and NB.
-template <int FAM, bool WANT_DEV>
+// deviance for the Gaussian family, 2 w [D/2 - c(y)] for Poisson and NB
+// (HALF: without that factor 2, which the caller applies to its float sum;
+// doubling is exact, so both give the same sums).
+template <int FAM, bool WANT_DEV, bool HALF = false>
 __device__ __forceinline__ void family_entry(float eta, float y, float w, const FamilyConst& c,
                                              float& d1, float& d2, float& dev) {
   if constexpr (FAM == kGaussian) {
@@ -96,7 +98,7 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
       d1 = wp * (mu - y);
       d2 = wp * mu;
       if constexpr (WANT_DEV) {
-        dev = 2.f * w * fmaf(-y, ec, mu);
+        dev = (HALF ? 1.f : 2.f) * w * fmaf(-y, ec, mu);
       }
     } else {
       const float s = c.a + mu;
@@ -105,7 +107,7 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
       d1 = wa * (mu - y);
       d2 = wa * mu;
       if constexpr (WANT_DEV) {
-        dev = 2.f * w * fmaf(y + c.a, log1p_pos(mu * c.inv_a, c.a * inv), -y * ec);
+        dev = (HALF ? 1.f : 2.f) * w * fmaf(y + c.a, log1p_pos(mu * c.inv_a, c.a * inv), -y * ec);
       }
     }
   }

@@ -329,7 +329,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         // eta, mu, D1, D2 are finite.  Only the deviance sum is masked.
         for (int v = 0; v < 4; ++v) {
           float dv = 0.f;
-          family_entry<FAM, WANT_DEV>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+          family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
           if constexpr (WANT_DEV) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
         }
       }
@@ -397,7 +397,8 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
     __syncthreads();   // the column group's transposed rows are complete
 
-    if constexpr (WANT_DEV) dev_acc += (double)dev_grp;
+    // the Poisson and NB entries left out the deviance's factor 2
+    if constexpr (WANT_DEV) dev_acc += (FAM == kGaussian ? 1.0 : 2.0) * (double)dev_grp;
     if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
     for (int cc = 0; cc < NC; ++cc) {
