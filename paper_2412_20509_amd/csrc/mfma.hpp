@@ -42,15 +42,22 @@ constexpr bool kSplitCurvature = true;
 // EMA of the gradient and curvature (eq. 12) and the step
 // theta -= stepsize * Gbar / (Hbar + damping) (eq. 13-14) for one parameter;
 // returns false if the result is not finite.
-__device__ __forceinline__ bool ema_step(float* th, double* gm, double* hm, double G, double H,
-                                         double a1, double a2, double damping, double stepsize) {
-  const double gbar = (1.0 - a1) * (*gm) + a1 * G;
-  const double hbar = (1.0 - a2) * (*hm) + a2 * H;
+// ema_apply takes the current theta, Gbar, Hbar as values (loaded ahead by
+// the caller); ema_step loads them itself.
+__device__ __forceinline__ bool ema_apply(float* th, double* gm, double* hm, float th0, double g0,
+                                          double h0, double G, double H, double a1, double a2,
+                                          double damping, double stepsize) {
+  const double gbar = (1.0 - a1) * g0 + a1 * G;
+  const double hbar = (1.0 - a2) * h0 + a2 * H;
   *gm = gbar;
   *hm = hbar;
-  const float nv = (float)((double)*th - stepsize * gbar / (hbar + damping));
+  const float nv = (float)((double)th0 - stepsize * gbar / (hbar + damping));
   *th = nv;
   return isfinite(nv);
+}
+__device__ __forceinline__ bool ema_step(float* th, double* gm, double* hm, double G, double H,
+                                         double a1, double a2, double damping, double stepsize) {
+  return ema_apply(th, gm, hm, *th, *gm, *hm, G, H, a1, a2, damping, stepsize);
 }
 
 }  // namespace gmf

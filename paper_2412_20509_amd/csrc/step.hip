@@ -550,21 +550,32 @@ __device__ void update_rows(const LevelArgs& a, const LevelStep& st, int row0, i
   const int KU = a.KU;
   const float* U = a.Upart + (int64_t)st.slot * a.slot_u_elems;
   const int seg = (row1 - row0) * 2 * KU;
+  const int cnt = (row1 - row0) * KU;
+  // The thread's parameter, read before the partial sums so that both loads
+  // are in flight together (a chunk has at most blockDim.x parameters; no
+  // other workgroup of the launch writes these rows).
+  const int idx = threadIdx.x;
+  const int i = idx / KU, o = idx - i * KU;
+  const int64_t grow = (int64_t)st.ro + row0 + i;
+  float th0 = 0.f;
+  double g0 = 0.0, h0 = 0.0;
+  if (idx < cnt) {
+    th0 = a.Prow[grow * a.KP + a.p + o];
+    g0 = a.Grow[grow * KU + o];
+    h0 = a.Hrow[grow * KU + o];
+  }
   sum_segments(U + (int64_t)row0 * 2 * KU, (int64_t)n_b * 2 * KU, n_ct, seg, sums);
   __syncthreads();
   const double scale_m = (double)a.m / m_b;
-  bool ok = true;
-  for (int idx = threadIdx.x; idx < (row1 - row0) * KU; idx += blockDim.x) {
-    const int i = idx / KU, o = idx % KU;
-    const int64_t grow = (int64_t)st.ro + row0 + i;
-    float* th = a.Prow + grow * a.KP + a.p + o;
+  if (idx < cnt) {
     const double lam = (o < a.q) ? a.lam_A : a.lam_U;
-    const double theta = (double)*th;
-    ok = ema_step(th, a.Grow + grow * KU + o, a.Hrow + grow * KU + o,
-                  scale_m * sums[i * 2 * KU + o] + lam * theta, scale_m * sums[i * 2 * KU + KU + o] + lam,
-                  a.a1, a.a2, a.damping, st.stepsize) && ok;
+    const bool ok = ema_apply(a.Prow + grow * a.KP + a.p + o, a.Grow + grow * KU + o,
+                              a.Hrow + grow * KU + o, th0, g0, h0,
+                              scale_m * sums[i * 2 * KU + o] + lam * (double)th0,
+                              scale_m * sums[i * 2 * KU + KU + o] + lam, a.a1, a.a2, a.damping,
+                              st.stepsize);
+    if (!ok) atomicOr(a.err_flag, 1);
   }
-  if (!ok) atomicOr(a.err_flag, 1);
 }
 
 // Columns [col0, col1) of block s (block-local indices).
@@ -575,22 +586,31 @@ __device__ void update_cols(const LevelArgs& a, const LevelStep& st, int col0, i
   const int KV = a.KV;
   const float* V = a.Vpart + (int64_t)st.slot * a.slot_v_elems;
   const int seg = (col1 - col0) * 2 * KV;
+  const int cnt = (col1 - col0) * KV;
+  // as in update_rows: the thread's parameter is read before the partial sums
+  const int idx = threadIdx.x;
+  const int j = idx / KV, o = idx - j * KV;
+  const int64_t gcol = (int64_t)st.co + col0 + j;
+  const int pc = (o < a.p) ? o : (o + a.q);
+  float th0 = 0.f;
+  double g0 = 0.0, h0 = 0.0;
+  if (idx < cnt) {
+    th0 = a.Pcol[gcol * a.KP + pc];
+    g0 = a.Gcol[gcol * KV + o];
+    h0 = a.Hcol[gcol * KV + o];
+  }
   sum_segments(V + (int64_t)col0 * 2 * KV, (int64_t)m_b * 2 * KV, n_rr, seg, sums);
   __syncthreads();
   const double scale_n = (double)a.n / n_b;
-  bool ok = true;
-  for (int idx = threadIdx.x; idx < (col1 - col0) * KV; idx += blockDim.x) {
-    const int j = idx / KV, o = idx % KV;
-    const int64_t gcol = (int64_t)st.co + col0 + j;
-    const int pc = (o < a.p) ? o : (o + a.q);
-    float* th = a.Pcol + gcol * a.KP + pc;
+  if (idx < cnt) {
     const double lam = (o < a.p) ? a.lam_B : a.lam_V;
-    const double theta = (double)*th;
-    ok = ema_step(th, a.Gcol + gcol * KV + o, a.Hcol + gcol * KV + o,
-                  scale_n * sums[j * 2 * KV + o] + lam * theta, scale_n * sums[j * 2 * KV + KV + o] + lam,
-                  a.a1, a.a2, a.damping, st.stepsize) && ok;
+    const bool ok = ema_apply(a.Pcol + gcol * a.KP + pc, a.Gcol + gcol * KV + o,
+                              a.Hcol + gcol * KV + o, th0, g0, h0,
+                              scale_n * sums[j * 2 * KV + o] + lam * (double)th0,
+                              scale_n * sums[j * 2 * KV + KV + o] + lam, a.a1, a.a2, a.damping,
+                              st.stepsize);
+    if (!ok) atomicOr(a.err_flag, 1);
   }
-  if (!ok) atomicOr(a.err_flag, 1);
 }
 
 // Block deviance of the step: fixed-order tree over the tile partials.
