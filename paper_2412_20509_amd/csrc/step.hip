@@ -202,15 +202,17 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       for (int h = 0; h < 2; ++h) vacc[c][ob][h] = floatx4{0.f, 0.f, 0.f, 0.f};
   double dev_acc = 0.0;
 
-  // Y of a row group: lane reads rows rg + 2 l16 + R, cols colw + 16C + 4g .. +3
+  // Y of a row group: lane reads rows rg + 2 l16 + R, cols colw + 16C + 4g .. +3.
+  // Rows past the tile end and columns past the padded row are clamped to the
+  // last valid ones instead of zero-filled: those entries meet zero panel
+  // operands in every contraction and are masked out of the deviance, so any
+  // finite count serves.
   auto load_y = [&](int rg, float4 (&y)[NR][2]) {
     for (int rr = 0; rr < NR; ++rr) {
-      const int row = rg + 2 * l16 + R0 + rr;
+      const int row = min(rg + 2 * l16 + R0 + rr, tv.row_end - 1);
       for (int C = 0; C < 2; ++C) {
-        const int colb = colw + 16 * C + 4 * g;
-        y[rr][C] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (row < tv.row_end && colb < tv.ldy)
-          y[rr][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
+        const int colb = min(colw + 16 * C + 4 * g, tv.ldy - 4);
+        y[rr][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
       }
     }
   };
@@ -318,9 +320,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         }
         const int colb = colw + 16 * C + 4 * g;
         float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);   // a literal 1 without weights
-        if constexpr (HAS_W)
-          if (row_ok && colb < tv.ldy)
-            w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)row * tv.ldy + colb);
+        if constexpr (HAS_W)   // clamped like the counts
+          w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)min(row, tv.row_end - 1) * tv.ldy +
+                                                min(colb, tv.ldy - 4));
         const float ys[4] = {ycur[rr][C].x, ycur[rr][C].y, ycur[rr][C].z, ycur[rr][C].w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
         // Entries outside the block (rows past the tile end, padded columns)
