@@ -155,3 +155,61 @@ def test_header_compiles_and_struct_layout_matches_binding(tmp_path, struct):
     assert int(out["size"]) == ctypes.sizeof(cls)
     for f in fields:
         assert int(out[f]) == getattr(cls, f).offset, f
+
+
+def _header_prototypes():
+    """name -> number of parameters of every gmf_* function declared in include/*.h."""
+    protos = {}
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"\b(gmf_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", txt):
+            args = m.group(2).strip()
+            protos[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return protos
+
+
+def test_binding_signatures_match_header(lib):
+    """Every function the Python binding declares is in the header, with the
+    same number of parameters, and every header function is bound."""
+    protos = _header_prototypes()
+    assert len(protos) >= 40
+    so = lib.load_library()
+    for n, nargs in protos.items():
+        fn = getattr(so, n)
+        assert fn.argtypes is not None, f"{n} is not bound"
+        assert len(fn.argtypes) == nargs, (n, len(fn.argtypes), nargs)
+
+
+@pytest.mark.parametrize("name,extra", [
+    ("gmf_step", (1,)), ("gmf_set_precision", (0,)), ("gmf_fit", (1, 0.0, 1, None, None)),
+    ("gmf_run", (1, 1, None, None)), ("gmf_deviance", (None, None)),
+    ("gmf_row_deviance", (None,)), ("gmf_block_deviance", (None, 1)),
+    ("gmf_get_params", (None, None, None, None, 0)), ("gmf_set_params", (None, None, None, None)),
+    ("gmf_get_moments", (None, None, None, None)), ("gmf_get_schedule", (None, None, 1, 1, None)),
+    ("gmf_project", (None, 0, None, 0, 1, None, None, None, 1, 0, None, None, None)),
+    ("gmf_project_warm", (None, 0, None, 0, 1, None, None, 1, 1, None, None, None, None, None)),
+    ("gmf_batch_run", (1, 1, None)), ("gmf_set_trace", (None, 0)), ("gmf_set_timing", (1,)),
+    ("gmf_get_timing", (None, None, None)), ("gmf_sync", ()),
+])
+def test_null_handle_is_rejected_without_touching_the_device(lib, name, extra):
+    """A NULL context (or batch) handle is an argument error (GMF_EINVAL, with a
+    message), checked before any device work, so this runs without a GPU."""
+    so = lib.load_library()
+    rc = getattr(so, name)(None, *extra)
+    assert rc == lib.GMF_EINVAL, (name, rc)
+    assert b"NULL" in so.gmf_last_error(), name
+
+
+def test_null_handles_elsewhere(lib):
+    so = lib.load_library()
+    assert so.gmf_steps_done(None) == -1
+    assert so.gmf_project_workspace_bytes(None, 100) == 0
+    so.gmf_destroy(None)
+    so.gmf_batch_destroy(None)
+    so.gmf_encoder_destroy(None)
+    for name, extra in (("gmf_encoder_train", (None, 0, None, 1, 1, None)),
+                        ("gmf_encoder_forward", (None, 0, 1, None, 1)),
+                        ("gmf_encoder_loss_grad", (None, 0, None, 1, None, None)),
+                        ("gmf_encoder_get_weights", (None,) * 6)):
+        assert getattr(so, name)(None, *extra) == lib.GMF_EINVAL, name
+        assert so.gmf_encoder_last_error(), name
