@@ -243,9 +243,12 @@ __global__ void finalize_kernel(const double* dev, int ndev, const double* norm,
                                 const int* flag, double* out) {
   __shared__ double red[5][256];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 8
   for (int i = threadIdx.x; i < ndev; i += 256) acc[0] += dev[i];
   if (norm)
     for (int k = 0; k < 4; ++k)
+#pragma unroll 8
       for (int i = threadIdx.x; i < nnorm; i += 256) acc[1 + k] += norm[k * nnorm + i];
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
   __syncthreads();
@@ -268,6 +271,7 @@ hipError_t launch_finalize(const double* dev, int ndev, const double* norm, int 
 __global__ void sum_partials_kernel(const double* partial, int count, double* out) {
   __shared__ double red[256];
   double s = 0.0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < count; i += 256) s += partial[i];
   red[threadIdx.x] = s;
   __syncthreads();
