@@ -181,11 +181,14 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
 int gmf_deviance(void* ctx, double* total_host, double* penalized_host);
 
 /* gmf_row_deviance -- the deviance of every row, sum_j w_ij D(y_ij, mu_ij) at
- * the current parameters (D as in gmf_deviance), into per_row (device, n
- * doubles, the caller's row order).  Per entry: eta and the mu part of the
+ * the current parameters (the unit deviance D defined after eq. 2,
+ * Supplementary Table 1 times 2, NB form of Appendix B: the row terms of the
+ * full deviance of gmf_deviance), into per_row (device, n doubles, the
+ * caller's row order; caller-owned).  Per entry: eta and the mu part of the
  * unit deviance in float32, the count-only part and the row sums in float64
  * (fixed order); the rows add up to gmf_deviance's total up to the summation
- * order.  Asynchronous on the context's stream.  Errors: GMF_EINVAL. */
+ * order.  Asynchronous on the context's stream.  Errors: GMF_EINVAL (NULL
+ * ctx or per_row), GMF_EDEVICE (launch failure). */
 int gmf_row_deviance(void* ctx, double* per_row);
 
 /* gmf_block_deviance -- the block deviances of the last `count` steps, oldest
