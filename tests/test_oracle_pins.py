@@ -454,3 +454,116 @@ def test_warm_start_rows_picks_lower_row_deviance():
         assert warm[i] == (a < b)
         np.testing.assert_array_equal(U0[i], cand[i] if a < b else np.zeros(d))
     assert warm.any() and (~warm).any()       # both outcomes occur
+
+
+# ------------------------------------------------ step sizes (Section 3.2) --
+
+def _rate_table():
+    rows = []
+    for ln in open(os.path.join(GOLDEN, "learning_rate_table.txt")):
+        ln = ln.split("#")[0].split()
+        if ln:
+            rows.append((float(ln[0]), float(ln[1]), float(ln[2]), int(ln[3]), float(ln[4])))
+    return rows
+
+
+def test_learning_rate_matches_hand_table():
+    """rho_t against values of the definition evaluated outside the oracle
+    (30-digit decimal arithmetic), at t = 1, 2, 50, 1000 with k1 != 0: a shift
+    of t, or k0, k1 or tau misplaced, moves at least one entry."""
+    rows = _rate_table()
+    assert len(rows) == 8
+    for k0, k1, tau, t, want in rows:
+        cfg = G.Config(rate0=k0, decay=k1, tau=tau)
+        assert abs(G.learning_rate(cfg, t) - want) <= 1e-14 * want
+
+
+def test_step_uses_rate_of_global_counter():
+    """The displacement of step t divided by the Newton direction G/H is
+    rho_t of the hand table (alpha1 = alpha2 = 1, damping 0, full batch): the
+    oracle's step applies the rate of its own global counter t = 1, 2, ...."""
+    k0, k1, tau = 0.05, 0.05, 0.75
+    want = {t: v for a, b, c, t, v in _rate_table() if (a, b, c) == (k0, k1, tau)}
+    pr = gen_tiny("poisson")
+    o = _oracle(pr, alpha1=1.0, alpha2=1.0, damping=0.0, rate0=k0, decay=k1, tau=tau)
+    for t in range(1, 1001):
+        if t in want:
+            before = np.hstack([o.A, o.U])
+            o.step()
+            disp = (before - np.hstack([o.A, o.U])) / (o.Grow / o.Hrow)
+            np.testing.assert_allclose(disp, want[t], rtol=1e-8)
+        else:
+            o.step()
+        assert o.t == t
+
+
+# --------------------------------------- Fisher weight with w and phi ------
+
+@pytest.mark.parametrize("w,phi", [(1.0, 1.0), (2.5, 1.0), (1.0, 0.4), (0.3, 3.0)])
+def test_gaussian_d2_with_weights_and_dispersion_is_fd_second_derivative(w, phi):
+    """Gaussian-identity: the per-entry NLL w (y - mu)^2 / (2 phi) has second
+    derivative w / phi in eta (canonical link: observed = Fisher).  Central
+    second differences of the NLL pin D2 including its w and phi factors."""
+    rng = np.random.default_rng(21)
+    y = rng.normal(size=12)
+    eta = rng.normal(size=12)
+    h = 1e-3
+    sec = (_nll_entry("gaussian", "identity", y, eta + h, w, phi, 5.0)
+           - 2 * _nll_entry("gaussian", "identity", y, eta, w, phi, 5.0)
+           + _nll_entry("gaussian", "identity", y, eta - h, w, phi, 5.0)) / h ** 2
+    wv = np.full(12, w)
+    _, D2 = G.deviance_derivatives("gaussian", "identity", y, eta, wv, phi, 5.0)
+    np.testing.assert_allclose(D2, sec, rtol=1e-6)
+    np.testing.assert_allclose(D2, w / phi, rtol=1e-14)
+
+
+@pytest.mark.parametrize("family", ["poisson", "negbin"])
+@pytest.mark.parametrize("w,phi", [(2.5, 1.0), (0.4, 1.7)])
+def test_fisher_weight_with_weights_and_dispersion(family, w, phi):
+    """D2 = E_y[d^2 (w D / (2 phi)) / d eta^2] for weighted entries with a
+    dispersion, summed exactly over the support of the unweighted law."""
+    alpha = 5.0
+    for eta in (-0.7, 1.1):
+        mu = np.exp(eta)
+        ys = np.arange(0, 400)
+        pmf = np.exp(_loglik(family, ys, mu, alpha))
+        h = 1e-4
+        sec = (_nll_entry(family, "log", ys, eta + h, w, phi, alpha)
+               - 2 * _nll_entry(family, "log", ys, eta, w, phi, alpha)
+               + _nll_entry(family, "log", ys, eta - h, w, phi, alpha)) / h ** 2
+        _, D2 = G.deviance_derivatives(family, "log", ys[:1], np.array([mu]),
+                                       np.array([w]), phi, alpha)
+        np.testing.assert_allclose(np.sum(pmf * sec), D2[0], rtol=1e-6)
+
+
+# ------------------------------------------- Fisher-Yates uniformity -------
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_permutation_is_uniform_over_all_orderings(n):
+    """Over many stream keys every one of the n! orderings appears equally
+    often (chi-square at 0.999).  A shuffle drawing j from [0, i) (Sattolo:
+    cyclic permutations only) or from [0, n) (biased) fails."""
+    from itertools import permutations
+    from math import factorial
+    index = {p: k for k, p in enumerate(permutations(range(n)))}
+    nperm = factorial(n)
+    draws = 1000 * nperm
+    counts = np.zeros(nperm)
+    for seed in range(draws):
+        counts[index[tuple(G.permutation(seed, G.STREAM_ROWS, n).tolist())]] += 1
+    expect = draws / nperm
+    chi2 = ((counts - expect) ** 2 / expect).sum()
+    assert counts.min() > 0
+    assert chi2 < stats.chi2.ppf(0.999, nperm - 1)
+
+
+def test_permutation_positions_are_uniform_for_larger_n():
+    """Each element lands in each position with probability 1/n (n = 10)."""
+    n, draws = 10, 20000
+    pos = np.zeros((n, n))
+    for seed in range(draws):
+        perm = G.permutation(seed, G.STREAM_COLS, n)
+        pos[np.arange(n), perm] += 1
+    expect = draws / n
+    chi2 = ((pos - expect) ** 2 / expect).sum()
+    assert chi2 < stats.chi2.ppf(0.999, (n - 1) * (n - 1))
