@@ -8,8 +8,10 @@ Tolerances (norm-wise relative error, max|x - ref| / max|ref|):
   * Full deviance of a fixed state: 1e-6 (float32 per-entry deviance,
     float64 sums).
   * Final deviance after several epochs: 1e-4.
-  * BF16 path: errors are reported per output; the final deviance is gated
-    at 1e-3 relative on the small Poisson case.
+  * BF16 path (plain bfloat16 operands): reported only.  Its per-output
+    errors and its final deviance are printed and bounded loosely (5e-2 and
+    1e-3) so that a broken kernel still fails; it does not carry the 1e-4
+    final-deviance target, which split BF16 meets (see test_gpu_parity_fit).
   * Split BF16 path (BF16X3): every operand keeps about 16 mantissa bits
     (|x - hi - lo| <= 2^-18 |x|) and only the lo*lo product is dropped, so a
     product is off by at most about 2^-17 relative, 128 times float32's
@@ -206,9 +208,11 @@ def test_postprocess_matches_oracle_projection():
     g.close()
 
 
-def test_bf16_path_reports_errors_and_reaches_oracle_deviance():
+def test_bf16_path_reports_errors():
+    """Plain BF16, reported only: per-output errors after one epoch and the
+    final deviance after 20 epochs, with loose sanity bounds."""
     pr = gen_poisson_small()
-    say("bf16 c1: per-output errors after one epoch, final deviance after 20 epochs")
+    say("bf16 c1 (reported only): per-output errors after one epoch, final deviance after 20 epochs")
     o = oracle_for(pr)
     g = gpu_for(pr, precision="bf16")
     o.epoch()
