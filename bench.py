@@ -1,34 +1,47 @@
 #!/usr/bin/env python
 """Benchmark of block-wise adaptive SGD for GMF on one MI355X.
 
-Workload (the headline configuration): negative binomial GMF (alpha = 5, log
-link), n = 10,000 x m = 2,000, rank d = 10, row covariates X = [1, batch
-indicator, N(0,1)] (p = 3), Z = 1 (q = 1), about 85 % zeros, blocks of 10 % of
-the rows x 20 % of the columns (R = 10, S = 5), plain FP32 path.
+Headline workload: negative binomial GMF (alpha = 5, log link),
+n = 100,000 x m = 5,000, rank d = 20, row covariates X = [1, batch indicator,
+N(0,1)] (p = 3), Z = 1 (q = 1), about 85 % zeros, blocks of 10 % of the rows x
+20 % of the columns (10000 x 1000, R = 10, S = 5).  Y is 2 GB of int32.
 
 One benchmark "step" is one epoch: R*S = 50 block steps of Algorithm 1 (block
 select, eta, inverse link, D1/D2, the four contractions, EMA and step, block
 deviance) followed by one evaluation of the full deviance.  Inputs are resident
-in HBM before the timed region starts.
+in HBM before the timed region starts.  --warmup epochs run untimed on a
+throwaway context, then exactly --steps epochs are timed.
 
 Printed JSON line:
-  value             epochs/s of the FP32 arm (whole job, one GPU)
-  s_to_1e-4         seconds from the first launch until the evaluation of the
+  value             epochs/s of the headline arm (--headline, default BF16:
+                    bfloat16 operands on the matrix cores, float32
+                    accumulation, float64 moments and deviance sums), over the
+                    --steps timed epochs with the deviance of every epoch
+  s_to_1e4          seconds from the first launch until the evaluation of the
                     full deviance that is first within 1e-4 (relative) of D*,
                     the FP64 oracle's deviance after 200 epochs of the same
-                    seeded schedule (tests/golden), completed on the device;
-                    the deviance of every epoch is evaluated on the device
-                    after the epoch's steps, in order on the same stream
-  roofline          dominant kernel (the fused tile kernel): algorithmic
-                    bytes per launch / mean launch time from HIP events stamped
-                    by the launches themselves on the library's stream, against
-                    the 8 TB/s HBM peak; traffic = measured HBM bytes per launch
-                    (rocprofv3 counters, summary under profiles/)
-  cpu_baseline      the FP64 oracle on the host, bounded sample
-  arms              the same measurements for each arm: FP32, BF16, split BF16
-                    (bf16x3), optionally BF16 steps finished by FP32 steps over
-                    the last quarter of the epochs (bf16+fp32)
-  large             the 100000 x 5000 rank-20 workload (steps only), per precision
+                    seeded schedule (tests/golden/oracle_trace_c3.json),
+                    completed on the device.  Measured by a separate
+                    convergence run of --budget epochs (whatever --steps is),
+                    the deviance of every epoch evaluated on the device after
+                    the epoch's steps, in order on the same stream
+  arms              per arm (FP32 plain, BF16, split BF16): epochs/s with and
+                    without the per-epoch deviance, s and epochs to 1e-4 of D*,
+                    the final distance to D*, the launch statistics
+  roofline          the headline arm's step kernel: algorithmic work of the
+                    timed steps / the summed launch time from HIP events stamped
+                    by the launches themselves on the library's stream.  The
+                    bfloat16 arms are rated on bytes against 8 TB/s HBM: 4 B of
+                    y per block entry plus the panel and moment traffic
+                    2 (|I| (q+d) + |J| (p+d)) (4 + 2 x 8) B per step; the FP32
+                    arm on flops against the 157.3 TFLOP/s float32 peak:
+                    2 (3p + 3q + 5d) per block entry.  traffic = measured HBM
+                    bytes per launch (rocprofv3 counters, summary under
+                    profiles/), null when the kernel changed since
+  cpu_baseline      the FP64 oracle on the host, a bounded sample of block
+                    steps of the same workload, with all threads and with one
+  small             the 10000 x 2000 rank-10 workload (FP32 plain path over its
+                    200 epochs and the bfloat16 arms), against its own D*
   batched           64 uneven fits advanced together (gmf_batch_*) against the
                     same fits stepped one by one
   warm_start        learned warm start of 1,000,000 new rows: epochs and
@@ -68,37 +81,68 @@ def make_gmf(pr, precision):
     return GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0")
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the headline step kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
-    (step.hip, family.hpp, mfma.hpp) changed since those counters were taken."""
+PREC_CODE = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+
+
+def step_kernel_name(pr, precision):
+    """Template name of the step kernel that runs a workload: level_kernel<
+    precision, family, panel stride, block deviance, wavefronts per tile>."""
+    fam = {"poisson": 0, "negbin": 1, "gaussian": 2}[pr.family]
+    k = pr.p + pr.q + pr.d
+    # automatic panel stride: k rounded up to 16 (FP32, or k <= 16), else to 32
+    stride = (k + 15) // 16 * 16 if (precision == "fp32" or k <= 16) else (k + 31) // 32 * 32
+    return f"level_kernel<{PREC_CODE[precision]}, {fam}, {stride}, true, 4>"
+
+
+def recorded_traffic(pr, precision):
+    """HBM bytes per launch of a workload's step kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the summary has no
+    line for the kernel or the kernel sources (step.hip, family.hpp, mfma.hpp)
+    changed since those counters were taken."""
+    import glob
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_level_kernel_nb10000x2000_nb100000x5000.md")
-    if not os.path.exists(path):
-        return None
-    m = re.search(r"traffic_bytes_per_launch: (\d+) source: ([0-9a-f]+)", open(path).read())
-    if not m:
-        return None
     h = hashlib.sha256()
     for f in ("step.hip", "family.hpp", "mfma.hpp"):
         with open(os.path.join(ROOT, "paper_2412_20509_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return float(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
+    src = h.hexdigest()[:16]
+    want = step_kernel_name(pr, precision)
+    shape = f"{pr.n}x{pr.m}"
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        for m in re.finditer(r"traffic_bytes_per_launch: (\d+) source: ([0-9a-f]+) "
+                             r"kernel: (level_kernel<[^>]*>) workload: (\S+)",
+                             open(path).read()):
+            if m.group(3) == want and m.group(4) == shape and m.group(2) == src:
+                return float(m.group(1))
+    return None
 
 
-def tile_bytes_per_launch(pr):
-    """Algorithmic bytes of one tile-kernel launch: the block's counts (4 B each)
-    plus one read of the block's two panels (p+q+d floats per row/column)."""
+FP32_PEAK_TFS = 157.3
+
+
+def step_work(pr, bf16):
+    """Algorithmic work of one block step (the per-entry figures times the
+    block's entries): bytes = 4 B of y per entry plus the panel and moment
+    traffic 2 (|I| (q+d) + |J| (p+d)) (4 + 2 s) with s = 8 B (float64 moments)
+    on the bfloat16 paths and 4 B on the FP32 path; flops = 2 (3p + 3q + 5d)
+    per entry (eta, the two U-side and the two V-side contractions)."""
     ns, ms = pr.n / pr.R, pr.m / pr.S
-    return 4.0 * ns * ms + 4.0 * (ns + ms) * pr.k
+    s_mom = 8.0 if bf16 else 4.0
+    panels = 2.0 * (ns * (pr.q + pr.d) + ms * (pr.p + pr.d)) * (4.0 + 2.0 * s_mom)
+    return dict(bytes=4.0 * ns * ms + panels,
+                flops=2.0 * (3 * pr.p + 3 * pr.q + 5 * pr.d) * ns * ms)
 
 
-def run_arm(pr, precision, epochs, warmup, dstar, torch, polish=0):
-    """Timed epochs of one arm; polish > 0: the last `polish` epochs switch
-    from BF16 to FP32 steps (gmf_set_precision) on the same iterate."""
+def run_arm(pr, precision, epochs, warmup, budget, dstar, torch, polish=0):
+    """One arm: `warmup` untimed epochs on a throwaway context; exactly `epochs`
+    timed epochs, each followed by the full deviance on the device (gmf_run);
+    the same epochs without the deviance; a separate convergence run of
+    `budget` epochs with the deviance of every epoch, for the seconds and
+    epochs to 1e-4 of D*; HIP-event launch statistics over 2 more epochs.
+    polish > 0: the last `polish` epochs of the convergence run switch from
+    BF16 to FP32 steps (gmf_set_precision) on the same iterate."""
     per_epoch = pr.R * pr.S
-    # warm-up on a throwaway context (kernel loading, caches)
     g = make_gmf(pr, precision)
     for _ in range(warmup):
         g.step(per_epoch)
@@ -107,47 +151,49 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch, polish=0):
     del g
     torch.cuda.synchronize()
 
+    # the timed region: `epochs` epochs, the full deviance of every epoch
     g = make_gmf(pr, precision)
     torch.cuda.synchronize()
-    # the timed region: `epochs` epochs, the full deviance of every epoch
-    # evaluated after the epoch's steps on the same stream (gmf_run)
+    t0 = time.perf_counter()
+    g.run(epochs, eval_every=1)
+    wall = time.perf_counter() - t0
+    # the same epochs without the deviance evaluations, then the launch
+    # statistics of 2 more epochs from HIP events on the library's stream
+    g.close()
+    g = make_gmf(pr, precision)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.run(epochs, trace=False)
+    wall_steps = time.perf_counter() - t1
+    g.set_timing(True)
+    for _ in range(2):
+        g.step(per_epoch)
+    launch_ms, launches, nsteps = g.get_timing()
+    g.set_timing(False)
+    g.close()
+    del g
+
+    # convergence: `budget` epochs from the start, deviance every epoch
+    g = make_gmf(pr, precision)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     if polish > 0:
-        devs, ms = g.run(epochs - polish, eval_every=1)
+        devs, ms = g.run(budget - polish, eval_every=1)
         t_mid = time.perf_counter() - t0
         g.set_precision("fp32")
         d2, m2 = g.run(polish, eval_every=1)
         devs, ms = devs + d2, ms + [1e3 * t_mid + x for x in m2]
     else:
-        devs, ms = g.run(epochs, eval_every=1)
-    wall = time.perf_counter() - t0
+        devs, ms = g.run(budget, eval_every=1)
+    conv_wall = time.perf_counter() - t0
     t_hit = e_hit = None
+    rel_at_200 = None
     if dstar is not None:
-        for e, (dv, t) in enumerate(zip(devs, ms)):
-            if abs(dv - dstar) <= 1e-4 * dstar:
-                t_hit, e_hit = t / 1e3, e + 1
-                break
-    # the same epochs without the deviance evaluations (steps only)
-    g2 = make_gmf(pr, precision)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if polish > 0:
-        g2.run(epochs - polish, trace=False)
-        g2.set_precision("fp32")
-        g2.run(polish, trace=False)
-    else:
-        g2.run(epochs, trace=False)
-    wall_steps = time.perf_counter() - t1
-    g2.close()
-    del g2
-
-    # HIP events around every step launch on the library's stream (2 more epochs)
-    g.set_timing(True)
-    for _ in range(2):
-        g.step(per_epoch)
-        g.deviance()
-    launch_ms, launches, nsteps = g.get_timing()
-    g.set_timing(False)
+        e, t = first_hit(devs, ms, dstar)
+        if e is not None:
+            t_hit, e_hit = t / 1e3, e + 1
+        if len(devs) >= 200:
+            rel_at_200 = abs(devs[199] - dstar) / dstar
     t_pp = time.perf_counter()
     g.params(postprocess=1)
     t_pp = time.perf_counter() - t_pp
@@ -155,37 +201,38 @@ def run_arm(pr, precision, epochs, warmup, dstar, torch, polish=0):
     g.close()
     return dict(epochs=epochs, wall_s=wall, epochs_per_s=epochs / wall,
                 ms_per_epoch=1e3 * wall / epochs,
-                epochs_per_s_without_deviance=epochs / wall_steps, final_deviance=final,
-                rel_to_oracle=(abs(final - dstar) / dstar) if dstar else None,
+                epochs_per_s_without_deviance=epochs / wall_steps,
+                budget_epochs=budget, budget_wall_s=conv_wall,
+                final_deviance=final,
+                rel_to_oracle_final=(abs(final - dstar) / dstar) if dstar else None,
+                rel_to_oracle_at_epoch_200=rel_at_200,
+                deviance_at_epoch_200=devs[199] if len(devs) >= 200 else None,
+                deviance_every_10_epochs=devs[9::10],
                 s_to_1e4=t_hit, epochs_to_1e4=e_hit,
                 launch_ms_total=launch_ms, launches=int(launches), timed_steps=nsteps,
                 postprocess_s=t_pp)
 
 
-def run_throughput(pr, precision, epochs, torch):
-    """Steps-only throughput of a large workload: epochs/s, launch roofline and
-    the time of one full-deviance evaluation."""
-    per_epoch = pr.R * pr.S
-    g = make_gmf(pr, precision)
-    g.step(per_epoch)                  # warm-up epoch
-    torch.cuda.synchronize()
-    g.set_timing(True)
-    t0 = time.perf_counter()
-    g.step(epochs * per_epoch)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms, launches, nsteps = g.get_timing()
-    g.set_timing(False)
-    t1 = time.perf_counter()
-    dev, _ = g.deviance()
-    t_dev = time.perf_counter() - t1
-    g.close()
-    bytes_step = tile_bytes_per_launch(pr)
-    achieved = nsteps * bytes_step / (launch_ms * 1e-3) / 1e9
-    return dict(epochs=epochs, epochs_per_s=epochs / wall, ms_per_epoch=1e3 * wall / epochs,
-                launches=int(launches), steps=nsteps, launch_ms_total=launch_ms,
-                bytes_per_step=bytes_step, achieved_GBs=achieved, hbm_frac=achieved / HBM_PEAK_GBS,
-                deviance_eval_s=t_dev, deviance=dev)
+def roofline_of(pr, arm, precision):
+    """Roofline object of an arm's step kernel (see the module docstring)."""
+    bf16 = precision != "fp32"
+    w = step_work(pr, bf16)
+    launches = max(arm["launches"], 1)
+    t = arm["launch_ms_total"] * 1e-3
+    steps = arm["timed_steps"]
+    if bf16:
+        achieved = steps * w["bytes"] / t / 1e9
+        out = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=achieved / HBM_PEAK_GBS)
+    else:
+        achieved = steps * w["flops"] / t / 1e12
+        out = dict(bound="mfma", achieved=achieved, peak=FP32_PEAK_TFS, unit="TFLOP/s",
+                   frac=achieved / FP32_PEAK_TFS)
+    out.update(traffic=recorded_traffic(pr, precision), kernel=f"level_kernel ({precision})",
+               bytes_per_step=w["bytes"], flops_per_step=w["flops"],
+               steps_per_launch=steps / launches, mean_launch_us=1e6 * t / launches,
+               launches=arm["launches"])
+    return out
 
 
 def first_hit(trace, ms, target, rel=1e-4):
@@ -361,37 +408,97 @@ def run_batched(nfits, scale, epochs, torch):
     )
 
 
-def cpu_baseline(pr, epochs=3):
-    from threadpoolctl import threadpool_info
+def cpu_info():
+    """Host CPU model and logical CPU count (nproc) of the machine this runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, nproc
+
+
+def cpu_baseline(pr, steps=8, steps_1t=3, dev_rows=2000):
+    """The FP64 oracle (numpy) on a bounded sample of the workload: `steps`
+    block steps of the seeded schedule and the full deviance over `dev_rows`
+    rows (scaled to all n rows), with the BLAS pool at its default size and
+    again with one thread; an epoch is R*S steps plus one full deviance."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import gmf_oracle as G
     cfg = G.Config(family=pr.family, link=pr.link, phi=pr.phi, nb_alpha=pr.nb_alpha,
                    R=pr.R, S=pr.S, seed=pr.sched_seed)
     o = G.OracleGMF(cfg, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0)
-    t0 = time.perf_counter()
-    for _ in range(epochs):
-        o.epoch()
-        o.full_deviance()
-    dt = time.perf_counter() - t0
+    rows = np.arange(min(dev_rows, pr.n))
+
+    def sample(k):
+        t0 = time.perf_counter()
+        o.steps(k)
+        t_step = (time.perf_counter() - t0) / k
+        t0 = time.perf_counter()
+        mu = G.inverse_link(cfg.link, o.eta_full(rows), cfg.eps, cfg.eta_max)
+        float(G.unit_deviance(cfg.family, o.Y[rows], mu, cfg.nb_alpha).sum())
+        t_dev = (time.perf_counter() - t0) * pr.n / len(rows)
+        return t_step, t_dev
+
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return dict(value=epochs / dt, unit="epochs/s", cores=threads, kind="oracle",
-                sample=f"{epochs} epochs ({epochs * pr.R * pr.S} block steps of "
-                       f"{pr.n // pr.R}x{pr.m // pr.S}, each epoch followed by one full "
-                       f"deviance) of the same {pr.n}x{pr.m} NB workload, FP64 numpy",
-                seconds=dt)
+    t_step, t_dev = sample(steps)
+    with threadpool_limits(limits=1):
+        t_step1, t_dev1 = sample(steps_1t)
+    per_epoch = pr.R * pr.S
+    ep = per_epoch * t_step + t_dev
+    ep1 = per_epoch * t_step1 + t_dev1
+    model, nproc = cpu_info()
+    return dict(value=1.0 / ep, unit="epochs/s", cores=threads, kind="oracle",
+                sample=(f"{steps} block steps of {pr.n // pr.R}x{pr.m // pr.S} (seeded schedule, "
+                        f"from the start) and the full deviance over {len(rows)} of {pr.n} "
+                        f"rows of the same {pr.n}x{pr.m} NB workload, FP64 numpy; epoch = "
+                        f"{per_epoch} steps + 1 full deviance"),
+                single_thread_value=1.0 / ep1, cpu_model=model, nproc=nproc,
+                seconds_per_step=t_step, seconds_per_step_1_thread=t_step1,
+                full_deviance_s=t_dev, full_deviance_s_1_thread=t_dev1)
+
+
+DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
+
+
+def run_arms(pr, arms_arg, epochs, warmup, budget, dstar, torch, tag):
+    arms = {}
+    for arm in arms_arg.split(","):
+        prec, polish = arm, 0
+        if arm == "bf16+fp32":             # BF16, then FP32 for the last quarter
+            prec, polish = "bf16", budget // 4
+        log(f"{tag} arm {arm}: {warmup} warm-up + {epochs} timed epochs, "
+            f"{budget}-epoch convergence run")
+        arms[arm] = run_arm(pr, prec, epochs, warmup, budget, dstar, torch, polish=polish)
+        arms[arm]["roofline"] = roofline_of(pr, arms[arm], prec)
+        log(f"{tag} arm {arm}: {arms[arm]['epochs_per_s']:.1f} epochs/s, "
+            f"s to 1e-4: {arms[arm]['s_to_1e4']} ({arms[arm]['epochs_to_1e4']} epochs), "
+            f"roofline frac {arms[arm]['roofline']['frac']:.3f}")
+    return arms
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed epochs")
-    ap.add_argument("--warmup", type=int, default=3, help="untimed warm-up epochs")
+    ap.add_argument("--steps", type=int, default=20, help="timed epochs per arm")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed warm-up epochs per arm")
+    ap.add_argument("--budget", type=int, default=400,
+                    help="epochs of each arm's convergence run (s to 1e-4 of D*)")
     ap.add_argument("--arms", default="fp32,bf16,bf16x3",
                     help="fp32, bf16, bf16x3 (split bfloat16), bf16+fp32 (BF16 steps, "
-                         "FP32 for the last quarter)")
+                         "FP32 for the last quarter of the convergence run)")
+    ap.add_argument("--headline", default="bf16", help="arm whose epochs/s is `value`")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 100000x5000 rank-20 throughput section")
-    ap.add_argument("--large-epochs", type=int, default=5)
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 10000x2000 rank-10 section")
+    ap.add_argument("--small-epochs", type=int, default=200)
+    ap.add_argument("--small-budget", type=int, default=300)
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start section")
     ap.add_argument("--warm-rows", type=int, default=1_000_000)
     ap.add_argument("--warm-epochs", type=int, default=60,
@@ -425,47 +532,40 @@ def main():
     from paper_2412_20509_amd import gmf as _gmf  # noqa: F401  (fails if not built)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log("generating the 10000x2000 NB workload")
-    pr = make_problem("c2")
-    target = load_target("c2")
-    dstar = target["final"] if target else None
+    log("generating the 100000x5000 NB workload (rank 20)")
+    pr = make_problem("c3")
+    target = load_target("c3")
+    dstar = target["final"] if target and target.get("epochs_done") == target.get("epochs") \
+        else None
+    arms = run_arms(pr, args.arms, args.steps, args.warmup, args.budget, dstar, torch, "c3")
+    head = arms.get(args.headline) or next(iter(arms.values()))
+    head_name = args.headline if args.headline in arms else next(iter(arms))
 
-    arms = {}
-    for arm in args.arms.split(","):
-        prec, polish = arm, 0
-        if arm == "bf16+fp32":             # BF16, then FP32 for the last quarter
-            prec, polish = "bf16", args.steps // 4
-        log(f"arm {arm}: {args.warmup} warm-up + {args.steps} timed epochs")
-        arms[arm] = run_arm(pr, prec, args.steps, args.warmup, dstar, torch, polish=polish)
-        log(f"arm {arm}: {arms[arm]['epochs_per_s']:.1f} epochs/s, "
-            f"s to 1e-4: {arms[arm]['s_to_1e4']}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        cpu = cpu_baseline(pr)
+    workload = ("NB GMF 100000x5000, d=20, p=3, q=1, alpha=5, blocks 10000x1000 (R=10, S=5); "
+                "step = 1 epoch (50 block steps + full deviance)")
+    config = dict(workload=workload, n=pr.n, m=pr.m, d=pr.d, p=pr.p, q=pr.q, R=pr.R, S=pr.S,
+                  zero_fraction=float((pr.Y == 0).mean()), arm=head_name,
+                  comparison_arm="fp32")
+    del pr
 
-    main_arm = arms.get("fp32") or next(iter(arms.values()))
-    bytes_step = tile_bytes_per_launch(pr)
-    bytes_launch = bytes_step * main_arm["timed_steps"] / max(main_arm["launches"], 1)
-    mean_launch_s = main_arm["launch_ms_total"] * 1e-3 / max(main_arm["launches"], 1)
-    achieved = bytes_launch / mean_launch_s / 1e9
-    roof = dict(bound="hbm", kernel="level_kernel<0, 1, 16, true, 4>", achieved=achieved,
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=recorded_traffic(), bytes_per_launch=bytes_launch,
-                mean_launch_us=1e6 * mean_launch_s, steps_per_launch=main_arm["timed_steps"] /
-                max(main_arm["launches"], 1))
-    large = None
-    if not args.no_large:
-        log("generating the 100000x5000 NB workload (rank 20)")
-        pr3 = make_problem("c3")
-        large = {}
-        for prec in ("bf16x3", "bf16", "fp32"):
-            log(f"large workload, arm {prec}: 1 warm-up + {args.large_epochs} timed epochs")
-            large[prec] = run_throughput(pr3, prec, args.large_epochs, torch)
-            log(f"large {prec}: {large[prec]['epochs_per_s']:.1f} epochs/s, "
-                f"{large[prec]['achieved_GBs']:.0f} GB/s")
-        large["workload"] = ("NB GMF 100000x5000, d=20, p=3, q=1, alpha=5, blocks 10000x1000 "
-                             "(R=10, S=5); steps only, one full deviance timed separately")
-        del pr3
+    small = None
+    if not args.no_small:
+        log("generating the 10000x2000 NB workload")
+        pr2 = make_problem("c2")
+        t2 = load_target("c2")
+        small = dict(workload="NB GMF 10000x2000, d=10, p=3, q=1, alpha=5, blocks 1000x400",
+                     oracle_final_deviance=t2["final"] if t2 else None,
+                     arms=run_arms(pr2, "fp32,bf16,bf16x3", args.small_epochs, args.warmup,
+                                   args.small_budget, t2["final"] if t2 else None, torch, "c2"))
+        pr2_keep = pr2
     warm = None
     if not args.no_warm:
-        warm = run_warm_start(pr, args.warm_rows, args.warm_epochs, args.encoder_epochs, torch)
+        pr2w = pr2_keep if small is not None else make_problem("c2")
+        warm = run_warm_start(pr2w, args.warm_rows, args.warm_epochs, args.encoder_epochs, torch)
         log(f"warm start: cold {warm['cold']['epochs_to_1e4']} epochs, "
             f"warm {warm['warm']['epochs_to_1e4']} epochs, "
             f"warm bf16x3 {warm['warm_bf16x3']['epochs_to_1e4']} epochs, "
@@ -476,25 +576,17 @@ def main():
         batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)
         log(f"batched fits: {batched['batched_graph_epochs_per_s']:.1f} epochs/s batched "
             f"(graph), {batched['separate_epochs_per_s']:.1f} separately")
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on the host")
-        cpu = cpu_baseline(pr)
 
     out = dict(
-        metric=METRIC, value=main_arm["epochs_per_s"], unit="epochs/s", n_gpus=1,
-        steps=args.steps, warmup=args.warmup, ms_per_step=main_arm["ms_per_epoch"],
-        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
-        data="synthetic",
-        config=dict(workload="NB GMF 10000x2000, d=10, p=3, q=1, alpha=5, blocks "
-                              "1000x400 (R=10, S=5), FP32 plain path, step = 1 epoch "
-                              "(50 block steps + full deviance)",
-                    n=pr.n, m=pr.m, d=pr.d, p=pr.p, q=pr.q, R=pr.R, S=pr.S,
-                    zero_fraction=float((pr.Y == 0).mean())),
-        s_to_1e4=main_arm["s_to_1e4"], epochs_to_1e4=main_arm["epochs_to_1e4"],
-        oracle_final_deviance=dstar, roofline=roof, cpu_baseline=cpu, large=large,
-        warm_start=warm, batched=batched,
-        arms={k: {kk: vv for kk, vv in v.items()} for k, v in arms.items()},
+        metric=METRIC, value=head["epochs_per_s"], unit="epochs/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=head["ms_per_epoch"],
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=DTYPE[head_name.split("+")[0]],
+        data="synthetic", config=config,
+        s_to_1e4=head["s_to_1e4"], epochs_to_1e4=head["epochs_to_1e4"],
+        s_to_1e4_by_arm={k: v["s_to_1e4"] for k, v in arms.items()},
+        epochs_per_s_by_arm={k: v["epochs_per_s"] for k, v in arms.items()},
+        oracle_final_deviance=dstar, roofline=head["roofline"], cpu_baseline=cpu,
+        arms=arms, small=small, warm_start=warm, batched=batched,
     )
     print(json.dumps(out))
 

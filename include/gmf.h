@@ -192,7 +192,9 @@ int gmf_deviance(void* ctx, double* total_host, double* penalized_host);
 int gmf_row_deviance(void* ctx, double* per_row);
 
 /* gmf_block_deviance -- the block deviances of the last `count` steps, oldest
- * first, into host memory (count <= min(steps done, 4096)).  Synchronises. */
+ * first, into host memory (count <= min(steps done, 4096)).  Synchronises.
+ * GMF_EINVAL when the context skips them (skip_block_deviance) or when any
+ * of the requested steps was run by gmf_batch_run, which forms none. */
 int gmf_block_deviance(void* ctx, double* out_host, int64_t count);
 
 /* gmf_get_params -- copy B (m x p), Gamma (n x q), U (n x d), V (m x d) into
@@ -216,6 +218,29 @@ int gmf_get_moments(void* ctx, double* Grow, double* Hrow, double* Gcol,
  * starting values); the moments and the step counter are kept. */
 int gmf_set_params(void* ctx, const float* B, const float* A, const float* U,
                    const float* V);
+
+/* Saved state (checkpoint and resume of Algorithm 1).  The state of a fit
+ * between two steps is: the parameters [Gamma, U] and [B, V] (with the
+ * covariates, in the context's permuted panel layout), the four float64
+ * smoothed moments of eq. 12, the step counter t (which is also the cursor of
+ * the seeded schedule: the partitions and the row-block draws are functions
+ * of seed, n, m, R and S) and the ring of the last block deviances.
+ * gmf_state_bytes -- host bytes of a saved state of ctx (0 for NULL). */
+size_t gmf_state_bytes(void* ctx);
+/* gmf_save_state -- write ctx's state into host_buf (caller-owned host
+ * memory of at least gmf_state_bytes bytes): a header (format version, shape,
+ * family, link, panel stride, schedule seed, step-size and EMA parameters, t)
+ * and the device regions, copied after the work queued on ctx's stream.
+ * Synchronises.  Errors: GMF_EINVAL (NULL, buffer too small), GMF_EDEVICE. */
+int gmf_save_state(void* ctx, void* host_buf, size_t bytes);
+/* gmf_load_state -- replace ctx's state by a saved one.  ctx must come from
+ * gmf_init with the same Y, X, Z, W and a configuration with the same n, m, d,
+ * p, q, R, S, family, link, panel stride, seed, rate0, decay, tau, alpha1,
+ * alpha2 and damping (the starting values passed to gmf_init do not matter);
+ * else GMF_EINVAL and ctx is unchanged.  Steps run after the load continue
+ * the saved run exactly: the same blocks, step sizes and results, bit for bit,
+ * as if it had not been interrupted.  Synchronises. */
+int gmf_load_state(void* ctx, const void* host_buf, size_t bytes);
 
 /* gmf_get_schedule -- the drawn schedule, for checking: row_perm_host (n) and
  * col_perm_host (m) receive the permutations (block r holds

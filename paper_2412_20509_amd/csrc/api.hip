@@ -355,6 +355,7 @@ struct Ctx {
   std::vector<int> row_perm, col_perm;
   uint64_t draw_start = 0;
   int64_t t = 0;
+  int64_t batched_upto = 0;   // last step run by gmf_batch_run (no block deviance)
   int want_block_dev = 1;
   unsigned long long launches = 0;
   // optional per-task trace (caller's device buffer)
@@ -889,6 +890,9 @@ int gmf_block_deviance(void* ctx, double* out_host, int64_t count) {
   Ctx* c = as_ctx(ctx);
   if (count < 0 || count > c->t || count > kDevRing) return fail(GMF_EINVAL, "bad count");
   if (!c->want_block_dev) return fail(GMF_EINVAL, "block deviance is off (skip_block_deviance)");
+  if (count > 0 && c->t - count + 1 <= c->batched_upto)
+    return fail(GMF_EINVAL, "the requested steps include steps run by gmf_batch_run, which "
+                            "form no block deviance");
   std::vector<double> ring(kDevRing);
   HIP_TRY(hipMemcpyAsync(ring.data(), c->at<double>(c->P.o_devring), sizeof(double) * kDevRing,
                          hipMemcpyDeviceToHost, c->st));
@@ -1004,6 +1008,122 @@ int64_t gmf_steps_done(void* ctx) { return ctx ? as_ctx(ctx)->t : -1; }
 int gmf_sync(void* ctx) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   return check_flag(as_ctx(ctx));
+}
+
+
+// ------------------------------------------------------------ saved state --
+// A saved state is a header followed by the device regions that make up the
+// iterate of Algorithm 1 between two steps: both panels (the parameters, and
+// the covariates, in the context's permuted order), the four float64 moment
+// arrays of eq. 12 and the ring of block deviances.  The partitions and the
+// row-block draws are functions of (seed, n, m, R, S), recorded in the header
+// and checked on load, so the step counter t is the whole schedule cursor.
+namespace {
+constexpr char kStateMagic[8] = {'G', 'M', 'F', 'S', 'T', 'A', 'T', '1'};
+struct StateHeader {
+  char magic[8];
+  uint32_t version, nregion;
+  int64_t n, m;
+  int32_t d, p, q, R, S, family, link, KP;
+  uint64_t seed;
+  int64_t t, batched_upto;
+  double stepsize_params[6];   // rate0, decay, tau, alpha1, alpha2, damping (checked)
+  uint64_t region_bytes[8];
+};
+constexpr int kStateRegions = 7;
+
+void state_regions(const Ctx* c, size_t off[kStateRegions], size_t bytes[kStateRegions]) {
+  const Plan& P = c->P;
+  off[0] = P.o_Prow; bytes[0] = sizeof(float) * (size_t)P.n * P.KP;
+  off[1] = P.o_Pcol; bytes[1] = sizeof(float) * (size_t)P.m * P.KP;
+  off[2] = P.o_Grow; bytes[2] = sizeof(double) * (size_t)P.n * P.KU;
+  off[3] = P.o_Hrow; bytes[3] = sizeof(double) * (size_t)P.n * P.KU;
+  off[4] = P.o_Gcol; bytes[4] = sizeof(double) * (size_t)P.m * P.KV;
+  off[5] = P.o_Hcol; bytes[5] = sizeof(double) * (size_t)P.m * P.KV;
+  off[6] = P.o_devring; bytes[6] = sizeof(double) * kDevRing;
+}
+
+void fill_header(const Ctx* c, StateHeader& h) {
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = 1;
+  h.nregion = kStateRegions;
+  const gmf_config& f = c->cfg;
+  h.n = f.n; h.m = f.m; h.d = f.d; h.p = f.p; h.q = f.q; h.R = f.R; h.S = f.S;
+  h.family = f.family; h.link = f.link; h.KP = c->P.KP; h.seed = f.seed;
+  h.t = c->t; h.batched_upto = c->batched_upto;
+  const double sp[6] = {f.rate0, f.decay, f.tau, f.alpha1, f.alpha2, f.damping};
+  std::memcpy(h.stepsize_params, sp, sizeof(sp));
+  size_t off[kStateRegions], bytes[kStateRegions];
+  state_regions(c, off, bytes);
+  for (int i = 0; i < kStateRegions; ++i) h.region_bytes[i] = bytes[i];
+}
+
+size_t state_total(const Ctx* c) {
+  size_t off[kStateRegions], bytes[kStateRegions];
+  state_regions(c, off, bytes);
+  size_t tot = sizeof(StateHeader);
+  for (int i = 0; i < kStateRegions; ++i) tot += bytes[i];
+  return tot;
+}
+}  // namespace
+
+extern "C" size_t gmf_state_bytes(void* ctx) {
+  return ctx ? state_total(as_ctx(ctx)) : 0;
+}
+
+extern "C" int gmf_save_state(void* ctx, void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer smaller than gmf_state_bytes");
+  StateHeader h;
+  fill_header(c, h);
+  char* out = static_cast<char*>(host_buf);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off[kStateRegions], rb[kStateRegions];
+  state_regions(c, off, rb);
+  size_t at = sizeof(h);
+  for (int i = 0; i < kStateRegions; ++i) {
+    HIP_TRY(hipMemcpyAsync(out + at, c->ws + off[i], rb[i], hipMemcpyDeviceToHost, c->st));
+    at += rb[i];
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  return check_flag(c);
+}
+
+extern "C" int gmf_load_state(void* ctx, const void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (bytes < sizeof(StateHeader)) return fail(GMF_EINVAL, "buffer too small for a state header");
+  StateHeader h, mine;
+  std::memcpy(&h, host_buf, sizeof(h));
+  fill_header(c, mine);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 || h.nregion != kStateRegions)
+    return fail(GMF_EINVAL, "not a saved libgmf state (magic or version)");
+  if (h.n != mine.n || h.m != mine.m || h.d != mine.d || h.p != mine.p || h.q != mine.q ||
+      h.R != mine.R || h.S != mine.S || h.family != mine.family || h.link != mine.link ||
+      h.KP != mine.KP || h.seed != mine.seed)
+    return fail(GMF_EINVAL, "saved state belongs to a context of another shape, family, panel "
+                            "stride or schedule seed");
+  if (std::memcmp(h.stepsize_params, mine.stepsize_params, sizeof(h.stepsize_params)) != 0)
+    return fail(GMF_EINVAL, "saved state was made with other step-size or EMA parameters");
+  for (int i = 0; i < kStateRegions; ++i)
+    if (h.region_bytes[i] != mine.region_bytes[i]) return fail(GMF_EINVAL, "region size mismatch");
+  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer shorter than the saved state");
+  if (h.t < 0 || h.batched_upto < 0 || h.batched_upto > h.t)
+    return fail(GMF_EINVAL, "corrupt step counter");
+  size_t off[kStateRegions], rb[kStateRegions];
+  state_regions(c, off, rb);
+  const char* in = static_cast<const char*>(host_buf);
+  size_t at = sizeof(h);
+  for (int i = 0; i < kStateRegions; ++i) {
+    HIP_TRY(hipMemcpyAsync(c->ws + off[i], in + at, rb[i], hipMemcpyHostToDevice, c->st));
+    at += rb[i];
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  c->t = h.t;
+  c->batched_upto = h.batched_upto;
+  return check_flag(c);
 }
 
 // ------------------------------------------------------------ projection --
@@ -1673,7 +1793,10 @@ extern "C" int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every,
       if (rc != GMF_OK) return rc;
     }
     ++b->used;
-    for (Ctx* c : b->fits) c->t += (int64_t)c->P.R * c->P.S;
+    for (Ctx* c : b->fits) {
+      c->t += (int64_t)c->P.R * c->P.S;
+      c->batched_upto = c->t;
+    }
     if ((e + 1) % eval_every == 0 && dev_trace_host) {
       for (int f = 0; f < nfits; ++f) {
         Ctx* c = b->fits[f];

@@ -91,6 +91,9 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(i32)]),
         "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
                                         C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_state_bytes": (C.c_size_t, [vp]),
+        "gmf_save_state": (C.c_int, [vp, vp, C.c_size_t]),
+        "gmf_load_state": (C.c_int, [vp, vp, C.c_size_t]),
         "gmf_project_workspace_bytes": (C.c_size_t, [vp, i64]),
         "gmf_project": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, vp, i32, i32, vp, vp,
                                   f64p]),
@@ -437,6 +440,19 @@ class GMF:
                                             device=self.device) if c > 0 else None)
         gmf_set_params(self.ctx, conv(B, self.m, self.p), conv(A, self.n, self.q),
                        conv(U, self.n, self.d), conv(V, self.m, self.d))
+
+    def save_state(self) -> bytes:
+        """gmf_save_state: the fit's state as bytes (host memory)."""
+        lib = load_library()
+        nbytes = lib.gmf_state_bytes(self.ctx)
+        buf = C.create_string_buffer(nbytes)
+        _check(lib.gmf_save_state(self.ctx, C.cast(buf, C.c_void_p), nbytes))
+        return buf.raw
+
+    def load_state(self, state: bytes):
+        """gmf_load_state: resume from bytes written by save_state."""
+        buf = C.create_string_buffer(state, len(state))
+        _check(load_library().gmf_load_state(self.ctx, C.cast(buf, C.c_void_p), len(state)))
 
     def schedule(self, t_first=1, count=0):
         return gmf_get_schedule(self.ctx, self.n, self.m, t_first, count)

@@ -124,3 +124,23 @@ def test_tune_records_fastest_candidate_and_plans_with_it():
     M.tune_table_clear()
     g0.close()
     g1.close()
+
+
+def test_block_deviance_of_batched_steps_is_an_error(problems):
+    """gmf_batch_run forms no block deviance: asking for the block deviance of
+    a batched step is an argument error, while steps run on their own after
+    the batch report theirs."""
+    from paper_2412_20509_amd.gmf import Batch, GMFError
+    print("[case] block deviance after a batched epoch", flush=True)
+    pr = problems[0]
+    g = gpu_for(pr, panel_stride=32)
+    b = Batch([g], table_epochs=1, use_graph=False)
+    b.run(1, trace=False)
+    b.close()
+    with pytest.raises(GMFError):
+        g.block_deviance(1)
+    g.step(3)
+    assert len(g.block_deviance(3)) == 3
+    with pytest.raises(GMFError):
+        g.block_deviance(4)
+    g.close()
