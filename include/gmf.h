@@ -320,6 +320,21 @@ int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int
                      int32_t frozen, float* A_out, float* U_out, double* dev_trace_host,
                      double* epoch_ms_host, int64_t* fallback_rows_host);
 
+/* gmf_project_noalloc -- gmf_project without a workspace argument and without
+ * any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * projection's scratch (the new rows' block layout, panels, moments, deviance
+ * partials) lives in a resident 64 MiB device array of the library, one per
+ * device, held until the process ends; its address is taken at gmf_init.
+ * Limit: gmf_project_workspace_bytes(ctx, n_new) must be <= 64 MiB (about
+ * 8,000 new rows of 2,000 columns), else GMF_EWORKSPACE.  Every call on a
+ * device shares that device's array and overwrites it: calls that overlap on
+ * one device (several streams or threads) race and must be serialised by the
+ * caller.  Arguments, results and the other errors as gmf_project. */
+int gmf_project_noalloc(void* ctx, const void* Ynew, int32_t y_dtype, int64_t n_new,
+                        const float* Xnew, const float* A0, const float* U0, int32_t epochs,
+                        int32_t frozen, float* A_out, float* U_out, double* dev_trace_host);
+
 /* ---------------------------------------------------------------------------
  * Batched fits.  Many independent contexts (each from gmf_init, any shapes,
  * Poisson / NB / Gaussian mixed) advance together: one epoch of the batch is

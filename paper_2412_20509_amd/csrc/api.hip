@@ -356,6 +356,7 @@ struct Ctx {
   uint64_t draw_start = 0;
   int64_t t = 0;
   int64_t batched_upto = 0;   // last step run by gmf_batch_run (no block deviance)
+  int device = 0;             // HIP device of the context
   int want_block_dev = 1;
   unsigned long long launches = 0;
   // optional per-task trace (caller's device buffer)
@@ -622,6 +623,32 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
 }  // namespace
 
 // =================================================================== C ABI ==
+// Resident scratch of the allocation-free projection (gmf_project_noalloc):
+// one array per device, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address from hipGetSymbolAddress, taken once per
+// device with that device current (at gmf_init) and kept in scratch_addr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+
+int resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMF_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_addr[dev]) return GMF_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(GMF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  scratch_addr[dev] = ptr;
+  return GMF_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void gmf_config_default(gmf_config* c) {
@@ -673,8 +700,13 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(GMF_EDEVICE, std::string("libgmf needs a gfx950 device, found ") + prop.gcnArchName);
 
+  {
+    const int rc = resolve_scratch(dev);
+    if (rc != GMF_OK) return rc;
+  }
   Ctx* c = new Ctx();
   c->cfg = *cfg;
+  c->device = dev;
   make_plan(cfg, W != nullptr, c->P);
   const Plan& P = c->P;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < P.total) {
@@ -943,16 +975,16 @@ int gmf_set_params(void* ctx, const float* B, const float* A, const float* U, co
   // The covariates are kept: read them back out of the panels first.
   // Packing rewrites whole rows, so stage X and Z through the panel itself:
   // pack only the parameter columns by unpacking X/Z into scratch.
-  float* scratch = reinterpret_cast<float*>(c->at<double>(P.o_post));
+  float* stage = reinterpret_cast<float*>(c->at<double>(P.o_post));
   const size_t need = (size_t)std::max<int64_t>(P.n * P.p, P.m * P.q);
   if (need * sizeof(float) > sizeof(double) * gmf::postprocess_scratch_doubles(P.n, P.m, P.KP, kSumsqBlocks))
     return fail(GMF_EINVAL, "internal: scratch too small");
   const int* rp = c->at<int>(P.o_rowperm);
   const int* cp = c->at<int>(P.o_colperm);
-  if (P.p > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Prow), P.KP, rp, P.n, 0, P.p, scratch, c->st));
-  HIP_TRY(gmf::launch_pack_panel(scratch, P.p, A, P.q, U, P.d, rp, P.n, P.KP, c->at<float>(P.o_Prow), c->st));
-  if (P.q > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, cp, P.m, P.p, P.q, scratch, c->st));
-  HIP_TRY(gmf::launch_pack_panel(B, P.p, scratch, P.q, V, P.d, cp, P.m, P.KP, c->at<float>(P.o_Pcol), c->st));
+  if (P.p > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Prow), P.KP, rp, P.n, 0, P.p, stage, c->st));
+  HIP_TRY(gmf::launch_pack_panel(stage, P.p, A, P.q, U, P.d, rp, P.n, P.KP, c->at<float>(P.o_Prow), c->st));
+  if (P.q > 0) HIP_TRY(gmf::launch_unpack_panel(c->at<float>(P.o_Pcol), P.KP, cp, P.m, P.p, P.q, stage, c->st));
+  HIP_TRY(gmf::launch_pack_panel(B, P.p, stage, P.q, V, P.d, cp, P.m, P.KP, c->at<float>(P.o_Pcol), c->st));
   return check_flag(c);
 }
 
@@ -1243,7 +1275,7 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
 #undef PH2D
   // ---- data: Y in column-block-major order, the new row panel, the frozen column panel
   float* Yb = reinterpret_cast<float*>(at(Q.o_Yb));
-  HIP_TRY(hipMemsetAsync(Yb, 0, sizeof(float) * (size_t)n_new * P.LDtot, st));
+  HIP_TRY(gmf::launch_fill_i32(reinterpret_cast<int*>(Yb), n_new * P.LDtot, 0, st));
   HIP_TRY(gmf::launch_permute_y(Ynew, y_dtype == GMF_Y_INT32, nullptr, n_new, P.m,
                                 reinterpret_cast<int*>(at(Q.o_zero)), reinterpret_cast<int*>(at(Q.o_iota)),
                                 c->at<int>(P.o_colblk), c->at<int>(P.o_colloc),
@@ -1398,6 +1430,24 @@ extern "C" int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void
   return project_impl(as_ctx(ctx), ws, ws_bytes, Ynew, y_dtype, n_new, Xnew, nullptr, nullptr,
                       kInitWarm, U_cand, epochs, frozen, A_out, U_out, dev_trace_host,
                       epoch_ms_host, fallback_rows_host);
+}
+
+extern "C" int gmf_project_noalloc(void* ctx, const void* Ynew, int32_t y_dtype, int64_t n_new,
+                                   const float* Xnew, const float* A0, const float* U0,
+                                   int32_t epochs, int32_t frozen, float* A_out, float* U_out,
+                                   double* dev_trace_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  void* ws = (c->device >= 0 && c->device < kMaxDevices) ? scratch_addr[c->device] : nullptr;
+  if (!ws) return fail(GMF_EDEVICE, "resident scratch of the context's device is not set up");
+  ProjPlan Q;
+  if (!make_proj_plan(c, n_new, Q)) return fail(GMF_EINVAL, "bad n_new");
+  if (Q.total > kScratchBytes)
+    return fail(GMF_EWORKSPACE, "projection of " + std::to_string(n_new) + " rows needs " +
+                                    std::to_string(Q.total) + " bytes of scratch, more than the " +
+                                    std::to_string(kScratchBytes) + " resident bytes");
+  return project_impl(c, ws, kScratchBytes, Ynew, y_dtype, n_new, Xnew, A0, U0, kInitGiven,
+                      nullptr, epochs, frozen, A_out, U_out, dev_trace_host, nullptr, nullptr);
 }
 
 int gmf_set_trace(void* ctx, void* buffer, int64_t records) {

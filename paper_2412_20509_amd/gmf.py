@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
                                   f64p]),
         "gmf_project_warm": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i64, vp, vp, i32, i32, vp,
                                        vp, f64p, f64p, C.POINTER(i64)]),
+        "gmf_project_noalloc": (C.c_int, [vp, vp, i32, i64, vp, vp, vp, i32, i32, vp, vp, f64p]),
         "gmf_batch_workspace_bytes": (C.c_size_t, [C.POINTER(vp), i32, i32]),
         "gmf_batch_init": (C.c_int, [C.POINTER(vp), C.POINTER(vp), i32, vp, C.c_size_t, i32,
                                      i32]),
@@ -247,6 +248,15 @@ def gmf_project(ctx, workspace, Ynew, y_dtype, n_new, Xnew, A0, U0, epochs, froz
                                       workspace.numel() * workspace.element_size(), _ptr(Ynew),
                                       y_dtype, int(n_new), _ptr(Xnew), _ptr(A0), _ptr(U0),
                                       int(epochs), int(frozen), _ptr(A_out), _ptr(U_out), tr))
+    return None if tr is None else list(tr)
+
+
+def gmf_project_noalloc(ctx, Ynew, y_dtype, n_new, Xnew, A0, U0, epochs, frozen, A_out, U_out,
+                        trace: bool = False):
+    tr = (C.c_double * (epochs + 1))() if trace else None
+    _check(load_library().gmf_project_noalloc(ctx, _ptr(Ynew), y_dtype, int(n_new), _ptr(Xnew),
+                                              _ptr(A0), _ptr(U0), int(epochs), int(frozen),
+                                              _ptr(A_out), _ptr(U_out), tr))
     return None if tr is None else list(tr)
 
 
@@ -495,6 +505,30 @@ class GMF:
         Ao = t.empty((n_new, self.q), dtype=t.float32, device=self.device) if self.q else None
         Uo = t.empty((n_new, self.d), dtype=t.float32, device=self.device)
         tr = gmf_project(self.ctx, wsv, Yt, ydt, n_new, Xt, At, Ut, epochs, frozen, Ao, Uo, trace)
+        self.stream.synchronize()
+        return Ao, Uo, tr
+
+    def project_noalloc(self, Ynew, Xnew, A0, U0, epochs, frozen=0, trace=False):
+        """gmf_project_noalloc: as project(), with the library's resident scratch
+        instead of a workspace (inputs and outputs still come from the caller)."""
+        t = self.torch
+        n_new = Ynew.shape[0]
+        if isinstance(Ynew, t.Tensor):
+            Yt = Ynew.to(self.device).contiguous()
+            ydt = GMF_Y_INT32 if Yt.dtype == t.int32 else GMF_Y_FLOAT32
+        elif np.issubdtype(np.asarray(Ynew).dtype, np.integer):
+            Yt = t.as_tensor(np.ascontiguousarray(Ynew, dtype=np.int32), device=self.device)
+            ydt = GMF_Y_INT32
+        else:
+            Yt = t.as_tensor(np.ascontiguousarray(Ynew, dtype=np.float32), device=self.device)
+            ydt = GMF_Y_FLOAT32
+        Xt = self._dev_f32(Xnew, n_new, self.p)
+        At = self._dev_f32(A0, n_new, self.q)
+        Ut = self._dev_f32(U0, n_new, self.d)
+        Ao = t.empty((n_new, self.q), dtype=t.float32, device=self.device) if self.q else None
+        Uo = t.empty((n_new, self.d), dtype=t.float32, device=self.device)
+        tr = gmf_project_noalloc(self.ctx, Yt, ydt, n_new, Xt, At, Ut, epochs, frozen, Ao, Uo,
+                                 trace)
         self.stream.synchronize()
         return Ao, Uo, tr
 
