@@ -242,6 +242,41 @@ int gmf_save_state(void* ctx, void* host_buf, size_t bytes);
  * as if it had not been interrupted.  Synchronises. */
 int gmf_load_state(void* ctx, const void* host_buf, size_t bytes);
 
+/* gmf_initialize_workspace_bytes -- device bytes gmf_initialize needs for a
+ * test matrix of k columns (0 for NULL ctx or k outside [d, 64]). */
+size_t gmf_initialize_workspace_bytes(void* ctx, int32_t k);
+/* gmf_initialize -- the paper's parameter initialization (Section 4.1,
+ * "Parameter initialization"), in the least-squares form the paper gives for
+ * high-dimensional data, computed on the device into the context's iterate:
+ *   1. B' = (X'X)^-1 X'L with L = g(y + c) (the m column regressions);
+ *   2. Gamma = (L - X B') Z (Z'Z)^-1 (the n row regressions given the column
+ *      offsets);
+ *   3. U: the d leading left singular vectors of the residual matrix E at
+ *      mu~ = g^-1(X B' + Gamma Z') (clamped like the fit's mean), Pearson
+ *      residuals (y - mu~) sqrt(w / nu(mu~)) (residual = 0) or deviance
+ *      residuals sign(y - mu~) sqrt(w D(y, mu~)) (residual = 1), by a
+ *      randomized range finder (Halko, Martinsson and Tropp 2011): Y = E Omega,
+ *      power_iters times Y = E orth(E' orth(Y)), Q = orth(Y), then the left
+ *      singular vectors of Q'E mapped back by Q;
+ *   4. V' = (U'U)^-1 U' (L - X B' - Gamma Z') (the column regressions of the
+ *      link-scale residual on the scores);
+ *   then each pair (u_k, v_k) is rescaled to equal norms (U V' unchanged).
+ * No n x m matrix is stored: every pass forms its entries from Y on the fly;
+ * sums are float32 within 64-entry tiles and float64 across tiles (fixed
+ * order); orthonormalisation (two rounds of Cholesky QR), the normal
+ * equations and the small eigenproblem are float64.
+ *   ws / ws_bytes: caller device workspace (gmf_initialize_workspace_bytes).
+ *   Omega: m x k float32 test matrix (device, the caller's column order;
+ *     normally standard Gaussian draws), d <= k <= 64.
+ *   y_offset: c in g(y + c); < 0 selects 1/2 for the log link, 0 for the
+ *     identity link; the log link needs c > 0.
+ * Needs p + q <= 32 and no step run yet (t = 0); the moments stay zero.
+ * Synchronises.  Errors: GMF_EINVAL, GMF_EWORKSPACE, GMF_ENUMERIC (X'X,
+ * Z'Z or U'U not positive definite, or the range finder's basis lost rank),
+ * GMF_EDEVICE. */
+int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float* Omega, int32_t k,
+                   int32_t power_iters, int32_t residual, double y_offset);
+
 /* gmf_get_schedule -- the drawn schedule, for checking: row_perm_host (n) and
  * col_perm_host (m) receive the permutations (block r holds
  * row_perm[floor(rn/R) .. floor((r+1)n/R)-1]); r_host receives the row

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgmf.so")
-SOURCES = ["api.hip", "step.hip", "aux.hip", "post.hip", "mlp.hip", "warm.hip", "project.hip"]
+SOURCES = ["api.hip", "step.hip", "aux.hip", "post.hip", "mlp.hip", "warm.hip", "project.hip", "init.hip"]
 ARCH = "gfx950"
 
 

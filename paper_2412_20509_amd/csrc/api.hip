@@ -1043,121 +1043,6 @@ int gmf_sync(void* ctx) {
 }
 
 
-// ------------------------------------------------------------ saved state --
-// A saved state is a header followed by the device regions that make up the
-// iterate of Algorithm 1 between two steps: both panels (the parameters, and
-// the covariates, in the context's permuted order), the four float64 moment
-// arrays of eq. 12 and the ring of block deviances.  The partitions and the
-// row-block draws are functions of (seed, n, m, R, S), recorded in the header
-// and checked on load, so the step counter t is the whole schedule cursor.
-namespace {
-constexpr char kStateMagic[8] = {'G', 'M', 'F', 'S', 'T', 'A', 'T', '1'};
-struct StateHeader {
-  char magic[8];
-  uint32_t version, nregion;
-  int64_t n, m;
-  int32_t d, p, q, R, S, family, link, KP;
-  uint64_t seed;
-  int64_t t, batched_upto;
-  double stepsize_params[6];   // rate0, decay, tau, alpha1, alpha2, damping (checked)
-  uint64_t region_bytes[8];
-};
-constexpr int kStateRegions = 7;
-
-void state_regions(const Ctx* c, size_t off[kStateRegions], size_t bytes[kStateRegions]) {
-  const Plan& P = c->P;
-  off[0] = P.o_Prow; bytes[0] = sizeof(float) * (size_t)P.n * P.KP;
-  off[1] = P.o_Pcol; bytes[1] = sizeof(float) * (size_t)P.m * P.KP;
-  off[2] = P.o_Grow; bytes[2] = sizeof(double) * (size_t)P.n * P.KU;
-  off[3] = P.o_Hrow; bytes[3] = sizeof(double) * (size_t)P.n * P.KU;
-  off[4] = P.o_Gcol; bytes[4] = sizeof(double) * (size_t)P.m * P.KV;
-  off[5] = P.o_Hcol; bytes[5] = sizeof(double) * (size_t)P.m * P.KV;
-  off[6] = P.o_devring; bytes[6] = sizeof(double) * kDevRing;
-}
-
-void fill_header(const Ctx* c, StateHeader& h) {
-  std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, kStateMagic, 8);
-  h.version = 1;
-  h.nregion = kStateRegions;
-  const gmf_config& f = c->cfg;
-  h.n = f.n; h.m = f.m; h.d = f.d; h.p = f.p; h.q = f.q; h.R = f.R; h.S = f.S;
-  h.family = f.family; h.link = f.link; h.KP = c->P.KP; h.seed = f.seed;
-  h.t = c->t; h.batched_upto = c->batched_upto;
-  const double sp[6] = {f.rate0, f.decay, f.tau, f.alpha1, f.alpha2, f.damping};
-  std::memcpy(h.stepsize_params, sp, sizeof(sp));
-  size_t off[kStateRegions], bytes[kStateRegions];
-  state_regions(c, off, bytes);
-  for (int i = 0; i < kStateRegions; ++i) h.region_bytes[i] = bytes[i];
-}
-
-size_t state_total(const Ctx* c) {
-  size_t off[kStateRegions], bytes[kStateRegions];
-  state_regions(c, off, bytes);
-  size_t tot = sizeof(StateHeader);
-  for (int i = 0; i < kStateRegions; ++i) tot += bytes[i];
-  return tot;
-}
-}  // namespace
-
-extern "C" size_t gmf_state_bytes(void* ctx) {
-  return ctx ? state_total(as_ctx(ctx)) : 0;
-}
-
-extern "C" int gmf_save_state(void* ctx, void* host_buf, size_t bytes) {
-  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
-  Ctx* c = as_ctx(ctx);
-  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer smaller than gmf_state_bytes");
-  StateHeader h;
-  fill_header(c, h);
-  char* out = static_cast<char*>(host_buf);
-  std::memcpy(out, &h, sizeof(h));
-  size_t off[kStateRegions], rb[kStateRegions];
-  state_regions(c, off, rb);
-  size_t at = sizeof(h);
-  for (int i = 0; i < kStateRegions; ++i) {
-    HIP_TRY(hipMemcpyAsync(out + at, c->ws + off[i], rb[i], hipMemcpyDeviceToHost, c->st));
-    at += rb[i];
-  }
-  HIP_TRY(hipStreamSynchronize(c->st));
-  return check_flag(c);
-}
-
-extern "C" int gmf_load_state(void* ctx, const void* host_buf, size_t bytes) {
-  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
-  Ctx* c = as_ctx(ctx);
-  if (bytes < sizeof(StateHeader)) return fail(GMF_EINVAL, "buffer too small for a state header");
-  StateHeader h, mine;
-  std::memcpy(&h, host_buf, sizeof(h));
-  fill_header(c, mine);
-  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 || h.nregion != kStateRegions)
-    return fail(GMF_EINVAL, "not a saved libgmf state (magic or version)");
-  if (h.n != mine.n || h.m != mine.m || h.d != mine.d || h.p != mine.p || h.q != mine.q ||
-      h.R != mine.R || h.S != mine.S || h.family != mine.family || h.link != mine.link ||
-      h.KP != mine.KP || h.seed != mine.seed)
-    return fail(GMF_EINVAL, "saved state belongs to a context of another shape, family, panel "
-                            "stride or schedule seed");
-  if (std::memcmp(h.stepsize_params, mine.stepsize_params, sizeof(h.stepsize_params)) != 0)
-    return fail(GMF_EINVAL, "saved state was made with other step-size or EMA parameters");
-  for (int i = 0; i < kStateRegions; ++i)
-    if (h.region_bytes[i] != mine.region_bytes[i]) return fail(GMF_EINVAL, "region size mismatch");
-  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer shorter than the saved state");
-  if (h.t < 0 || h.batched_upto < 0 || h.batched_upto > h.t)
-    return fail(GMF_EINVAL, "corrupt step counter");
-  size_t off[kStateRegions], rb[kStateRegions];
-  state_regions(c, off, rb);
-  const char* in = static_cast<const char*>(host_buf);
-  size_t at = sizeof(h);
-  for (int i = 0; i < kStateRegions; ++i) {
-    HIP_TRY(hipMemcpyAsync(c->ws + off[i], in + at, rb[i], hipMemcpyHostToDevice, c->st));
-    at += rb[i];
-  }
-  HIP_TRY(hipStreamSynchronize(c->st));
-  c->t = h.t;
-  c->batched_upto = h.batched_upto;
-  return check_flag(c);
-}
-
 // ------------------------------------------------------------ projection --
 namespace {
 
@@ -1609,6 +1494,515 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ saved state --
+// A saved state is a header followed by the device regions that make up the
+// iterate of Algorithm 1 between two steps: both panels (the parameters, and
+// the covariates, in the context's permuted order), the four float64 moment
+// arrays of eq. 12 and the ring of block deviances.  The partitions and the
+// row-block draws are functions of (seed, n, m, R, S), recorded in the header
+// and checked on load, so the step counter t is the whole schedule cursor.
+namespace {
+constexpr char kStateMagic[8] = {'G', 'M', 'F', 'S', 'T', 'A', 'T', '1'};
+struct StateHeader {
+  char magic[8];
+  uint32_t version, nregion;
+  int64_t n, m;
+  int32_t d, p, q, R, S, family, link, KP;
+  uint64_t seed;
+  int64_t t, batched_upto;
+  double stepsize_params[6];   // rate0, decay, tau, alpha1, alpha2, damping (checked)
+  uint64_t region_bytes[8];
+};
+constexpr int kStateRegions = 7;
+
+void state_regions(const Ctx* c, size_t off[kStateRegions], size_t bytes[kStateRegions]) {
+  const Plan& P = c->P;
+  off[0] = P.o_Prow; bytes[0] = sizeof(float) * (size_t)P.n * P.KP;
+  off[1] = P.o_Pcol; bytes[1] = sizeof(float) * (size_t)P.m * P.KP;
+  off[2] = P.o_Grow; bytes[2] = sizeof(double) * (size_t)P.n * P.KU;
+  off[3] = P.o_Hrow; bytes[3] = sizeof(double) * (size_t)P.n * P.KU;
+  off[4] = P.o_Gcol; bytes[4] = sizeof(double) * (size_t)P.m * P.KV;
+  off[5] = P.o_Hcol; bytes[5] = sizeof(double) * (size_t)P.m * P.KV;
+  off[6] = P.o_devring; bytes[6] = sizeof(double) * kDevRing;
+}
+
+void fill_header(const Ctx* c, StateHeader& h) {
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = 1;
+  h.nregion = kStateRegions;
+  const gmf_config& f = c->cfg;
+  h.n = f.n; h.m = f.m; h.d = f.d; h.p = f.p; h.q = f.q; h.R = f.R; h.S = f.S;
+  h.family = f.family; h.link = f.link; h.KP = c->P.KP; h.seed = f.seed;
+  h.t = c->t; h.batched_upto = c->batched_upto;
+  const double sp[6] = {f.rate0, f.decay, f.tau, f.alpha1, f.alpha2, f.damping};
+  std::memcpy(h.stepsize_params, sp, sizeof(sp));
+  size_t off[kStateRegions], bytes[kStateRegions];
+  state_regions(c, off, bytes);
+  for (int i = 0; i < kStateRegions; ++i) h.region_bytes[i] = bytes[i];
+}
+
+size_t state_total(const Ctx* c) {
+  size_t off[kStateRegions], bytes[kStateRegions];
+  state_regions(c, off, bytes);
+  size_t tot = sizeof(StateHeader);
+  for (int i = 0; i < kStateRegions; ++i) tot += bytes[i];
+  return tot;
+}
+}  // namespace
+
+extern "C" size_t gmf_state_bytes(void* ctx) {
+  return ctx ? state_total(as_ctx(ctx)) : 0;
+}
+
+extern "C" int gmf_save_state(void* ctx, void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer smaller than gmf_state_bytes");
+  StateHeader h;
+  fill_header(c, h);
+  char* out = static_cast<char*>(host_buf);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off[kStateRegions], rb[kStateRegions];
+  state_regions(c, off, rb);
+  size_t at = sizeof(h);
+  for (int i = 0; i < kStateRegions; ++i) {
+    HIP_TRY(hipMemcpyAsync(out + at, c->ws + off[i], rb[i], hipMemcpyDeviceToHost, c->st));
+    at += rb[i];
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  return check_flag(c);
+}
+
+extern "C" int gmf_load_state(void* ctx, const void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (bytes < sizeof(StateHeader)) return fail(GMF_EINVAL, "buffer too small for a state header");
+  StateHeader h, mine;
+  std::memcpy(&h, host_buf, sizeof(h));
+  fill_header(c, mine);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 || h.nregion != kStateRegions)
+    return fail(GMF_EINVAL, "not a saved libgmf state (magic or version)");
+  if (h.n != mine.n || h.m != mine.m || h.d != mine.d || h.p != mine.p || h.q != mine.q ||
+      h.R != mine.R || h.S != mine.S || h.family != mine.family || h.link != mine.link ||
+      h.KP != mine.KP || h.seed != mine.seed)
+    return fail(GMF_EINVAL, "saved state belongs to a context of another shape, family, panel "
+                            "stride or schedule seed");
+  if (std::memcmp(h.stepsize_params, mine.stepsize_params, sizeof(h.stepsize_params)) != 0)
+    return fail(GMF_EINVAL, "saved state was made with other step-size or EMA parameters");
+  for (int i = 0; i < kStateRegions; ++i)
+    if (h.region_bytes[i] != mine.region_bytes[i]) return fail(GMF_EINVAL, "region size mismatch");
+  if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer shorter than the saved state");
+  if (h.t < 0 || h.batched_upto < 0 || h.batched_upto > h.t)
+    return fail(GMF_EINVAL, "corrupt step counter");
+  size_t off[kStateRegions], rb[kStateRegions];
+  state_regions(c, off, rb);
+  const char* in = static_cast<const char*>(host_buf);
+  size_t at = sizeof(h);
+  for (int i = 0; i < kStateRegions; ++i) {
+    HIP_TRY(hipMemcpyAsync(c->ws + off[i], in + at, rb[i], hipMemcpyHostToDevice, c->st));
+    at += rb[i];
+  }
+  HIP_TRY(hipStreamSynchronize(c->st));
+  c->t = h.t;
+  c->batched_upto = h.batched_upto;
+  return check_flag(c);
+}
+
+
+// --------------------------------------------------------- initialization --
+// The paper's initialization (Section 4.1, least-squares form): OLS column
+// effects on L = g(y + c), OLS row effects on the residual given those
+// offsets, the leading left singular vectors of the Pearson (or deviance)
+// residual matrix at mu~ = g^-1(X B' + Gamma Z') by a randomized range finder
+// with power iterations from the caller's test matrix, OLS loadings of the
+// link-scale residual on those scores, and equal norms within each pair
+// (u_k, v_k).  Every n x m quantity is formed entry by entry inside the passes
+// of init.hip; the k x k algebra (Cholesky factors, the symmetric eigenproblem
+// of the range finder's small matrix) runs in float64 on the host.
+namespace {
+
+constexpr int kInitChunkRows = 1024;
+constexpr int kGramParts = 128;
+
+struct InitPlan {
+  int kmax = 0, nrt = 0, nct = 0, nch = 0;
+  std::vector<int> rt, ct, ch;   // row tiles (r, li0), column tiles (s, lj0), chunks (r, li0, rows)
+  size_t o_rt, o_ct, o_ch, o_part, o_Dn, o_Dn2, o_Fn, o_Dm, o_Dm2, o_Fm, o_gpart, o_G, o_M, o_scale,
+      o_colfill, total;
+};
+
+bool make_init_plan(const Ctx* c, int k, InitPlan& I) {
+  const Plan& P = c->P;
+  if (k < P.d || k > 64) return false;
+  I.kmax = std::max(k, std::max(P.p, P.q));
+  I.rt.clear(); I.ct.clear(); I.ch.clear();
+  for (int r = 0; r < P.R; ++r)
+    for (int li = 0; li < P.nrows[r]; li += 64) { I.rt.push_back(r); I.rt.push_back(li); }
+  for (int s = 0; s < P.S; ++s)
+    for (int lj = 0; lj < P.mcols[s]; lj += 64) { I.ct.push_back(s); I.ct.push_back(lj); }
+  for (int r = 0; r < P.R; ++r)
+    for (int li = 0; li < P.nrows[r]; li += kInitChunkRows) {
+      I.ch.push_back(r); I.ch.push_back(li); I.ch.push_back(std::min(kInitChunkRows, P.nrows[r] - li));
+    }
+  I.nrt = (int)I.rt.size() / 2; I.nct = (int)I.ct.size() / 2; I.nch = (int)I.ch.size() / 3;
+  const int64_t part_floats = std::max<int64_t>((int64_t)P.S * P.n, (int64_t)I.nch * P.m) * I.kmax;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  I.o_rt = take(sizeof(int) * I.rt.size());
+  I.o_ct = take(sizeof(int) * I.ct.size());
+  I.o_ch = take(sizeof(int) * I.ch.size());
+  I.o_part = take(sizeof(float) * (size_t)part_floats);
+  I.o_Dn = take(sizeof(double) * (size_t)P.n * I.kmax);
+  I.o_Dn2 = take(sizeof(double) * (size_t)P.n * I.kmax);
+  I.o_Fn = take(sizeof(float) * (size_t)P.n * I.kmax);
+  I.o_Dm = take(sizeof(double) * (size_t)P.m * I.kmax);
+  I.o_Dm2 = take(sizeof(double) * (size_t)P.m * I.kmax);
+  I.o_Fm = take(sizeof(float) * (size_t)P.m * I.kmax);
+  I.o_gpart = take(sizeof(double) * kGramParts * 64 * 64);
+  I.o_G = take(sizeof(double) * 64 * 64);
+  I.o_M = take(sizeof(double) * 64 * 64);
+  I.o_scale = take(sizeof(double) * 64);
+  I.o_colfill = take(sizeof(float) * (size_t)P.m);
+  I.total = o;
+  return true;
+}
+
+// G = R'R with R upper triangular (k x k, row-major); false if G is not
+// positive definite.
+bool cholesky_upper(const std::vector<double>& G, int k, std::vector<double>& R) {
+  R.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double s = G[(size_t)j * k + j];
+    for (int i = 0; i < j; ++i) s -= R[(size_t)i * k + j] * R[(size_t)i * k + j];
+    if (!(s > 0.0)) return false;
+    const double rjj = std::sqrt(s);
+    R[(size_t)j * k + j] = rjj;
+    for (int l = j + 1; l < k; ++l) {
+      double t = G[(size_t)j * k + l];
+      for (int i = 0; i < j; ++i) t -= R[(size_t)i * k + j] * R[(size_t)i * k + l];
+      R[(size_t)j * k + l] = t / rjj;
+    }
+  }
+  return true;
+}
+
+// Inverse of an upper triangular matrix (back substitution, column by column).
+void upper_inverse(const std::vector<double>& R, int k, std::vector<double>& Ri) {
+  Ri.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    Ri[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= j; ++l) s += R[(size_t)i * k + l] * Ri[(size_t)l * k + j];
+      Ri[(size_t)i * k + j] = -s / R[(size_t)i * k + i];
+    }
+  }
+}
+
+// Eigenvalues (descending) and eigenvectors (columns of V, row-major k x k) of
+// a symmetric matrix by cyclic Jacobi rotations.
+void sym_eigen(std::vector<double> A, int k, std::vector<double>& ev, std::vector<double>& V) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        const double a = A[(size_t)i * k + j] * A[(size_t)i * k + j];
+        tot += a;
+        if (i != j) off += a;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int l = 0; l < k; ++l) {   // A <- A J (columns p, q)
+          const double alp = A[(size_t)l * k + p], alq = A[(size_t)l * k + q];
+          A[(size_t)l * k + p] = cs * alp - sn * alq;
+          A[(size_t)l * k + q] = sn * alp + cs * alq;
+        }
+        for (int l = 0; l < k; ++l) {   // A <- J' A (rows p, q)
+          const double apl = A[(size_t)p * k + l], aql = A[(size_t)q * k + l];
+          A[(size_t)p * k + l] = cs * apl - sn * aql;
+          A[(size_t)q * k + l] = sn * apl + cs * aql;
+        }
+        for (int l = 0; l < k; ++l) {   // V <- V J
+          const double vlp = V[(size_t)l * k + p], vlq = V[(size_t)l * k + q];
+          V[(size_t)l * k + p] = cs * vlp - sn * vlq;
+          V[(size_t)l * k + q] = sn * vlp + cs * vlq;
+        }
+      }
+  }
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return A[(size_t)a * k + a] > A[(size_t)b * k + b]; });
+  ev.resize(k);
+  std::vector<double> Vs((size_t)k * k);
+  for (int j = 0; j < k; ++j) {
+    ev[j] = A[(size_t)order[j] * k + order[j]];
+    for (int i = 0; i < k; ++i) Vs[(size_t)i * k + j] = V[(size_t)i * k + order[j]];
+  }
+  V.swap(Vs);
+}
+
+struct InitRun {
+  Ctx* c;
+  InitPlan I;
+  char* W;
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(W + off); }
+
+  gmf::InitPassArgs pass_args(int mode, int ke, float c_off, const float* Q, int kq,
+                              int64_t nout) const {
+    const Plan& P = c->P;
+    gmf::InitPassArgs a{};
+    a.Yb = c->at<float>(P.o_Yb);
+    a.Wb = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+    a.LDtot = P.LDtot;
+    a.Prow = c->at<float>(P.o_Prow);
+    a.Pcol = c->at<float>(P.o_Pcol);
+    a.KP = P.KP; a.ke = ke;
+    a.ro = c->at<int>(P.o_ro); a.nrows = c->at<int>(P.o_nrows);
+    a.co = c->at<int>(P.o_co); a.mcols = c->at<int>(P.o_mcols);
+    a.ldy = c->at<int>(P.o_ld); a.coP = c->at<int64_t>(P.o_coP);
+    a.mode = mode; a.fam = P.fam; a.log_link = c->cfg.link == GMF_LINK_LOG;
+    a.c_off = c_off;
+    a.f = family_args(c->cfg);
+    a.colfill = nullptr;
+    a.Q = Q; a.kq = kq;
+    a.part = at<float>(I.o_part);
+    a.nout = nout;
+    return a;
+  }
+  // E Q over all column blocks: out (n x kq) = sum over s of the partials.
+  int row_pass(int mode, int ke, float c_off, const float* Qm, int kq, double* out64, float* out32) {
+    const Plan& P = c->P;
+    gmf::InitPassArgs a = pass_args(mode, ke, c_off, Qm, kq, P.n);
+    a.tiles = at<int>(I.o_rt);
+    HIP_TRY(gmf::launch_init_pass(a, true, I.nrt, P.S, c->st));
+    HIP_TRY(gmf::launch_sum_parts(a.part, P.S, P.n * kq, P.n * kq, out64, out32, c->st));
+    return GMF_OK;
+  }
+  // E' Q over all row chunks: out (m x kq).
+  int col_pass(int mode, int ke, float c_off, const float* Qn, int kq, double* out64, float* out32,
+               const float* colfill = nullptr) {
+    const Plan& P = c->P;
+    gmf::InitPassArgs a = pass_args(mode, ke, c_off, Qn, kq, P.m);
+    a.tiles = at<int>(I.o_ct);
+    a.chunks = at<int>(I.o_ch);
+    a.colfill = colfill;
+    HIP_TRY(gmf::launch_init_pass(a, false, I.nct, I.nch, c->st));
+    HIP_TRY(gmf::launch_sum_parts(a.part, I.nch, P.m * kq, P.m * kq, out64, out32, c->st));
+    return GMF_OK;
+  }
+  // k x k Gram matrix A'A of a tall float64 operand, on the host.
+  int gram(const double* A, int64_t rows, int k, std::vector<double>& G) {
+    HIP_TRY(gmf::launch_gram(A, rows, k, at<double>(I.o_gpart), kGramParts, at<double>(I.o_G), c->st));
+    G.resize((size_t)k * k);
+    HIP_TRY(hipMemcpyAsync(G.data(), at<double>(I.o_G), sizeof(double) * G.size(),
+                           hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    return GMF_OK;
+  }
+  // Copies a small host matrix to the device and waits, so that the host
+  // buffer may be released at once.
+  int upload_small(const std::vector<double>& M, size_t off) {
+    HIP_TRY(hipMemcpyAsync(at<double>(off), M.data(), sizeof(double) * M.size(),
+                           hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    return GMF_OK;
+  }
+  // A (rows x k, float64, in place through Tmp) <- an orthonormal basis of its
+  // range, by two rounds of Cholesky QR; the float32 copy goes to out32.
+  int orth(double* A, double* Tmp, int64_t rows, int k, float* out32) {
+    for (int round = 0; round < 2; ++round) {
+      std::vector<double> G, R, Ri;
+      int rc = gram(A, rows, k, G);
+      if (rc != GMF_OK) return rc;
+      if (!cholesky_upper(G, k, R))
+        return fail(GMF_ENUMERIC, "initialization: the range finder's basis lost rank");
+      upper_inverse(R, k, Ri);
+      rc = upload_small(Ri, I.o_M);
+      if (rc != GMF_OK) return rc;
+      HIP_TRY(gmf::launch_apply(A, rows, k, k, at<double>(I.o_M), nullptr, Tmp,
+                                round == 1 ? out32 : nullptr, nullptr, 0, 0, c->st));
+      HIP_TRY(hipMemcpyAsync(A, Tmp, sizeof(double) * rows * k, hipMemcpyDeviceToDevice, c->st));
+    }
+    return GMF_OK;
+  }
+  // (A'A)^-1 for a tall operand A (rows x k).
+  int normal_inverse(const double* A, int64_t rows, int k, std::vector<double>& Inv) {
+    std::vector<double> G, R, Ri;
+    int rc = gram(A, rows, k, G);
+    if (rc != GMF_OK) return rc;
+    if (!cholesky_upper(G, k, R))
+      return fail(GMF_ENUMERIC, "initialization: a design Gram matrix is not positive definite");
+    upper_inverse(R, k, Ri);
+    Inv.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+        for (int l = std::max(i, j); l < k; ++l) s += Ri[(size_t)i * k + l] * Ri[(size_t)j * k + l];
+        Inv[(size_t)i * k + j] = s;
+      }
+    return GMF_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" size_t gmf_initialize_workspace_bytes(void* ctx, int32_t k) {
+  if (!ctx) return 0;
+  InitPlan I;
+  if (!make_init_plan(as_ctx(ctx), k, I)) return 0;
+  return I.total;
+}
+
+extern "C" int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float* Omega, int32_t k,
+                              int32_t power_iters, int32_t residual, double y_offset) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  InitRun run;
+  run.c = c;
+  if (!make_init_plan(c, k, run.I)) return fail(GMF_EINVAL, "k must be in [d, 64]");
+  const InitPlan& I = run.I;
+  if (!Omega) return fail(GMF_EINVAL, "Omega is NULL");
+  if (power_iters < 0 || power_iters > 64) return fail(GMF_EINVAL, "power_iters must be in [0, 64]");
+  if (residual != 0 && residual != 1) return fail(GMF_EINVAL, "residual must be 0 (Pearson) or 1 (deviance)");
+  if (P.p + P.q > 32) return fail(GMF_EINVAL, "initialization needs p + q <= 32");
+  if (c->t != 0) return fail(GMF_EINVAL, "initialization must precede the first step");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < I.total)
+    return fail(GMF_EWORKSPACE, "initialization workspace NULL, misaligned or smaller than " +
+                                    std::to_string(I.total) + " bytes");
+  run.W = static_cast<char*>(ws);
+  const float c_off = (float)(y_offset >= 0 ? y_offset : (c->cfg.link == GMF_LINK_LOG ? 0.5 : 0.0));
+  if (c->cfg.link == GMF_LINK_LOG && !(c_off > 0))
+    return fail(GMF_EINVAL, "the log link needs y_offset > 0");
+  hipStream_t st = c->st;
+  float* Prow = c->at<float>(P.o_Prow);
+  float* Pcol = c->at<float>(P.o_Pcol);
+  HIP_TRY(hipMemcpyAsync(run.at<int>(I.o_rt), I.rt.data(), sizeof(int) * I.rt.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(run.at<int>(I.o_ct), I.ct.data(), sizeof(int) * I.ct.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(run.at<int>(I.o_ch), I.ch.data(), sizeof(int) * I.ch.size(), hipMemcpyHostToDevice, st));
+  // start from B = Gamma = U = V = 0 (X and Z stay)
+  if (P.p > 0) HIP_TRY(gmf::launch_panel_cols(Pcol, P.KP, P.m, 0, P.p, nullptr, nullptr, 1, st));
+  if (P.q > 0) HIP_TRY(gmf::launch_panel_cols(Prow, P.KP, P.n, P.p, P.q, nullptr, nullptr, 1, st));
+  HIP_TRY(gmf::launch_panel_cols(Prow, P.KP, P.n, P.p + P.q, P.d, nullptr, nullptr, 1, st));
+  HIP_TRY(gmf::launch_panel_cols(Pcol, P.KP, P.m, P.p + P.q, P.d, nullptr, nullptr, 1, st));
+  double* Dn = run.at<double>(I.o_Dn);
+  double* Dn2 = run.at<double>(I.o_Dn2);
+  float* Fn = run.at<float>(I.o_Fn);
+  double* Dm = run.at<double>(I.o_Dm);
+  double* Dm2 = run.at<double>(I.o_Dm2);
+  float* Fm = run.at<float>(I.o_Fm);
+  int rc = GMF_OK;
+  std::vector<double> Inv;
+  // 1. column effects: B' = (X'X)^-1 X'L
+  if (P.p > 0) {
+    HIP_TRY(gmf::launch_panel_cols(Prow, P.KP, P.n, 0, P.p, Dn, Fn, 0, st));
+    rc = run.col_pass(0, 0, c_off, Fn, P.p, Dm, nullptr);
+    if (rc != GMF_OK) return rc;
+    rc = run.normal_inverse(Dn, P.n, P.p, Inv);
+    if (rc != GMF_OK) return rc;
+    rc = run.upload_small(Inv, I.o_M);
+    if (rc != GMF_OK) return rc;
+    HIP_TRY(gmf::launch_apply(Dm, P.m, P.p, P.p, run.at<double>(I.o_M), nullptr, nullptr, nullptr,
+                              Pcol, P.KP, 0, st));
+  }
+  // 2. row effects given the column offsets: Gamma = (L - X B') Z (Z'Z)^-1
+  if (P.q > 0) {
+    HIP_TRY(gmf::launch_panel_cols(Pcol, P.KP, P.m, P.p, P.q, Dm, Fm, 0, st));
+    rc = run.row_pass(1, P.p, c_off, Fm, P.q, Dn, nullptr);
+    if (rc != GMF_OK) return rc;
+    rc = run.normal_inverse(Dm, P.m, P.q, Inv);
+    if (rc != GMF_OK) return rc;
+    rc = run.upload_small(Inv, I.o_M);
+    if (rc != GMF_OK) return rc;
+    HIP_TRY(gmf::launch_apply(Dn, P.n, P.q, P.q, run.at<double>(I.o_M), nullptr, nullptr, nullptr,
+                              Prow, P.KP, P.p, st));
+  }
+  // 3. scores: randomized range finder on the residual matrix E
+  const int ke = P.p + P.q;
+  const int emode = residual == 0 ? 2 : 3;
+  HIP_TRY(gmf::launch_pack_panel(Omega, k, nullptr, 0, nullptr, 0, c->at<int>(P.o_colperm), P.m, k,
+                                 Fm, st));
+  rc = run.row_pass(emode, ke, c_off, Fm, k, Dn, nullptr);          // Y = E Omega
+  if (rc != GMF_OK) return rc;
+  for (int it = 0; it < power_iters; ++it) {
+    rc = run.orth(Dn, Dn2, P.n, k, Fn);
+    if (rc != GMF_OK) return rc;
+    rc = run.col_pass(emode, ke, c_off, Fn, k, Dm, nullptr);        // E' Q
+    if (rc != GMF_OK) return rc;
+    rc = run.orth(Dm, Dm2, P.m, k, Fm);
+    if (rc != GMF_OK) return rc;
+    rc = run.row_pass(emode, ke, c_off, Fm, k, Dn, nullptr);        // Y = E orth(E' Q)
+    if (rc != GMF_OK) return rc;
+  }
+  rc = run.orth(Dn, Dn2, P.n, k, Fn);                                 // Q
+  if (rc != GMF_OK) return rc;
+  rc = run.col_pass(emode, ke, c_off, Fn, k, Dm, nullptr);          // (Q'E)' = E'Q
+  if (rc != GMF_OK) return rc;
+  {
+    // left singular vectors of Q'E = eigenvectors of (Q'E)(Q'E)' = (E'Q)'(E'Q)
+    std::vector<double> G2, ev, Vk;
+    rc = run.gram(Dm, P.m, k, G2);
+    if (rc != GMF_OK) return rc;
+    sym_eigen(G2, k, ev, Vk);
+    std::vector<double> Ub((size_t)k * P.d);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < P.d; ++j) Ub[(size_t)i * P.d + j] = Vk[(size_t)i * k + j];
+    rc = run.upload_small(Ub, I.o_M);
+    if (rc != GMF_OK) return rc;
+    HIP_TRY(gmf::launch_apply(Dn, P.n, k, P.d, run.at<double>(I.o_M), nullptr, Dn2, Fn, nullptr, 0,
+                              0, st));                              // U = Q Ub
+  }
+  // 4. loadings: V = R' U (U'U)^-1 with R = L - X B' - Gamma Z'
+  rc = run.col_pass(1, ke, c_off, Fn, P.d, Dm, nullptr);
+  if (rc != GMF_OK) return rc;
+  std::vector<double> GU;
+  rc = run.gram(Dn2, P.n, P.d, GU);
+  if (rc != GMF_OK) return rc;
+  rc = run.normal_inverse(Dn2, P.n, P.d, Inv);
+  if (rc != GMF_OK) return rc;
+  rc = run.upload_small(Inv, I.o_M);
+  if (rc != GMF_OK) return rc;
+  HIP_TRY(gmf::launch_apply(Dm, P.m, P.d, P.d, run.at<double>(I.o_M), nullptr, Dm2, nullptr, nullptr,
+                            0, 0, st));
+  // equal norms within each pair: u_k * s_k, v_k / s_k, s_k = sqrt(|v_k| / |u_k|)
+  std::vector<double> GV;
+  rc = run.gram(Dm2, P.m, P.d, GV);
+  if (rc != GMF_OK) return rc;
+  std::vector<double> su(P.d), sv(P.d), eye((size_t)P.d * P.d, 0.0);
+  for (int j = 0; j < P.d; ++j) {
+    eye[(size_t)j * P.d + j] = 1.0;
+    const double nu = std::sqrt(GU[(size_t)j * P.d + j]), nv = std::sqrt(GV[(size_t)j * P.d + j]);
+    const double s = (nu > 0 && nv > 0) ? std::sqrt(nv / nu) : 1.0;
+    su[j] = s;
+    sv[j] = 1.0 / s;
+  }
+  rc = run.upload_small(eye, I.o_M);
+  if (rc != GMF_OK) return rc;
+  std::vector<double> scales(su);
+  scales.insert(scales.end(), sv.begin(), sv.end());
+  HIP_TRY(hipMemcpyAsync(run.at<double>(I.o_scale), scales.data(), sizeof(double) * scales.size(),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(gmf::launch_apply(Dn2, P.n, P.d, P.d, run.at<double>(I.o_M), run.at<double>(I.o_scale),
+                            nullptr, nullptr, Prow, P.KP, P.p + P.q, st));
+  HIP_TRY(gmf::launch_apply(Dm2, P.m, P.d, P.d, run.at<double>(I.o_M), run.at<double>(I.o_scale) + P.d,
+                            nullptr, nullptr, Pcol, P.KP, P.p + P.q, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return check_flag(c);
+}
+
 
 // ------------------------------------------------------------ batched fits --
 // Many independent fits advanced together.  One epoch of the batch is a fixed

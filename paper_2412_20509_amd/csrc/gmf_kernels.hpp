@@ -222,6 +222,44 @@ hipError_t launch_iota(int* p, int64_t count, hipStream_t s);
 hipError_t launch_sumsq(const float* P, int KP, int64_t rows, int col0, int ncols,
                         double* partial, int nblocks, hipStream_t s);
 
+// Parameter initialization (init.hip).  A pass computes each entry of one of
+// mode 0: L = g(y + c_off); 1: L - eta; 2: Pearson residual; 3: deviance
+// residual (eta over the first ke panel columns, mu clamped as in the fit)
+// and contracts it with the dense operand Q (kq <= 64 columns, permuted
+// order): the row pass writes part[s][i][:] = sum_{j in J_s} E_ij Q[j][:] for
+// every column block s (grid: row tiles x S); the column pass writes
+// part[c][j][:] = sum_{i in chunk c} E_ij Q[i][:] for every row chunk c
+// (grid: column tiles x chunks).  nout: rows of one partial set (n or m).
+struct InitPassArgs {
+  const float* Yb; const float* Wb;
+  int64_t LDtot;
+  const float* Prow; const float* Pcol;
+  int KP, ke;
+  const int* ro; const int* nrows; const int* co; const int* mcols; const int* ldy;
+  const int64_t* coP;
+  int mode, fam, log_link;
+  float c_off;
+  FamilyArgs f;
+  const float* colfill;   // mode 0: per permuted column, the value of missing entries (or null)
+  const float* Q;
+  int kq;
+  float* part;
+  int64_t nout;
+  const int* tiles;       // (block, first local row/column) per workgroup x
+  const int* chunks;      // column pass: (row block, first local row, rows) per workgroup y
+};
+hipError_t launch_init_pass(const InitPassArgs& a, bool row_pass, int grid_x, int grid_y,
+                            hipStream_t st);
+hipError_t launch_sum_parts(const float* part, int nparts, int64_t stride, int64_t count,
+                            double* out64, float* out32, hipStream_t st);
+hipError_t launch_gram(const double* A, int64_t rows, int k, double* part, int nparts, double* out,
+                       hipStream_t st);
+hipError_t launch_apply(const double* A, int64_t rows, int ka, int kb, const double* M,
+                        const double* scale, double* out64, float* out32, float* panel, int KP,
+                        int col0, hipStream_t st);
+hipError_t launch_panel_cols(float* P, int KP, int64_t rows, int col0, int ncols, double* out64,
+                             float* out32, int zero, hipStream_t st);
+
 // Identifiability post-processing (float64).
 struct PostArgs {
   const float* Prow; const float* Pcol;   // current iterate (permuted order)

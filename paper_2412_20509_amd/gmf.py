@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(i32)]),
         "gmf_schedule_host": (C.c_int, [C.c_uint64, i64, i64, i32, i64, i64, C.POINTER(i32),
                                         C.POINTER(i32), C.POINTER(i32)]),
+        "gmf_initialize_workspace_bytes": (C.c_size_t, [vp, i32]),
+        "gmf_initialize": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i32, i32, C.c_double]),
         "gmf_state_bytes": (C.c_size_t, [vp]),
         "gmf_save_state": (C.c_int, [vp, vp, C.c_size_t]),
         "gmf_load_state": (C.c_int, [vp, vp, C.c_size_t]),
@@ -450,6 +452,27 @@ class GMF:
                                             device=self.device) if c > 0 else None)
         gmf_set_params(self.ctx, conv(B, self.m, self.p), conv(A, self.n, self.q),
                        conv(U, self.n, self.d), conv(V, self.m, self.d))
+
+    def initialize(self, Omega, power_iters=2, residual="pearson", y_offset=-1.0):
+        """gmf_initialize: the least-squares initialization (Section 4.1) into the
+        context's iterate, from the m x k test matrix Omega (caller's column
+        order)."""
+        t = self.torch
+        lib = load_library()
+        if isinstance(Omega, t.Tensor):
+            Om = Omega.to(self.device).float().contiguous()
+        else:
+            Om = t.as_tensor(np.ascontiguousarray(Omega, np.float32), device=self.device)
+        k = Om.shape[1]
+        nbytes = lib.gmf_initialize_workspace_bytes(self.ctx, k)
+        if nbytes == 0:
+            raise GMFError(GMF_EINVAL, "k must be in [d, 64]")
+        ws = t.empty(nbytes + 256, dtype=t.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        _check(lib.gmf_initialize(self.ctx, _ptr(ws[off:off + nbytes]), nbytes, _ptr(Om), k,
+                                  int(power_iters), {"pearson": 0, "deviance": 1}[residual],
+                                  float(y_offset)))
+        self.stream.synchronize()
 
     def save_state(self) -> bytes:
         """gmf_save_state: the fit's state as bytes (host memory)."""
