@@ -45,7 +45,7 @@ import numpy as np
 # Families (Section 2, eq. 1-2; Supplementary Table 1; Appendix B for NB)
 # ---------------------------------------------------------------------------
 
-FAMILIES = ("poisson", "negbin", "gaussian")
+FAMILIES = ("poisson", "negbin", "gaussian", "gamma", "bernoulli", "invgauss")
 
 
 def _xlogy_ratio(y, a):
@@ -59,8 +59,9 @@ def _xlogy_ratio(y, a):
     return out
 
 
-def unit_deviance(family: str, y, mu, nb_alpha: float = 5.0):
-    """D(y, mu) = -2 log{f(y, mu)/f(y, y)} without the dispersion (Supp. Table 1 x 2)."""
+def unit_deviance(family: str, y, mu, nb_alpha=5.0):
+    """D(y, mu) = -2 log{f(y, mu)/f(y, y)} without the dispersion (Supp. Table 1 x 2).
+    nb_alpha may be a scalar or a per-column vector (broadcast over rows)."""
     y = np.asarray(y, dtype=np.float64)
     mu = np.asarray(mu, dtype=np.float64)
     if family == "gaussian":
@@ -68,37 +69,55 @@ def unit_deviance(family: str, y, mu, nb_alpha: float = 5.0):
     if family == "poisson":
         return 2.0 * (_xlogy_ratio(y, mu) - (y - mu))
     if family == "negbin":
-        a = nb_alpha
+        a = np.asarray(nb_alpha, dtype=np.float64)
         return 2.0 * (_xlogy_ratio(y, mu) - (y + a) * np.log((y + a) / (mu + a)))
+    if family == "gamma":
+        return 2.0 * ((y - mu) / mu - np.log(y / mu))
+    if family == "invgauss":
+        return (y - mu) ** 2 / (y * mu ** 2)
+    if family == "bernoulli":
+        return 2.0 * (_xlogy_ratio(y, mu) + _xlogy_ratio(1.0 - y, 1.0 - mu))
     raise ValueError(family)
 
 
-def variance_fn(family: str, mu, nb_alpha: float = 5.0):
+def variance_fn(family: str, mu, nb_alpha=5.0):
     """nu(mu) (Supp. Table 1)."""
+    mu = np.asarray(mu, dtype=np.float64)
     if family == "gaussian":
         return np.ones_like(mu)
     if family == "poisson":
         return mu
     if family == "negbin":
-        return mu * (1.0 + mu / nb_alpha)
+        return mu * (1.0 + mu / np.asarray(nb_alpha, dtype=np.float64))
+    if family == "gamma":
+        return mu ** 2
+    if family == "invgauss":
+        return mu ** 3
+    if family == "bernoulli":
+        return mu * (1.0 - mu)
     raise ValueError(family)
 
 
 def link_deriv(link: str, mu):
-    """g'(mu) for g = log or identity."""
+    """g'(mu) for g = log, identity or logit."""
     if link == "log":
         return 1.0 / mu
     if link == "identity":
         return np.ones_like(mu)
+    if link == "logit":
+        return 1.0 / (mu * (1.0 - mu))
     raise ValueError(link)
 
 
 def inverse_link(link: str, eta, eps: float = 1e-8, eta_max: float = 30.0):
-    """mu = g^{-1}(eta) with the clamp of the log link."""
+    """mu = g^{-1}(eta) with the clamps: log link eta in [log eps, eta_max],
+    logit link eta in [-eta_max, eta_max]."""
     if link == "log":
         return np.exp(np.clip(eta, np.log(eps), eta_max))
     if link == "identity":
         return np.asarray(eta, dtype=np.float64)
+    if link == "logit":
+        return 1.0 / (1.0 + np.exp(-np.clip(eta, -eta_max, eta_max)))
     raise ValueError(link)
 
 
@@ -106,13 +125,23 @@ def deviance_derivatives(family, link, y, mu, w, phi, nb_alpha=5.0):
     """First derivative and Fisher weight of the per-entry NLL in eta (Section 3).
 
     D1 = -w (y - mu) / (phi nu g'),  D2 = w / (phi nu g'^2).
+    A missing entry (NaN) is imputed by its mean, y <- mu (Section 3.2.2).
     """
+    y = np.where(np.isnan(y), mu, y)
     nu = variance_fn(family, mu, nb_alpha)
     gp = link_deriv(link, mu)
     wt = 1.0 if w is None else w
     D1 = -wt * (y - mu) / (phi * nu * gp)
     D2 = wt / (phi * nu * gp * gp) * np.ones_like(mu)
     return D1, D2
+
+
+def observed_deviance(family, y, mu, nb_alpha=5.0, w=None):
+    """Unit deviances with missing entries (NaN) contributing 0 (y <- mu)."""
+    miss = np.isnan(y)
+    dev = unit_deviance(family, np.where(miss, mu, y), mu, nb_alpha)
+    dev = np.where(miss, 0.0, dev)
+    return dev if w is None else w * dev
 
 
 # ---------------------------------------------------------------------------
@@ -198,6 +227,8 @@ class Config:
     R: int = 10
     S: int = 5
     seed: int = 0
+    estimate_phi: bool = False     # Appendix B, "Unknown dispersion parameter"
+    estimate_alpha: bool = False   # Appendix B, "Negative Binomial inflation parameter"
 
 
 def learning_rate(cfg: Config, t: int) -> float:
@@ -243,6 +274,40 @@ class OracleGMF:
         self.lam_row = np.array([lam[1]] * self.q + [lam[2]] * self.d)
         self.lam_col = np.array([lam[0]] * self.p + [lam[3]] * self.d)
         self.last_block_dev = None
+        # dispersion and NB shape in use: fixed, or the smoothed stochastic
+        # estimates of Appendix B started at the configured values
+        self.phi_bar = float(cfg.phi)
+        self.alpha_bar = cfg.nb_alpha if np.ndim(cfg.nb_alpha) == 0 else np.asarray(
+            cfg.nb_alpha, dtype=np.float64)
+
+    def alpha_of(self, J=None):
+        """NB shape of the columns J (scalar, or the per-column values)."""
+        a = self.alpha_bar
+        return a if np.ndim(a) == 0 or J is None else a[J]
+
+    def estimate_dispersion(self, t, yB, mu, wB, aJ, ns, ms):
+        """Stochastic dispersion and NB-shape updates of Appendix B from the
+        block's pre-step means, over the observed entries: Pearson estimate
+        phi^ = (1/N) (nm/(n* m*)) sum w (y - mu)^2 / nu(mu) with
+        N = nm - mp - nq - (n+m)d - 1, moment estimate alpha^ = sum w mu^2 /
+        sum w ((y - mu)^2 - mu); each smoothed with weight rho_t,
+        alpha_bar <- (1 - rho_t) alpha_bar + rho_t max(eps, alpha^)."""
+        cfg = self.cfg
+        obs = ~np.isnan(yB)
+        wt = np.ones_like(mu) if wB is None else wB
+        y0 = np.where(obs, yB, mu)
+        rho = learning_rate(cfg, t)
+        if cfg.estimate_phi:
+            N = (self.n * self.m - self.m * self.p - self.n * self.q
+                 - (self.n + self.m) * self.d - 1)
+            pear = np.where(obs, wt * (y0 - mu) ** 2 / variance_fn(cfg.family, mu, aJ), 0.0)
+            phi_hat = (self.n * self.m) / (ns * ms) * pear.sum() / N
+            self.phi_bar = (1.0 - rho) * self.phi_bar + rho * phi_hat
+        if cfg.estimate_alpha:
+            num = np.where(obs, wt * mu * mu, 0.0).sum()
+            den = np.where(obs, wt * ((y0 - mu) ** 2 - mu), 0.0).sum()
+            alpha_hat = num / den
+            self.alpha_bar = (1.0 - rho) * self.alpha_bar + rho * max(cfg.eps, alpha_hat)
 
     # -- one step ----------------------------------------------------------
     def block_of_step(self, t: int):
@@ -268,8 +333,8 @@ class OracleGMF:
         mu = inverse_link(cfg.link, eta, cfg.eps, cfg.eta_max)
         yB = self.Y[np.ix_(I, J)]
         wB = None if self.W is None else self.W[np.ix_(I, J)]
-        D1, D2 = deviance_derivatives(cfg.family, cfg.link, yB, mu, wB, cfg.phi,
-                                      cfg.nb_alpha)
+        aJ = self.alpha_of(J)
+        D1, D2 = deviance_derivatives(cfg.family, cfg.link, yB, mu, wB, self.phi_bar, aJ)
         # minibatch gradients from the pre-step parameters (eq. 15, Appendix B)
         Pc = np.hstack([self.Z[J], self.V[J]])            # [Z, V]_J
         Pr = np.hstack([self.X[I], self.U[I]])            # [X, U]_I
@@ -295,8 +360,9 @@ class OracleGMF:
         self.B[J] = col_new[:, :p]
         self.V[J] = col_new[:, p:]
         self.t = t
-        dev = unit_deviance(cfg.family, yB, mu, cfg.nb_alpha)
-        self.last_block_dev = float(np.sum(dev if wB is None else wB * dev))
+        self.last_block_dev = float(np.sum(observed_deviance(cfg.family, yB, mu, aJ, wB)))
+        if cfg.estimate_phi or cfg.estimate_alpha:
+            self.estimate_dispersion(t, yB, mu, wB, aJ, ns, ms)
         return self.last_block_dev
 
     def steps(self, k: int):
@@ -318,9 +384,8 @@ class OracleGMF:
         for r0 in range(0, self.n, chunk):
             rows = np.arange(r0, min(self.n, r0 + chunk))
             mu = inverse_link(cfg.link, self.eta_full(rows), cfg.eps, cfg.eta_max)
-            dev = unit_deviance(cfg.family, self.Y[rows], mu, cfg.nb_alpha)
-            if self.W is not None:
-                dev = self.W[rows] * dev
+            dev = observed_deviance(cfg.family, self.Y[rows], mu, self.alpha_of(None),
+                                    None if self.W is None else self.W[rows])
             tot += float(dev.sum())
         return tot
 
@@ -329,14 +394,14 @@ class OracleGMF:
         lam = self.cfg.lam
         pen = 0.5 * (lam[0] * np.sum(self.B ** 2) + lam[1] * np.sum(self.A ** 2)
                      + lam[2] * np.sum(self.U ** 2) + lam[3] * np.sum(self.V ** 2))
-        return self.full_deviance() / (2.0 * self.cfg.phi) + pen
+        return self.full_deviance() / (2.0 * self.phi_bar) + pen
 
     def full_gradient(self):
         """Exact gradient of the objective: D1 [Z,V] + lam[0,U], D1' [X,U] + lam[0,V]."""
         cfg = self.cfg
         mu = inverse_link(cfg.link, self.eta_full(), cfg.eps, cfg.eta_max)
         D1, _ = deviance_derivatives(cfg.family, cfg.link, self.Y, mu, self.W,
-                                     cfg.phi, cfg.nb_alpha)
+                                     self.phi_bar, self.alpha_of(None))
         g_row = D1 @ np.hstack([self.Z, self.V]) + self.lam_row * np.hstack([self.A, self.U])
         g_col = D1.T @ np.hstack([self.X, self.U]) + self.lam_col * np.hstack([self.B, self.V])
         return g_row, g_col
@@ -433,10 +498,32 @@ def row_deviance(cfg: Config, Y, X, Z, B, A, U, V, W=None):
     eta = (np.asarray(X) @ np.asarray(B).T + np.asarray(A) @ np.asarray(Z).T
            + np.asarray(U) @ np.asarray(V).T)
     mu = inverse_link(cfg.link, eta, cfg.eps, cfg.eta_max)
-    dev = unit_deviance(cfg.family, np.asarray(Y, np.float64), mu, cfg.nb_alpha)
-    if W is not None:
-        dev = W * dev
-    return dev.sum(axis=1)
+    return observed_deviance(cfg.family, np.asarray(Y, np.float64), mu, cfg.nb_alpha,
+                             W).sum(axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Out-of-sample reconstruction error (Section 5.2)
+# ---------------------------------------------------------------------------
+
+
+def heldout_metrics(family, y_val, mu_val, ybar_train, nb_alpha=5.0):
+    """The two relative out-of-sample errors of Section 5.2 over the held-out
+    entries: the relative squared logarithmic error
+    sum [log((1+y)/(1+mu))]^2 / sum [log((1+y)/(1+ybar_T))]^2, and the relative
+    deviance sum D(y, mu) / sum D(y, ybar_T), ybar_T the mean of the training
+    entries; the deviance is the Poisson one (the paper's) and, as a second
+    value, the model family's.  Returns (log_error, poisson_deviance,
+    family_deviance)."""
+    y = np.asarray(y_val, np.float64)
+    mu = np.asarray(mu_val, np.float64)
+    log_err = (np.sum(np.log((1.0 + y) / (1.0 + mu)) ** 2)
+               / np.sum(np.log((1.0 + y) / (1.0 + ybar_train)) ** 2))
+    pois = (np.sum(unit_deviance("poisson", y, mu))
+            / np.sum(unit_deviance("poisson", y, np.full_like(y, ybar_train))))
+    fam = (np.sum(unit_deviance(family, y, mu, nb_alpha))
+           / np.sum(unit_deviance(family, y, np.full_like(y, ybar_train), nb_alpha)))
+    return log_err, pois, fam
 
 
 # ---------------------------------------------------------------------------

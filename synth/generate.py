@@ -225,7 +225,10 @@ def gen_gaussian_lowrank(n=60, m=40, d=3, R=1, S=1, sing=(9.0, 6.0, 4.0),
 
 def gen_tiny(family="poisson", n=6, m=5, d=2, p=2, q=1, R=1, S=1, seed=1020,
              weights=False):
-    """Tiny problem with general covariates for finite-difference checks."""
+    """Tiny problem with general covariates for finite-difference checks.
+    Families: poisson, negbin (alpha 5), gaussian (identity link, noise sd
+    0.3, phi 0.7 in the fit), gamma (log link, shape 2: phi 0.5), invgauss
+    (log link, shape 1/0.3: phi 0.3), bernoulli (logit link)."""
     rng = _rng(seed)
     X = _f32(np.column_stack([np.ones(n)] + [rng.normal(size=n) for _ in range(p - 1)]))
     Z = _f32(np.column_stack([np.ones(m)] + [rng.normal(size=m) for _ in range(q - 1)]))
@@ -234,20 +237,45 @@ def gen_tiny(family="poisson", n=6, m=5, d=2, p=2, q=1, R=1, S=1, seed=1020,
     U = rng.normal(0.0, 0.4, size=(n, d))
     V = rng.normal(0.0, 0.4, size=(m, d))
     eta = X @ B.T + A @ Z.T + U @ V.T
+    phi = 1.0
     if family == "gaussian":
         Y = _f32(eta + 0.3 * rng.normal(size=(n, m)))
-        link = "identity"
+        link, phi = "identity", 0.7
     elif family == "negbin":
         mu = np.exp(eta + 1.0)
         Y = rng.negative_binomial(5.0, 5.0 / (5.0 + mu)).astype(np.int32)
         link = "log"
+    elif family == "gamma":
+        phi = 0.5
+        Y = _f32(rng.gamma(1.0 / phi, np.exp(eta) * phi))
+        link = "log"
+    elif family == "invgauss":
+        phi = 0.3
+        Y = _f32(rng.wald(np.exp(eta), 1.0 / phi))
+        link = "log"
+    elif family == "bernoulli":
+        Y = (rng.random(size=(n, m)) < 1.0 / (1.0 + np.exp(-eta))).astype(np.int32)
+        link = "logit"
     else:
         Y = rng.poisson(np.exp(eta + 1.0)).astype(np.int32)
         link = "log"
     W = _f32(rng.uniform(0.5, 2.0, size=(n, m))) if weights else None
+    shift = 1.0 if family in ("poisson", "negbin") else 0.0
+    true = dict(B=B, A=A, U=U, V=V, eta=eta + shift)
     return Problem(family, link, n, m, d, p, q, R, S, Y, X, Z, _f32(B), _f32(A),
-                   _f32(U), _f32(V), phi=1.0 if family != "gaussian" else 0.7,
-                   W=W, sched_seed=seed + 1000, name=f"tiny_{family}")
+                   _f32(U), _f32(V), phi=phi, W=W, sched_seed=seed + 1000,
+                   true=true, name=f"tiny_{family}")
+
+
+def holdout(Y, frac, seed):
+    """Hide a uniformly drawn fraction of the entries (Section 5.2's protocol):
+    returns (Y_train as float64 with NaN at the held-out entries, held-out
+    mask)."""
+    rng = _rng(seed)
+    mask = rng.random(size=np.shape(Y)) < frac
+    Yt = np.asarray(Y, np.float64).copy()
+    Yt[mask] = np.nan
+    return Yt, mask
 
 
 # The workloads: shapes, families and seeds.  "c1".."c5" follow the order of
