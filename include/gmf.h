@@ -47,9 +47,15 @@ enum {
   GMF_ENOTCONV = -5     /* gmf_fit stopped at max_epochs without meeting tol */
 };
 
-/* Families and links of Supplementary Table 1 supported on the device path. */
-enum { GMF_POISSON = 0, GMF_NEGBIN = 1, GMF_GAUSSIAN = 2 };
-enum { GMF_LINK_LOG = 0, GMF_LINK_IDENTITY = 1 };
+/* Families and links of Supplementary Table 1.  Pairs: Poisson, NB, Gamma and
+ * inverse Gaussian with the log link, Gaussian with the identity link,
+ * Bernoulli with the logit link.  Poisson, NB and Gaussian on complete data
+ * with a fixed dispersion run specialised epilogues in every precision; the
+ * other families, missing entries, per-column NB shapes and dispersion
+ * estimation run a generic epilogue (family switched at run time) in FP32. */
+enum { GMF_POISSON = 0, GMF_NEGBIN = 1, GMF_GAUSSIAN = 2, GMF_GAMMA = 3, GMF_BERNOULLI = 4,
+       GMF_INVGAUSS = 5 };
+enum { GMF_LINK_LOG = 0, GMF_LINK_IDENTITY = 1, GMF_LINK_LOGIT = 2 };
 /* Arithmetic of the block contractions (eta and the four gradient sums).
  * FP32: float32 matrix-core products with float32 accumulation.
  * BF16: bfloat16 operands (round to nearest even), float32 accumulation.
@@ -98,13 +104,31 @@ typedef struct gmf_config {
                            context's stream after the epoch's steps (full
                            grid); 1 = on a second stream from a copy of the
                            panels, overlapped with the following steps       */
+  int32_t allow_missing; /* 1: a negative int32 or a NaN float32 in Y is a
+                           missing entry, imputed by its current mean at every
+                           step (y <- mu, Section 3.2.2: no gradient, its
+                           Fisher weight kept, no deviance); the deviance
+                           and its per-row form cover the observed entries  */
+  int32_t estimate_phi;  /* 1: the dispersion phi (Gaussian, Gamma, inverse
+                           Gaussian) is estimated during the fit by the
+                           smoothed stochastic Pearson estimator of Appendix
+                           B ("Unknown dispersion parameter"), starting at
+                           cfg.phi                                           */
+  int32_t estimate_alpha; /* 1: the NB shape is estimated during the fit by the
+                           smoothed stochastic moment estimator of Appendix
+                           B ("Negative Binomial inflation parameter"),
+                           starting at cfg.nb_alpha, floored at cfg.eps.
+                           With either estimator every step waits for the
+                           previous one (its D1, D2 use the estimate it
+                           updated): two launches per step               */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
  * S=5, phi=1, nb_alpha=5, lambda=(0,0,1,1), rate0=0.05, decay=0.05,
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
  * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0,
- * tile_waves=0, eval_overlap=0. */
+ * tile_waves=0, eval_overlap=0, allow_missing=0, estimate_phi=0,
+ * estimate_alpha=0. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -116,7 +140,10 @@ size_t gmf_workspace_bytes(const gmf_config* cfg, int32_t with_weights);
  * Fisher-Yates shuffles, and copy Y, W, X, Z and the starting parameters into
  * the workspace, physically permuted so that every block I_r x J_s is a dense
  * rectangle.
- *   Y  n x m, GMF_Y_INT32 counts (0 <= y < 2^24) or GMF_Y_FLOAT32 reals.
+ *   Y  n x m, GMF_Y_INT32 counts (0 <= y < 2^24) or GMF_Y_FLOAT32 reals;
+ *      Poisson and NB need integer counts >= 0, Gamma and inverse Gaussian
+ *      y > 0, Bernoulli y in {0, 1}; with cfg.allow_missing a negative int32
+ *      or a NaN float32 marks a missing entry.
  *   X  n x p, Z m x q (may be NULL when p or q is 0).
  *   W  n x m positive weights w_ij of a_ij(phi) = phi/w_ij (eq. 2), or NULL
  *      for w = 1; non-NULL requires with_weights in gmf_workspace_bytes.
@@ -276,6 +303,56 @@ size_t gmf_initialize_workspace_bytes(void* ctx, int32_t k);
  * GMF_EDEVICE. */
 int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float* Omega, int32_t k,
                    int32_t power_iters, int32_t residual, double y_offset);
+
+/* gmf_set_column_alpha -- give the NB family one shape per column: alpha
+ * (device, m positive floats, the caller's column order) replaces the scalar
+ * cfg.nb_alpha in D1, D2 and the deviance of every following step and
+ * evaluation (Appendix B's NB law, with alpha_j per column).  The context then
+ * runs the generic FP32 epilogue.  Errors: GMF_EINVAL (not NB, NB shape being
+ * estimated, precision not FP32, a value not positive and finite). */
+int gmf_set_column_alpha(void* ctx, const float* alpha);
+
+/* gmf_get_dispersion -- the dispersion phi and NB shape in use: the
+ * configured values, or the current estimates when cfg.estimate_phi /
+ * cfg.estimate_alpha are set.  Either pointer may be NULL.  Synchronises. */
+int gmf_get_dispersion(void* ctx, double* phi_host, double* alpha_host);
+
+/* gmf_heldout_metrics -- the out-of-sample reconstruction errors of Section
+ * 5.2 for entries held out of the fit.  Ytest (device, n x m, the caller's
+ * order, y_dtype as in gmf_init) holds the held-out values; every other entry
+ * is marked by a negative int32 or a NaN float32.  With ybar_T the mean of
+ * the observed entries of the context's Y and mu the fitted means:
+ *   out_host[0] = sum [log((1+y)/(1+mu))]^2 / sum [log((1+y)/(1+ybar_T))]^2,
+ *   out_host[1] = sum D_Poisson(y, mu) / sum D_Poisson(y, ybar_T),
+ *   out_host[2] the same ratio with the context family's deviance,
+ *   out_host[3] the number of held-out entries, out_host[4] ybar_T,
+ *   out_host[5] the number of observed training entries.
+ * Sums over the held-out entries; per entry float32, float64 sums in a fixed
+ * order.  Synchronises.  Errors: GMF_EINVAL, GMF_EDEVICE. */
+int gmf_heldout_metrics(void* ctx, const void* Ytest, int32_t y_dtype, double* out_host);
+
+/* Rank selection (Section 4.2, "Model selection").
+ * gmf_init_spectrum -- the `count` largest singular values (descending) of
+ * the residual matrix that the last gmf_initialize on ctx factored (the
+ * Pearson or deviance residuals after the least-squares column and row
+ * effects; the paper's scree plot uses their squares), as estimated by its
+ * range finder; count <= that call's k.  GMF_EINVAL before any
+ * initialization. */
+int gmf_init_spectrum(void* ctx, double* sv_host, int32_t count);
+/* gmf_rank_eigengap -- the eigenvalue-gap ("edge distribution") estimator of
+ * Onatski (2010, Review of Economics and Statistics 92(4)) on host
+ * eigenvalues lambda_1 >= ... >= lambda_count (count >= rmax + 5): from
+ * j = rmax + 1, delta = 2 |slope| of the least-squares line of
+ * lambda_j..lambda_{j+4} on (j-1)^{2/3}..(j+3)^{2/3}; rank = the largest
+ * i <= rmax with lambda_i - lambda_{i+1} >= delta (0 if none); j = rank + 1;
+ * repeated until the rank no longer changes.  Pure host computation.
+ * Errors: GMF_EINVAL (NULL, count too small, not sorted or not finite). */
+int gmf_rank_eigengap(const double* eigenvalues, int32_t count, int32_t rmax, int32_t* rank_host);
+/* gmf_rank_select_cv -- the out-of-sample criterion: dev_host[r * nfolds + f]
+ * is the held-out deviance (gmf_heldout_metrics) of candidate r's fit on fold
+ * f; *best_host = the candidate with the smallest mean over the folds (the
+ * first on ties).  Pure host computation. */
+int gmf_rank_select_cv(const double* dev_host, int32_t nranks, int32_t nfolds, int32_t* best_host);
 
 /* gmf_get_schedule -- the drawn schedule, for checking: row_perm_host (n) and
  * col_perm_host (m) receive the permutations (block r holds

@@ -517,10 +517,11 @@ def heldout_metrics(family, y_val, mu_val, ybar_train, nb_alpha=5.0):
     family_deviance)."""
     y = np.asarray(y_val, np.float64)
     mu = np.asarray(mu_val, np.float64)
-    log_err = (np.sum(np.log((1.0 + y) / (1.0 + mu)) ** 2)
-               / np.sum(np.log((1.0 + y) / (1.0 + ybar_train)) ** 2))
-    pois = (np.sum(unit_deviance("poisson", y, mu))
-            / np.sum(unit_deviance("poisson", y, np.full_like(y, ybar_train))))
+    with np.errstate(invalid="ignore", divide="ignore"):   # count metrics of real data: NaN
+        log_err = (np.sum(np.log((1.0 + y) / (1.0 + mu)) ** 2)
+                   / np.sum(np.log((1.0 + y) / (1.0 + ybar_train)) ** 2))
+        pois = (np.sum(unit_deviance("poisson", y, mu))
+                / np.sum(unit_deviance("poisson", y, np.full_like(y, ybar_train))))
     fam = (np.sum(unit_deviance(family, y, mu, nb_alpha))
            / np.sum(unit_deviance(family, y, np.full_like(y, ybar_train), nb_alpha)))
     return log_err, pois, fam

@@ -25,7 +25,10 @@ Steps, in the paper's order:
      V' = argmin ||R - U V'||_F.
 
 Readings (the paper is silent on these points):
-  * c = 1/2 for the log link (g(0) is not finite), 0 for the identity link.
+  * c = 1/2 for the log link (g(0) is not finite), 0 for the identity link;
+    the logit link transforms (y + c)/(1 + 2c) with c = 1/2.
+  * Missing entries (NaN) take the current prediction: in step 1 the mean of
+    the column's observed L, afterwards a zero residual (y <- mu).
   * The scores are scaled so that each pair of columns (u_k, v_k) has equal
     Euclidean norms, which leaves U V' unchanged and minimises
     ||u_k||^2 + ||v_k||^2 over the rescalings of the pair (the ridge penalty
@@ -44,17 +47,21 @@ from oracle import gmf_oracle as G
 def link_offset(link: str, offset=None) -> float:
     if offset is not None and offset >= 0:
         return float(offset)
-    return 0.5 if link == "log" else 0.0
+    return 0.0 if link == "identity" else 0.5
 
 
 def link_transform(link: str, Y, offset=None):
-    """L = g(y + c)."""
+    """L = g(y + c); for the logit link g((y + c)/(1 + 2c)), which maps {0, 1}
+    into (0, 1)."""
     c = link_offset(link, offset)
     Y = np.asarray(Y, np.float64)
     if link == "log":
         return np.log(Y + c)
     if link == "identity":
         return Y + c
+    if link == "logit":
+        q = (Y + c) / (1.0 + 2.0 * c)
+        return np.log(q / (1.0 - q))
     raise ValueError(link)
 
 
@@ -95,12 +102,17 @@ def initialize(cfg: G.Config, Y, X, Z, d: int, Omega, power_iters: int = 2,
     Z = np.asarray(Z, np.float64).reshape(m, -1)
     p, q = X.shape[1], Z.shape[1]
     L = link_transform(cfg.link, Y, offset)
+    # a missing entry takes the current prediction: before any effect is
+    # fitted, the mean of its column's observed L; afterwards its residuals
+    # are 0 (y <- mu)
+    miss = np.isnan(Y)
+    L1 = np.where(miss, np.nanmean(L, axis=0), L) if miss.any() else L
     # 1. column effects
     if p > 0:
-        B = np.linalg.lstsq(X, L, rcond=None)[0].T
+        B = np.linalg.lstsq(X, L1, rcond=None)[0].T
     else:
         B = np.zeros((m, 0))
-    R1 = L - X @ B.T
+    R1 = np.where(miss, 0.0, L1 - X @ B.T)
     # 2. row effects given the column offsets
     if q > 0:
         A = np.linalg.lstsq(Z, R1.T, rcond=None)[0].T
@@ -109,10 +121,11 @@ def initialize(cfg: G.Config, Y, X, Z, d: int, Omega, power_iters: int = 2,
     eta0 = X @ B.T + A @ Z.T
     mu0 = G.inverse_link(cfg.link, eta0, cfg.eps, cfg.eta_max)
     # 3. scores: leading left singular vectors of the residual matrix
-    E = residuals(residual, cfg.family, Y, mu0, cfg.nb_alpha, W)
+    E = np.where(miss, 0.0, residuals(residual, cfg.family, np.where(miss, mu0, Y), mu0,
+                                      cfg.nb_alpha, W))
     U = randomized_left_vectors(E, np.asarray(Omega, np.float64), power_iters, d)
     # 4. loadings: least squares of the link-scale residual on the scores
-    R = L - eta0
+    R = np.where(miss, 0.0, L - eta0)
     V = np.linalg.lstsq(U, R, rcond=None)[0].T
     # equal norms within each pair (u_k, v_k)
     nu = np.linalg.norm(U, axis=0)

@@ -94,7 +94,9 @@ struct Plan {
       o_colloc, o_blkrowbase, o_blknrows, o_blkcoloff, o_blkld, o_tileblk, o_tilefirst,
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
       o_scal, o_sumsq, o_post, o_firstnz, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
-      o_ld, o_nct, o_coP, o_snap, o_devpart2, o_evring, total;
+      o_ld, o_nct, o_coP, o_snap, o_devpart2, o_evring, o_alphacol, o_est, o_stats, o_hopart,
+      total;
+  int stats_wg = 0, ho_wg = 0;
   int row_chunk = 1, col_chunk = 1, upd_sub = 1, upd_per_step = 1;
 };
 
@@ -109,6 +111,13 @@ constexpr int kSumsqBlocks = 256;
 
 int panel_stride_of(const gmf_config* c);
 
+// The generic epilogue (run-time family switch, missing entries, estimated
+// dispersion) serves everything but the three complete-data, fixed-dispersion
+// fast paths.
+bool needs_generic(const gmf_config* c) {
+  return c->family > GMF_GAUSSIAN || c->allow_missing || c->estimate_phi || c->estimate_alpha;
+}
+
 std::string check_config(const gmf_config* c) {
   if (!c) return "cfg is NULL";
   if (c->n < 1 || c->m < 1) return "n and m must be >= 1";
@@ -116,11 +125,23 @@ std::string check_config(const gmf_config* c) {
   if (c->d < 1 || c->p < 0 || c->q < 0) return "need d >= 1, p >= 0, q >= 0";
   if (c->p + c->q + c->d > 64) return "p + q + d must be <= 64";
   if (c->R < 1 || c->S < 1 || c->R > c->n || c->S > c->m) return "need 1 <= R <= n, 1 <= S <= m";
-  if (c->family < GMF_POISSON || c->family > GMF_GAUSSIAN) return "unknown family";
+  if (c->family < GMF_POISSON || c->family > GMF_INVGAUSS) return "unknown family";
   if (c->family == GMF_GAUSSIAN && c->link != GMF_LINK_IDENTITY)
     return "Gaussian family supports the identity link only";
-  if (c->family != GMF_GAUSSIAN && c->link != GMF_LINK_LOG)
-    return "Poisson and NB families support the log link only";
+  if (c->family == GMF_BERNOULLI && c->link != GMF_LINK_LOGIT)
+    return "Bernoulli family supports the logit link only";
+  if (c->family != GMF_GAUSSIAN && c->family != GMF_BERNOULLI && c->link != GMF_LINK_LOG)
+    return "Poisson, NB, Gamma and inverse Gaussian families support the log link only";
+  if (c->allow_missing != 0 && c->allow_missing != 1) return "allow_missing must be 0 or 1";
+  if (c->estimate_phi != 0 && c->estimate_phi != 1) return "estimate_phi must be 0 or 1";
+  if (c->estimate_alpha != 0 && c->estimate_alpha != 1) return "estimate_alpha must be 0 or 1";
+  if (c->estimate_alpha && c->family != GMF_NEGBIN) return "estimate_alpha needs the NB family";
+  if (c->estimate_phi && c->family != GMF_GAUSSIAN && c->family != GMF_GAMMA &&
+      c->family != GMF_INVGAUSS)
+    return "estimate_phi needs a family with a dispersion (Gaussian, Gamma, inverse Gaussian)";
+  if (needs_generic(c) && c->precision != GMF_PREC_FP32)
+    return "the Gamma, Bernoulli and inverse Gaussian families, missing entries and dispersion "
+           "estimation run in FP32 precision";
   if (c->precision != GMF_PREC_FP32 && c->precision != GMF_PREC_BF16 &&
       c->precision != GMF_PREC_BF16X3)
     return "unknown precision";
@@ -221,7 +242,8 @@ int upd_workgroups(int n_b, int m_b, int row_chunk, int col_chunk, int sub) {
 void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.n = c->n; P.m = c->m; P.R = c->R; P.S = c->S;
   P.p = c->p; P.q = c->q; P.d = c->d; P.k = c->p + c->q + c->d;
-  P.prec = c->precision; P.fam = c->family; P.with_w = with_w ? 1 : 0;
+  P.prec = c->precision; P.fam = needs_generic(c) ? gmf::kGeneric : c->family;
+  P.with_w = with_w ? 1 : 0;
   P.KP = panel_stride_of(c);
 
   const int tuned_rows = c->tile_rows > 0 ? 0 : tune_lookup(c);
@@ -325,6 +347,13 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   P.o_ld = take(sizeof(int) * P.S);
   P.o_nct = take(sizeof(int) * P.S);
   P.o_coP = take(sizeof(int64_t) * (P.S + 1));
+  P.o_alphacol = take(sizeof(float) * (size_t)P.m);
+  P.o_est = take(sizeof(double) * 4);
+  P.stats_wg = 0;
+  for (int r = 0; r < P.R; ++r) P.stats_wg = std::max(P.stats_wg, gmf::block_stats_workgroups(P.nrows[r]));
+  P.o_stats = take(sizeof(double) * 3 * (size_t)P.stats_wg);
+  P.ho_wg = gmf::heldout_workgroups(P.n);
+  P.o_hopart = take(sizeof(double) * std::max<size_t>(8 * (size_t)P.ho_wg, 2 * (size_t)P.dev_tiles));
   P.row_chunk = std::max(1, gmf::kTileThreads / (2 * P.KU));
   P.col_chunk = std::max(1, gmf::kTileThreads / (2 * P.KV));
   // chunks per update workgroup: at most about four update workgroups per
@@ -357,6 +386,9 @@ struct Ctx {
   int64_t t = 0;
   int64_t batched_upto = 0;   // last step run by gmf_batch_run (no block deviance)
   int device = 0;             // HIP device of the context
+  bool alpha_col = false;     // a per-column NB shape was set (generic path)
+  double est_init[4] = {1.0, 5.0, 0.0, 0.0};   // starting [phi, alpha] of the estimators
+  std::vector<double> init_sv;   // singular values of the residual matrix (last gmf_initialize)
   int want_block_dev = 1;
   unsigned long long launches = 0;
   // optional per-task trace (caller's device buffer)
@@ -400,6 +432,20 @@ gmf::FamilyArgs family_args(const gmf_config& c) {
   f.nb_alpha = (float)c.nb_alpha;
   f.eta_lo = (float)std::log(c.eps);
   f.eta_hi = (float)c.eta_max;
+  f.code = c.family;
+  f.link = c.link == GMF_LINK_IDENTITY ? gmf::kLinkIdentity
+                                       : (c.link == GMF_LINK_LOGIT ? gmf::kLinkLogit : gmf::kLinkLog);
+  f.alpha_col = nullptr;
+  f.est = nullptr;
+  return f;
+}
+
+// The family arguments of a context: with its per-column NB shape and its
+// estimated dispersion / NB shape on the device when those are in use.
+gmf::FamilyArgs family_args(const Ctx* c) {
+  gmf::FamilyArgs f = family_args(c->cfg);
+  if (c->alpha_col) f.alpha_col = c->at<float>(c->P.o_alphacol);
+  if (c->cfg.estimate_phi || c->cfg.estimate_alpha) f.est = c->at<double>(c->P.o_est);
   return f;
 }
 
@@ -454,7 +500,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   a.col_chunk = P.col_chunk;
   a.upd_sub = P.upd_sub;
   a.upd_per_step = P.upd_per_step;
-  a.f = family_args(cf);
+  a.f = family_args(c);
   a.fam = P.fam;
   a.p = P.p; a.q = P.q; a.d = P.d; a.KU = P.KU; a.KV = P.KV; a.KP = P.KP;
   a.lam_B = cf.lambda[0]; a.lam_A = cf.lambda[1]; a.lam_U = cf.lambda[2]; a.lam_V = cf.lambda[3];
@@ -497,10 +543,68 @@ gmf::LevelStep make_step(const Ctx* c, int64_t t) {
 // same column block, and on the same partial slot) of T + 2, or 0.  Launch k
 // runs the tiles of level k and the updates of level k-1; oversized levels are
 // split over several launches (tiles of level k never need updates of level k-1).
+// With dispersion or NB-shape estimation every step depends on the one before
+// it (its D1 and D2 use the estimates that step updated), so the steps run one
+// after another: per step the tile launch, the block statistics at the
+// pre-step parameters, the smoothed update of the estimates (weight rho_t;
+// Appendix B), then the update launch.
+int enqueue_steps_estimating(Ctx* c, int64_t nsteps) {
+  const Plan& P = c->P;
+  const bool want_dev = c->want_block_dev != 0;
+  gmf::LevelArgs a = level_args(c);
+  const int T = P.rr_max * P.ct_max;
+  const double N = (double)P.n * (double)P.m - (double)P.m * P.p - (double)P.n * P.q -
+                   (double)(P.n + P.m) * P.d - 1.0;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t t = c->t + 1 + k;
+    const gmf::LevelStep st = make_step(c, t);
+    for (int phase = 0; phase < 2; ++phase) {
+      a.n_tile_steps = phase == 0 ? 1 : 0;
+      a.n_upd_steps = phase == 0 ? 0 : 1;
+      a.steps[0] = st;
+      const int grid = phase == 0 ? T : P.upd_per_step;
+      a.launch_id = c->launches++;
+      a.trace_base = c->trace_used;
+      c->trace_used += grid;
+      hipEvent_t* ev = nullptr;
+      if (c->timing && c->timed_launches < kMaxTimedSteps) {
+        ev = &c->events[2 * c->timed_launches];
+        ++c->timed_launches;
+      }
+      HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, P.nw, a, grid, c->st,
+                                ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+      if (phase == 0) {
+        gmf::BlockStatsArgs b{};
+        b.Y = c->at<float>(P.o_Yb) + st.yoff;
+        b.W = P.with_w ? c->at<float>(P.o_Wb) + st.yoff : nullptr;
+        b.Prow = c->at<float>(P.o_Prow) + (int64_t)st.ro * P.KP;
+        b.Pcol = c->at<float>(P.o_Pcol) + (int64_t)st.co * P.KP;
+        b.ldy = st.ldy;
+        b.n_b = st.n_b;
+        b.m_b = st.m_b;
+        b.KP = P.KP;
+        b.col0 = st.co;
+        b.f = family_args(c);
+        b.partial = c->at<double>(P.o_stats);
+        HIP_TRY(gmf::launch_block_stats(b, c->st));
+        const double scale_phi = ((double)P.n * (double)P.m / ((double)st.n_b * st.m_b)) / N;
+        HIP_TRY(gmf::launch_est_update(b.partial, gmf::block_stats_workgroups(st.n_b),
+                                       c->at<double>(P.o_est), scale_phi,
+                                       learning_rate(c->cfg, t), c->cfg.eps,
+                                       c->cfg.estimate_phi, c->cfg.estimate_alpha, c->st));
+      }
+    }
+  }
+  if (c->timing) c->timed_steps += nsteps;
+  c->t += nsteps;
+  return GMF_OK;
+}
+
 int enqueue_steps(Ctx* c, int64_t nsteps) {
   const Plan& P = c->P;
   const bool want_dev = c->want_block_dev != 0;
   if (nsteps <= 0) return GMF_OK;
+  if (c->cfg.estimate_phi || c->cfg.estimate_alpha) return enqueue_steps_estimating(c, nsteps);
   std::vector<gmf::LevelStep> steps(nsteps);
   std::vector<int> level(nsteps);
   std::vector<int> lr(P.R, -1), ls(P.S, -1), lslot(P.nslot, -1);
@@ -570,7 +674,7 @@ gmf::DevArgs dev_args(Ctx* c) {
   a.blk_ldy = c->at<int>(P.o_bldy);
   a.blk_rpw = c->at<int>(P.o_brpw);
   a.blk_nct = c->at<int>(P.o_bnct);
-  a.f = family_args(c->cfg);
+  a.f = family_args(c);
   a.partial = c->at<double>(P.o_devpartial);
   a.n_tiles = P.dev_tiles;
   return a;
@@ -593,9 +697,44 @@ int count_constants(int fam, const gmf::DevArgs& da, const std::vector<int>& til
   return GMF_OK;
 }
 
+// Block of every full-deviance tile (the tiling of gmf_init).
+std::vector<int> dev_tile_blocks(const Plan& P) {
+  std::vector<int> tb;
+  tb.reserve(P.dev_tiles);
+  for (int r = 0; r < P.R; ++r)
+    for (int s = 0; s < P.S; ++s) {
+      const int nr = P.ro[r + 1] - P.ro[r];
+      const int drpw = dev_rows_per_wg(nr);
+      for (int k = 0; k < ((nr + drpw - 1) / drpw) * P.nct[s]; ++k) tb.push_back(r * P.S + s);
+    }
+  return tb;
+}
+
+// The dispersion and NB shape in use: [phi, alpha] from the device when they
+// are estimated, else the configured ones.
+int current_dispersion(Ctx* c, double out[2]) {
+  out[0] = c->cfg.phi;
+  out[1] = c->cfg.nb_alpha;
+  if (c->cfg.estimate_phi || c->cfg.estimate_alpha) {
+    HIP_TRY(hipMemcpyAsync(out, c->at<double>(c->P.o_est), 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+  }
+  return GMF_OK;
+}
+
+int count_constants(int fam, const gmf::DevArgs& da, const std::vector<int>& tileblk, int nblocks,
+                    hipStream_t st, std::vector<double>& kblock, double& ktotal);
+std::vector<int> dev_tile_blocks(const Plan& P);
+
 int compute_deviance(Ctx* c, double* total, double* pen) {
   const Plan& P = c->P;
   gmf::DevArgs a = dev_args(c);
+  if (c->cfg.estimate_alpha) {   // the count-only part depends on the current shape
+    const int rc = count_constants(P.fam, a, dev_tile_blocks(P), P.R * P.S, c->st, c->kblock,
+                                   c->ktotal);
+    if (rc != GMF_OK) return rc;
+  }
   // The deviance monitor uses float32 products regardless of the step
   // precision, so its panel stride must be a float32 case (16, 32, 48, 64).
   HIP_TRY(gmf::launch_deviance(P.fam, P.KP, a, c->st));
@@ -614,7 +753,10 @@ int compute_deviance(Ctx* c, double* total, double* pen) {
   if (total) *total = h[0];
   if (pen) {
     const double* lam = c->cfg.lambda;
-    *pen = h[0] / (2.0 * c->cfg.phi) +
+    double disp[2];
+    const int rc = current_dispersion(c, disp);
+    if (rc != GMF_OK) return rc;
+    *pen = h[0] / (2.0 * disp[0]) +
            0.5 * (lam[0] * h[1] + lam[1] * h[2] + lam[2] * h[3] + lam[3] * h[4]);
   }
   return h[5] != 0.0 ? check_flag(c) : GMF_OK;
@@ -788,7 +930,11 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
                               c->at<int>(P.o_colloc), c->at<int64_t>(P.o_blkrowbase),
                               c->at<int>(P.o_blknrows), c->at<int64_t>(P.o_blkcoloff),
                               c->at<int>(P.o_blkld), c->at<float>(P.o_Yb),
-                              P.with_w ? c->at<float>(P.o_Wb) : nullptr, c->at<int>(P.o_flag), st);
+                              P.with_w ? c->at<float>(P.o_Wb) : nullptr, c->at<int>(P.o_flag), st,
+                              cfg->allow_missing, cfg->family + 1);
+  c->est_init[0] = cfg->phi;
+  c->est_init[1] = cfg->nb_alpha;
+  if (e == hipSuccess) e = h2d(P.o_est, c->est_init, sizeof(c->est_init));
   if (e == hipSuccess)
     e = gmf::launch_pack_panel(X, P.p, A0, P.q, U0, P.d, c->at<int>(P.o_rowperm), P.n, P.KP,
                                c->at<float>(P.o_Prow), st);
@@ -831,6 +977,9 @@ int gmf_set_precision(void* ctx, int32_t precision) {
   Plan& P = c->P;
   if (precision != GMF_PREC_FP32 && precision != GMF_PREC_BF16 && precision != GMF_PREC_BF16X3)
     return fail(GMF_EINVAL, "unknown precision");
+  if (P.fam == gmf::kGeneric && precision != GMF_PREC_FP32)
+    return fail(GMF_EINVAL, "this context runs the generic FP32 epilogue (family, missing entries, "
+                            "per-column NB shape or dispersion estimation)");
   const bool ok = (precision != GMF_PREC_FP32) ? (P.KP == 16 || P.KP == 32 || P.KP == 64) : true;
   if (!ok) return fail(GMF_EINVAL, "BF16 needs panel stride 16, 32 or 64 (set panel_stride at init)");
   const int tw = c->cfg.tile_waves;
@@ -874,7 +1023,7 @@ int gmf_row_deviance(void* ctx, double* per_row) {
   a.ld = c->at<int>(P.o_ld);
   a.n = P.n;
   a.S = P.S;
-  a.f = family_args(c->cfg);
+  a.f = family_args(c);
   a.out = per_row;
   HIP_TRY(gmf::launch_row_deviance(P.fam, P.KP, a, c->st));
   return GMF_OK;
@@ -922,6 +1071,9 @@ int gmf_block_deviance(void* ctx, double* out_host, int64_t count) {
   Ctx* c = as_ctx(ctx);
   if (count < 0 || count > c->t || count > kDevRing) return fail(GMF_EINVAL, "bad count");
   if (!c->want_block_dev) return fail(GMF_EINVAL, "block deviance is off (skip_block_deviance)");
+  if (c->cfg.estimate_alpha)
+    return fail(GMF_EINVAL, "block deviances are not kept while the NB shape is estimated "
+                            "(their count-only part changes with it); use gmf_deviance");
   if (count > 0 && c->t - count + 1 <= c->batched_upto)
     return fail(GMF_EINVAL, "the requested steps include steps run by gmf_batch_run, which "
                             "form no block deviance");
@@ -1043,6 +1195,75 @@ int gmf_sync(void* ctx) {
 }
 
 
+
+// ------------------------------------------------------------ rank selection --
+// Section 4.2: spectral thresholding on the residual matrix of the
+// initialization, read by the eigenvalue-gap ("edge distribution") estimator
+// of Onatski (2010); and the out-of-sample criterion, the rank whose fits
+// have the smallest mean held-out deviance over the folds.
+extern "C" int gmf_init_spectrum(void* ctx, double* sv_host, int32_t count) {
+  if (!ctx || !sv_host) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  if (c->init_sv.empty()) return fail(GMF_EINVAL, "no initialization has run on this context");
+  if (count < 1 || count > (int32_t)c->init_sv.size())
+    return fail(GMF_EINVAL, "count must be in [1, k of the last initialization]");
+  for (int j = 0; j < count; ++j) sv_host[j] = c->init_sv[j];
+  return GMF_OK;
+}
+
+extern "C" int gmf_rank_eigengap(const double* eigenvalues, int32_t count, int32_t rmax,
+                                 int32_t* rank_host) {
+  if (!eigenvalues || !rank_host) return fail(GMF_EINVAL, "NULL argument");
+  if (rmax < 1 || count < rmax + 5) return fail(GMF_EINVAL, "need rmax >= 1 and count >= rmax + 5");
+  for (int i = 0; i + 1 < count; ++i)
+    if (!(eigenvalues[i] >= eigenvalues[i + 1]) || !std::isfinite(eigenvalues[i]))
+      return fail(GMF_EINVAL, "eigenvalues must be finite and sorted in descending order");
+  int j = rmax + 1, r = 0, r_prev = -1;
+  for (int it = 0; it < 100; ++it) {
+    // least-squares slope of lambda_j .. lambda_{j+4} on (j-1)^{2/3} .. (j+3)^{2/3}
+    double xs[5], ys[5], mx = 0.0, my = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      xs[q] = std::pow((double)(j + q - 1), 2.0 / 3.0);
+      ys[q] = eigenvalues[j + q - 1];
+      mx += xs[q] / 5.0;
+      my += ys[q] / 5.0;
+    }
+    double sxy = 0.0, sxx = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      sxy += (xs[q] - mx) * (ys[q] - my);
+      sxx += (xs[q] - mx) * (xs[q] - mx);
+    }
+    const double delta = 2.0 * std::fabs(sxy / sxx);
+    r = 0;
+    for (int i = 1; i <= rmax; ++i)
+      if (eigenvalues[i - 1] - eigenvalues[i] >= delta) r = i;
+    if (r == r_prev) break;
+    r_prev = r;
+    j = r + 1;
+  }
+  *rank_host = r;
+  return GMF_OK;
+}
+
+extern "C" int gmf_rank_select_cv(const double* dev_host, int32_t nranks, int32_t nfolds,
+                                  int32_t* best_host) {
+  if (!dev_host || !best_host || nranks < 1 || nfolds < 1) return fail(GMF_EINVAL, "bad arguments");
+  int best = -1;
+  double best_mean = 0.0;
+  for (int r = 0; r < nranks; ++r) {
+    double s = 0.0;
+    for (int f = 0; f < nfolds; ++f) s += dev_host[(size_t)r * nfolds + f];
+    const double mean = s / nfolds;
+    if (!std::isfinite(mean)) return fail(GMF_EINVAL, "non-finite held-out deviance");
+    if (best < 0 || mean < best_mean) {
+      best = r;
+      best_mean = mean;
+    }
+  }
+  *best_host = best;
+  return GMF_OK;
+}
+
 // ------------------------------------------------------------ projection --
 namespace {
 
@@ -1115,6 +1336,8 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
                  int64_t* fallback_host) {
   const auto t_start = std::chrono::steady_clock::now();
   const Plan& P = c->P;
+  if (P.fam == gmf::kGeneric)
+    return fail(GMF_EINVAL, "projection runs the Poisson, NB and Gaussian complete-data paths only");
   ProjPlan Q;
   if (!make_proj_plan(c, n_new, Q)) return fail(GMF_EINVAL, "bad n_new");
   if (!Ynew || !U_out || (P.p > 0 && !Xnew) || (P.q > 0 && !A_out))
@@ -1504,6 +1727,7 @@ int gmf_run(void* ctx, int32_t epochs, int32_t eval_every, double* dev_trace_hos
 // and checked on load, so the step counter t is the whole schedule cursor.
 namespace {
 constexpr char kStateMagic[8] = {'G', 'M', 'F', 'S', 'T', 'A', 'T', '1'};
+constexpr int kStateRegions = 9;
 struct StateHeader {
   char magic[8];
   uint32_t version, nregion;
@@ -1512,9 +1736,9 @@ struct StateHeader {
   uint64_t seed;
   int64_t t, batched_upto;
   double stepsize_params[6];   // rate0, decay, tau, alpha1, alpha2, damping (checked)
-  uint64_t region_bytes[8];
+  int32_t alpha_col, estimate;  // per-column NB shape set; estimation flags (checked)
+  uint64_t region_bytes[kStateRegions];
 };
-constexpr int kStateRegions = 7;
 
 void state_regions(const Ctx* c, size_t off[kStateRegions], size_t bytes[kStateRegions]) {
   const Plan& P = c->P;
@@ -1525,6 +1749,8 @@ void state_regions(const Ctx* c, size_t off[kStateRegions], size_t bytes[kStateR
   off[4] = P.o_Gcol; bytes[4] = sizeof(double) * (size_t)P.m * P.KV;
   off[5] = P.o_Hcol; bytes[5] = sizeof(double) * (size_t)P.m * P.KV;
   off[6] = P.o_devring; bytes[6] = sizeof(double) * kDevRing;
+  off[7] = P.o_est; bytes[7] = sizeof(double) * 4;   // dispersion / NB shape in use
+  off[8] = P.o_alphacol; bytes[8] = sizeof(float) * (size_t)P.m;
 }
 
 void fill_header(const Ctx* c, StateHeader& h) {
@@ -1538,6 +1764,8 @@ void fill_header(const Ctx* c, StateHeader& h) {
   h.t = c->t; h.batched_upto = c->batched_upto;
   const double sp[6] = {f.rate0, f.decay, f.tau, f.alpha1, f.alpha2, f.damping};
   std::memcpy(h.stepsize_params, sp, sizeof(sp));
+  h.alpha_col = c->alpha_col ? 1 : 0;
+  h.estimate = (f.estimate_phi ? 1 : 0) | (f.estimate_alpha ? 2 : 0) | (f.allow_missing ? 4 : 0);
   size_t off[kStateRegions], bytes[kStateRegions];
   state_regions(c, off, bytes);
   for (int i = 0; i < kStateRegions; ++i) h.region_bytes[i] = bytes[i];
@@ -1591,6 +1819,10 @@ extern "C" int gmf_load_state(void* ctx, const void* host_buf, size_t bytes) {
                             "stride or schedule seed");
   if (std::memcmp(h.stepsize_params, mine.stepsize_params, sizeof(h.stepsize_params)) != 0)
     return fail(GMF_EINVAL, "saved state was made with other step-size or EMA parameters");
+  if (h.estimate != mine.estimate)
+    return fail(GMF_EINVAL, "saved state was made with other estimation or missing-entry settings");
+  if (h.alpha_col && c->cfg.precision != GMF_PREC_FP32)
+    return fail(GMF_EINVAL, "a state with per-column NB shapes needs an FP32 context");
   for (int i = 0; i < kStateRegions; ++i)
     if (h.region_bytes[i] != mine.region_bytes[i]) return fail(GMF_EINVAL, "region size mismatch");
   if (bytes < state_total(c)) return fail(GMF_EINVAL, "buffer shorter than the saved state");
@@ -1607,6 +1839,94 @@ extern "C" int gmf_load_state(void* ctx, const void* host_buf, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(c->st));
   c->t = h.t;
   c->batched_upto = h.batched_upto;
+  if (h.alpha_col && !c->alpha_col) {
+    c->alpha_col = true;
+    c->P.fam = gmf::kGeneric;
+  }
+  if (h.alpha_col || c->cfg.estimate_alpha) {
+    const int rc = count_constants(c->P.fam, dev_args(c), dev_tile_blocks(c->P), c->P.R * c->P.S,
+                                   c->st, c->kblock, c->ktotal);
+    if (rc != GMF_OK) return rc;
+  }
+  return check_flag(c);
+}
+
+extern "C" int gmf_set_column_alpha(void* ctx, const float* alpha) {
+  if (!ctx || !alpha) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  Plan& P = c->P;
+  if (c->cfg.family != GMF_NEGBIN) return fail(GMF_EINVAL, "per-column shapes need the NB family");
+  if (c->cfg.estimate_alpha) return fail(GMF_EINVAL, "the NB shape is being estimated");
+  if (P.prec != GMF_PREC_FP32)
+    return fail(GMF_EINVAL, "per-column NB shapes run in FP32 precision (gmf_set_precision)");
+  // caller order -> permuted order, validated on the device
+  HIP_TRY(gmf::launch_pack_panel(alpha, 1, nullptr, 0, nullptr, 0, c->at<int>(P.o_colperm), P.m, 1,
+                                 c->at<float>(P.o_alphacol), c->st));
+  HIP_TRY(gmf::launch_check_positive(c->at<float>(P.o_alphacol), P.m, c->at<int>(P.o_flag), c->st));
+  const int rc0 = check_flag(c);
+  if (rc0 != GMF_OK) return rc0;
+  c->alpha_col = true;
+  P.fam = gmf::kGeneric;
+  return count_constants(P.fam, dev_args(c), dev_tile_blocks(P), P.R * P.S, c->st, c->kblock,
+                         c->ktotal);
+}
+
+extern "C" int gmf_get_dispersion(void* ctx, double* phi_host, double* alpha_host) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  double d[2];
+  const int rc = current_dispersion(as_ctx(ctx), d);
+  if (rc != GMF_OK) return rc;
+  if (phi_host) *phi_host = d[0];
+  if (alpha_host) *alpha_host = d[1];
+  return check_flag(as_ctx(ctx));
+}
+
+extern "C" int gmf_heldout_metrics(void* ctx, const void* Ytest, int32_t y_dtype,
+                                   double* out_host) {
+  if (!ctx || !Ytest || !out_host) return fail(GMF_EINVAL, "NULL argument");
+  if (y_dtype != GMF_Y_INT32 && y_dtype != GMF_Y_FLOAT32) return fail(GMF_EINVAL, "bad y_dtype");
+  Ctx* c = as_ctx(ctx);
+  const Plan& P = c->P;
+  double* part = c->at<double>(P.o_hopart);
+  // the mean of the observed training entries
+  gmf::DevArgs da = dev_args(c);
+  HIP_TRY(gmf::launch_observed_sum(da, part, c->st));
+  std::vector<double> h(2 * (size_t)P.dev_tiles);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  double sy = 0.0, cnt = 0.0;
+  for (int t = 0; t < P.dev_tiles; ++t) {
+    sy += h[2 * t];
+    cnt += h[2 * t + 1];
+  }
+  if (!(cnt > 0)) return fail(GMF_EINVAL, "no observed training entries");
+  const double ybar = sy / cnt;
+  gmf::HeldoutArgs a{};
+  a.Ytest = Ytest;
+  a.y_int = y_dtype == GMF_Y_INT32;
+  a.Prow = c->at<float>(P.o_Prow);
+  a.Pcol = c->at<float>(P.o_Pcol);
+  a.KP = P.KP;
+  a.row_perm = c->at<int>(P.o_rowperm);
+  a.col_perm = c->at<int>(P.o_colperm);
+  a.n = P.n;
+  a.m = P.m;
+  a.ybar = ybar;
+  a.f = family_args(c);
+  a.partial = part;
+  HIP_TRY(gmf::launch_heldout(a, c->st));
+  std::vector<double> g(8 * (size_t)P.ho_wg);
+  HIP_TRY(hipMemcpyAsync(g.data(), part, sizeof(double) * g.size(), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int w = 0; w < P.ho_wg; ++w)
+    for (int q = 0; q < 7; ++q) s[q] += g[8 * (size_t)w + q];
+  out_host[0] = s[1] > 0 ? s[0] / s[1] : 0.0;   // relative squared log error
+  out_host[1] = s[3] > 0 ? s[2] / s[3] : 0.0;   // relative Poisson deviance
+  out_host[2] = s[5] > 0 ? s[4] / s[5] : 0.0;   // relative deviance of the family
+  out_host[3] = s[6];                           // held-out entries
+  out_host[4] = ybar;                           // mean of the training entries
+  out_host[5] = cnt;                            // observed training entries
   return check_flag(c);
 }
 
@@ -1774,7 +2094,7 @@ struct InitRun {
     a.ldy = c->at<int>(P.o_ld); a.coP = c->at<int64_t>(P.o_coP);
     a.mode = mode; a.fam = P.fam; a.log_link = c->cfg.link == GMF_LINK_LOG;
     a.c_off = c_off;
-    a.f = family_args(c->cfg);
+    a.f = family_args(c);
     a.colfill = nullptr;
     a.Q = Q; a.kq = kq;
     a.part = at<float>(I.o_part);
@@ -1883,9 +2203,9 @@ extern "C" int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float*
     return fail(GMF_EWORKSPACE, "initialization workspace NULL, misaligned or smaller than " +
                                     std::to_string(I.total) + " bytes");
   run.W = static_cast<char*>(ws);
-  const float c_off = (float)(y_offset >= 0 ? y_offset : (c->cfg.link == GMF_LINK_LOG ? 0.5 : 0.0));
-  if (c->cfg.link == GMF_LINK_LOG && !(c_off > 0))
-    return fail(GMF_EINVAL, "the log link needs y_offset > 0");
+  const float c_off = (float)(y_offset >= 0 ? y_offset : (c->cfg.link == GMF_LINK_IDENTITY ? 0.0 : 0.5));
+  if (c->cfg.link != GMF_LINK_IDENTITY && !(c_off > 0))
+    return fail(GMF_EINVAL, "the log and logit links need y_offset > 0");
   hipStream_t st = c->st;
   float* Prow = c->at<float>(P.o_Prow);
   float* Pcol = c->at<float>(P.o_Pcol);
@@ -1905,10 +2225,22 @@ extern "C" int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float*
   float* Fm = run.at<float>(I.o_Fm);
   int rc = GMF_OK;
   std::vector<double> Inv;
+  // missing entries of L take their column's mean of the observed L (the
+  // prediction before any effect is fitted)
+  const float* colfill = nullptr;
+  if (c->cfg.allow_missing) {
+    HIP_TRY(gmf::launch_fill_i32(reinterpret_cast<int*>(Fn), P.n, 0x3f800000, st));   // ones
+    rc = run.col_pass(0, 0, c_off, Fn, 1, Dm, nullptr);       // sums of the observed L
+    if (rc != GMF_OK) return rc;
+    rc = run.col_pass(4, 0, c_off, Fn, 1, Dm2, nullptr);      // observed counts
+    if (rc != GMF_OK) return rc;
+    HIP_TRY(gmf::launch_ratio(Dm, Dm2, P.m, run.at<float>(I.o_colfill), st));
+    colfill = run.at<float>(I.o_colfill);
+  }
   // 1. column effects: B' = (X'X)^-1 X'L
   if (P.p > 0) {
     HIP_TRY(gmf::launch_panel_cols(Prow, P.KP, P.n, 0, P.p, Dn, Fn, 0, st));
-    rc = run.col_pass(0, 0, c_off, Fn, P.p, Dm, nullptr);
+    rc = run.col_pass(0, 0, c_off, Fn, P.p, Dm, nullptr, colfill);
     if (rc != GMF_OK) return rc;
     rc = run.normal_inverse(Dn, P.n, P.p, Inv);
     if (rc != GMF_OK) return rc;
@@ -1956,6 +2288,8 @@ extern "C" int gmf_initialize(void* ctx, void* ws, size_t ws_bytes, const float*
     rc = run.gram(Dm, P.m, k, G2);
     if (rc != GMF_OK) return rc;
     sym_eigen(G2, k, ev, Vk);
+    c->init_sv.resize(k);
+    for (int j = 0; j < k; ++j) c->init_sv[j] = std::sqrt(std::max(ev[j], 0.0));
     std::vector<double> Ub((size_t)k * P.d);
     for (int i = 0; i < k; ++i)
       for (int j = 0; j < P.d; ++j) Ub[(size_t)i * P.d + j] = Vk[(size_t)i * k + j];
@@ -2140,6 +2474,8 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
     if (P.prec != P0.prec || P.KP != P0.KP)
       return fail(GMF_EINVAL, "batched fits need one precision and one panel stride "
                               "(set gmf_config.panel_stride)");
+    if (as_ctx(ctxs[f])->cfg.estimate_phi || as_ctx(ctxs[f])->cfg.estimate_alpha)
+      return fail(GMF_EINVAL, "fits that estimate the dispersion or the NB shape run on their own");
     for (int g = 0; g < f; ++g)
       if (ctxs[g] == ctxs[f]) return fail(GMF_EINVAL, "a context appears twice in the batch");
   }

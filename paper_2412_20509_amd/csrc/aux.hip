@@ -37,9 +37,25 @@ struct PermuteTables {
   const int* blk_ld;           // s -> padded width of J_s
 };
 
+// Validation of y per family code (check = code + 1; 0 = none): counts (Poisson,
+// NB) integer-valued >= 0, Gamma and inverse Gaussian > 0, Bernoulli 0 or 1,
+// Gaussian finite.  With allow_missing a negative int32 or a NaN float32 is a
+// missing entry, stored as NaN.
+__device__ __forceinline__ bool valid_response(int check, float y) {
+  switch (check - 1) {
+    case kCodePoisson:
+    case kCodeNegBin: return y >= 0.f && y == floorf(y);
+    case kCodeGamma:
+    case kCodeInvGauss: return y > 0.f;
+    case kCodeBernoulli: return y == 0.f || y == 1.f;
+    default: return true;
+  }
+}
+
 __global__ void permute_y_kernel(const void* Y, int y_is_int, const float* W,
                                  int64_t n, int64_t m, PermuteTables t,
-                                 float* Yb, float* Wb, int* err_flag) {
+                                 float* Yb, float* Wb, int* err_flag, int allow_missing,
+                                 int check) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * m) return;
   const int64_t i = idx / m;
@@ -47,12 +63,21 @@ __global__ void permute_y_kernel(const void* Y, int y_is_int, const float* W,
   float y;
   if (y_is_int) {
     const int v = static_cast<const int*>(Y)[idx];
-    if (v < 0 || v >= (1 << 24)) atomicOr(err_flag, 2);
-    y = (float)v;
+    if (v < 0 && allow_missing) {
+      y = __builtin_nanf("");
+    } else {
+      if (v < 0 || v >= (1 << 24)) atomicOr(err_flag, 2);
+      y = (float)v;
+    }
   } else {
     y = static_cast<const float*>(Y)[idx];
-    if (!isfinite(y)) atomicOr(err_flag, 2);
+    if (!(y == y) && allow_missing) {
+      y = __builtin_nanf("");
+    } else if (!isfinite(y)) {
+      atomicOr(err_flag, 2);
+    }
   }
+  if (y == y && !valid_response(check, y)) atomicOr(err_flag, 2);
   const int r = t.row_block[i];
   const int s = t.col_block[j];
   const int64_t dst = t.blk_row_base[r] + (int64_t)t.blk_nrows[r] * t.blk_col_off[s] +
@@ -70,13 +95,14 @@ hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t
                             const int* col_block, const int* col_local,
                             const int64_t* blk_row_base, const int* blk_nrows,
                             const int64_t* blk_col_off, const int* blk_ld, float* Yb,
-                            float* Wb, int* err_flag, hipStream_t s) {
+                            float* Wb, int* err_flag, hipStream_t s, int allow_missing,
+                            int check) {
   PermuteTables t{row_block, row_local, col_block, col_local,
                   blk_row_base, blk_nrows, blk_col_off, blk_ld};
   const int64_t tot = n * m;
   const int64_t grid = (tot + 255) / 256;
   hipLaunchKernelGGL(permute_y_kernel, dim3((unsigned)grid), dim3(256), 0, s, Y,
-                     y_is_int, W, n, m, t, Yb, Wb, err_flag);
+                     y_is_int, W, n, m, t, Yb, Wb, err_flag, allow_missing, check);
   return hipGetLastError();
 }
 
@@ -376,7 +402,12 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
         for (int v = 0; v < 4; ++v) {
           float x1, x2, dv = 0.f;
-          family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+          if constexpr (FAM == kGeneric) {
+            const float av = column_alpha(fc, a.blk_col0[blk] + min(colb + v, m_b - 1));
+            family_entry_generic<true>(e[v], ys[v], ws[v], av, fc, x1, x2, dv);
+          } else {
+            family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+          }
           grp += (row < row_end && colb + v < m_b) ? dv : 0.f;
         }
       }
@@ -435,8 +466,8 @@ __global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
   const int ct = local % n_ct, rr = local / n_ct;
   const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
   const int col0 = ct * kTileCols, col_end = min(m_b, col0 + kTileCols);
-  const double alpha = (double)a.f.nb_alpha;
-  ctab[threadIdx.x] = count_part<FAM>((double)threadIdx.x, alpha);
+  const double alpha = a.f.est ? a.f.est[1] : (double)a.f.nb_alpha;
+  if constexpr (FAM != kGeneric) ctab[threadIdx.x] = count_part<FAM>((double)threadIdx.x, alpha);
   __syncthreads();
   double acc = 0.0;
   // thread t: column col0 + t % 128 of rows row0 + t / 128, row0 + t / 128 + 2, ...
@@ -446,9 +477,15 @@ __global__ __launch_bounds__(kTileThreads) void count_sum_kernel(DevArgs a) {
       const int64_t idx = (int64_t)r * ldy + c;
       const double w = W ? (double)W[idx] : 1.0;
       const float y = Y[idx];
-      const int yi = (int)y;
-      const double cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
-                                                                        : count_part<FAM>((double)y, alpha);
+      double cy;
+      if constexpr (FAM == kGeneric) {
+        const double ac = a.f.alpha_col ? (double)a.f.alpha_col[a.blk_col0[blk] + c] : alpha;
+        cy = count_part_generic(a.f.code, (double)y, ac);
+      } else {
+        const int yi = (int)y;
+        cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
+                                                              : count_part<FAM>((double)y, alpha);
+      }
       acc += w * cy;
     }
   red[threadIdx.x] = acc;
@@ -468,6 +505,9 @@ hipError_t launch_count_sum(int fam, const DevArgs& a, hipStream_t s) {
       break;
     case kNegBin:
       hipLaunchKernelGGL((count_sum_kernel<kNegBin>), dim3(a.n_tiles), dim3(kTileThreads), 0, s, a);
+      break;
+    case kGeneric:
+      hipLaunchKernelGGL((count_sum_kernel<kGeneric>), dim3(a.n_tiles), dim3(kTileThreads), 0, s, a);
       break;
     default:
       return hipSuccess;   // Gaussian: no count-only part
@@ -494,8 +534,8 @@ __global__ __launch_bounds__(kTileThreads) void row_deviance_kernel(RowDevArgs a
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * kRowDevRows;
   const int nr = (int)min<int64_t>(kRowDevRows, a.n - i0);
-  const double alpha = (double)a.f.nb_alpha;
-  ctab[tid] = count_part<FAM>((double)tid, alpha);
+  const double alpha = a.f.est ? a.f.est[1] : (double)a.f.nb_alpha;
+  if constexpr (FAM != kGeneric) ctab[tid] = count_part<FAM>((double)tid, alpha);
   if (tid < kRowDevRows) {
     int rb = 0, li = 0;
     if (tid < nr) { rb = a.rowblk[i0 + tid]; li = a.rowloc[i0 + tid]; }
@@ -534,10 +574,17 @@ __global__ __launch_bounds__(kTileThreads) void row_deviance_kernel(RowDevArgs a
         const float y = a.Yb[at];
         const float w = HAS_W ? a.Wb[at] : 1.f;
         float d1, d2, dv;
-        family_entry<FAM, true>(eta, y, w, fc, d1, d2, dv);
-        const int yi = (int)y;
-        const double cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
-                                                                          : count_part<FAM>((double)y, alpha);
+        double cy;
+        if constexpr (FAM == kGeneric) {
+          const float av = column_alpha(fc, c0 + j);
+          family_entry_generic<true>(eta, y, w, av, fc, d1, d2, dv);
+          cy = count_part_generic(fc.code, (double)y, (double)av);
+        } else {
+          family_entry<FAM, true>(eta, y, w, fc, d1, d2, dv);
+          const int yi = (int)y;
+          cy = (yi >= 0 && yi < kTileThreads && (float)yi == y) ? ctab[yi]
+                                                                : count_part<FAM>((double)y, alpha);
+        }
         acc[r] += (double)dv + 2.0 * (double)w * cy;
       }
     }
@@ -575,6 +622,7 @@ hipError_t launch_row_deviance(int fam, int KP, const RowDevArgs& a, hipStream_t
     case kPoisson: return launch_row_dev_w<kPoisson>(KP, a, s);
     case kNegBin: return launch_row_dev_w<kNegBin>(KP, a, s);
     case kGaussian: return launch_row_dev_w<kGaussian>(KP, a, s);
+    case kGeneric: return launch_row_dev_w<kGeneric>(KP, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -584,8 +632,204 @@ hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s) {
     case kPoisson: return launch_dev_kp<kPoisson>(KP, a, s);
     case kNegBin: return launch_dev_kp<kNegBin>(KP, a, s);
     case kGaussian: return launch_dev_kp<kGaussian>(KP, a, s);
+    case kGeneric: return launch_dev_kp<kGeneric>(KP, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------ dispersion estimation --
+constexpr int kStatRows = 16;
+
+int block_stats_workgroups(int n_b) { return (n_b + kStatRows - 1) / kStatRows; }
+
+__global__ __launch_bounds__(kTileThreads) void block_stats_kernel(BlockStatsArgs a) {
+  __shared__ float sP[kStatRows][65];
+  __shared__ double red[3][kTileThreads];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.x * kStatRows;
+  const int nr = min(kStatRows, a.n_b - r0);
+  for (int idx = tid; idx < kStatRows * a.KP; idx += kTileThreads) {
+    const int r = idx / a.KP, k = idx % a.KP;
+    sP[r][k] = r < nr ? a.Prow[(int64_t)(r0 + r) * a.KP + k] : 0.f;
+  }
+  __syncthreads();
+  const FamilyConst fc = family_const(a.f);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int j = tid; j < a.m_b; j += kTileThreads) {
+    const float* pc = a.Pcol + (int64_t)j * a.KP;
+    const float alpha = column_alpha(fc, a.col0 + j);
+    for (int r = 0; r < nr; ++r) {
+      const int64_t at = (int64_t)(r0 + r) * a.ldy + j;
+      const float y = a.Y[at];
+      if (!(y == y)) continue;   // missing
+      float eta = 0.f;
+      for (int k = 0; k < a.KP; ++k) eta = fmaf(sP[r][k], pc[k], eta);
+      const float mu = inverse_link_code(fc.link, eta, fc.lo, fc.hi);
+      const double w = a.W ? (double)a.W[at] : 1.0;
+      const double res = (double)y - (double)mu;
+      s0 += w * res * res / (double)variance_code(fc.code, mu, alpha);
+      s1 += w * (double)mu * (double)mu;
+      s2 += w * (res * res - (double)mu);
+    }
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  for (int off = kTileThreads / 2; off > 0; off >>= 1) {
+    if (tid < off)
+      for (int q = 0; q < 3; ++q) red[q][tid] += red[q][tid + off];
+    __syncthreads();
+  }
+  if (tid < 3) a.partial[3 * (int64_t)blockIdx.x + tid] = red[tid][0];
+}
+
+hipError_t launch_block_stats(const BlockStatsArgs& a, hipStream_t s) {
+  const int nwg = block_stats_workgroups(a.n_b);
+  if (nwg <= 0) return hipSuccess;
+  if (a.KP > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(block_stats_kernel, dim3(nwg), dim3(kTileThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void est_update_kernel(const double* partial, int nwg, double* est, double scale_phi,
+                                  double rho, double eps, int est_phi, int est_alpha) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int i = 0; i < nwg; ++i) {
+    s0 += partial[3 * i];
+    s1 += partial[3 * i + 1];
+    s2 += partial[3 * i + 2];
+  }
+  if (est_phi) est[0] = (1.0 - rho) * est[0] + rho * (scale_phi * s0);
+  if (est_alpha) est[1] = (1.0 - rho) * est[1] + rho * fmax(eps, s1 / s2);
+}
+
+hipError_t launch_est_update(const double* partial, int nwg, double* est, double scale_phi,
+                             double rho, double eps, int est_phi, int est_alpha, hipStream_t s) {
+  hipLaunchKernelGGL(est_update_kernel, dim3(1), dim3(64), 0, s, partial, nwg, est, scale_phi, rho,
+                     eps, est_phi, est_alpha);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- held-out metrics --
+__global__ __launch_bounds__(kTileThreads) void observed_sum_kernel(DevArgs a, double* partial) {
+  __shared__ double red[2][kTileThreads];
+  const int tile = blockIdx.x;
+  const int blk = a.tile_block[tile];
+  const int local = tile - a.tile_first[blk];
+  const int n_b = a.blk_nb[blk], m_b = a.blk_mb[blk];
+  const int ldy = a.blk_ldy[blk];
+  const int n_ct = a.blk_nct[blk];
+  const int rpw = a.blk_rpw[blk];
+  const float* Y = a.Y + a.blk_yoff[blk];
+  const int ct = local % n_ct, rr = local / n_ct;
+  const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
+  const int col0 = ct * kTileCols, col_end = min(m_b, col0 + kTileCols);
+  double sy = 0.0, cnt = 0.0;
+  const int c = col0 + (int)(threadIdx.x % kTileCols);
+  if (c < col_end)
+    for (int r = row0 + (int)(threadIdx.x / kTileCols); r < row_end; r += kTileThreads / kTileCols) {
+      const float y = Y[(int64_t)r * ldy + c];
+      if (y == y) {
+        sy += (double)y;
+        cnt += 1.0;
+      }
+    }
+  red[0][threadIdx.x] = sy;
+  red[1][threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = kTileThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) partial[2 * (int64_t)tile + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_observed_sum(const DevArgs& a, double* partial, hipStream_t s) {
+  if (a.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(observed_sum_kernel, dim3(a.n_tiles), dim3(kTileThreads), 0, s, a, partial);
+  return hipGetLastError();
+}
+
+int heldout_workgroups(int64_t n) { return (int)((n + kStatRows - 1) / kStatRows); }
+
+__global__ __launch_bounds__(kTileThreads) void heldout_kernel(HeldoutArgs a) {
+  __shared__ float sP[kStatRows][65];
+  __shared__ int64_t orow[kStatRows];
+  __shared__ double red[7][kTileThreads];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kStatRows;
+  const int nr = (int)min<int64_t>(kStatRows, a.n - r0);
+  for (int idx = tid; idx < kStatRows * a.KP; idx += kTileThreads) {
+    const int r = idx / a.KP, k = idx % a.KP;
+    sP[r][k] = r < nr ? a.Prow[(r0 + r) * a.KP + k] : 0.f;
+  }
+  if (tid < kStatRows) orow[tid] = tid < nr ? (int64_t)a.row_perm[r0 + tid] : 0;
+  __syncthreads();
+  const FamilyConst fc = family_const(a.f);
+  const float ybar = (float)a.ybar;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t jp = tid; jp < a.m; jp += kTileThreads) {
+    const float* pc = a.Pcol + jp * a.KP;
+    const int64_t jo = a.col_perm[jp];
+    const float alpha = column_alpha(fc, jp);
+    for (int r = 0; r < nr; ++r) {
+      const int64_t at = orow[r] * a.m + jo;
+      float y;
+      if (a.y_int) {
+        const int v = static_cast<const int*>(a.Ytest)[at];
+        if (v < 0) continue;
+        y = (float)v;
+      } else {
+        y = static_cast<const float*>(a.Ytest)[at];
+        if (!(y == y)) continue;
+      }
+      float eta = 0.f;
+      for (int k = 0; k < a.KP; ++k) eta = fmaf(sP[r][k], pc[k], eta);
+      const float mu = inverse_link_code(fc.link, eta, fc.lo, fc.hi);
+      const double l1 = (double)logf((1.f + y) / (1.f + mu));
+      const double l0 = (double)logf((1.f + y) / (1.f + ybar));
+      acc[0] += l1 * l1;
+      acc[1] += l0 * l0;
+      acc[2] += (double)unit_deviance_code(kCodePoisson, y, mu, alpha);
+      acc[3] += (double)unit_deviance_code(kCodePoisson, y, ybar, alpha);
+      acc[4] += (double)unit_deviance_code(fc.code, y, mu, alpha);
+      acc[5] += (double)unit_deviance_code(fc.code, y, ybar, alpha);
+      acc[6] += 1.0;
+    }
+  }
+  for (int q = 0; q < 7; ++q) red[q][tid] = acc[q];
+  __syncthreads();
+  for (int off = kTileThreads / 2; off > 0; off >>= 1) {
+    if (tid < off)
+      for (int q = 0; q < 7; ++q) red[q][tid] += red[q][tid + off];
+    __syncthreads();
+  }
+  if (tid < 7) a.partial[8 * (int64_t)blockIdx.x + tid] = red[tid][0];
+}
+
+hipError_t launch_heldout(const HeldoutArgs& a, hipStream_t s) {
+  const int nwg = heldout_workgroups(a.n);
+  if (nwg <= 0) return hipSuccess;
+  if (a.KP > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(heldout_kernel, dim3(nwg), dim3(kTileThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void check_positive_kernel(const float* x, int64_t count, int* err_flag) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count && !(x[idx] > 0.f && isfinite(x[idx]))) atomicOr(err_flag, 2);
+}
+
+hipError_t launch_check_positive(const float* x, int64_t count, int* err_flag, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_positive_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     x, count, err_flag);
+  return hipGetLastError();
 }
 
 }  // namespace gmf

@@ -55,17 +55,32 @@ __device__ __forceinline__ float log1p_pos(float z, float inv_q) {
 // Per-launch constants of the epilogue.
 struct FamilyConst {
   float phi_inv, a, a_phi, inv_a, lo, hi;
+  int code, link;
+  const float* alpha_col;
 };
 
 __device__ __forceinline__ FamilyConst family_const(const FamilyArgs& f) {
   FamilyConst c;
-  c.phi_inv = f.phi_inv;
-  c.a = f.nb_alpha;
-  c.a_phi = f.nb_alpha * f.phi_inv;
-  c.inv_a = 1.0f / f.nb_alpha;
+  float phi_inv = f.phi_inv, a = f.nb_alpha;
+  if (f.est) {   // dispersion and NB shape as currently estimated
+    phi_inv = (float)(1.0 / f.est[0]);
+    a = (float)f.est[1];
+  }
+  c.phi_inv = phi_inv;
+  c.a = a;
+  c.a_phi = a * phi_inv;
+  c.inv_a = 1.0f / a;
   c.lo = f.eta_lo;
   c.hi = f.eta_hi;
+  c.code = f.code;
+  c.link = f.link;
+  c.alpha_col = f.alpha_col;
   return c;
+}
+
+// NB shape of permuted column `col` on the generic path.
+__device__ __forceinline__ float column_alpha(const FamilyConst& c, int64_t col) {
+  return c.alpha_col ? c.alpha_col[col] : c.a;
 }
 
 // The count-only part c(y) of half the unit deviance (see above), float64.
@@ -74,6 +89,140 @@ __device__ __forceinline__ double count_part(double y, double a) {
   if (FAM == kGaussian || y <= 0.0) return 0.0;
   if constexpr (FAM == kPoisson) return y * log(y) - y;
   else return y * log(y) - (y + a) * log1p(y / a);
+}
+
+// The count-only part c(y) of half the unit deviance on the generic path
+// (float64): Poisson y log y - y, NB y log y - (y+a) log1p(y/a), Gamma
+// -1 - log y, inverse Gaussian 1/(2y), Gaussian and Bernoulli 0; 0 for a
+// missing entry.
+__device__ __forceinline__ double count_part_generic(int code, double y, double a) {
+  if (!(y == y)) return 0.0;
+  switch (code) {
+    case kCodePoisson: return y > 0.0 ? y * log(y) - y : 0.0;
+    case kCodeNegBin: return y > 0.0 ? y * log(y) - (y + a) * log1p(y / a) : 0.0;
+    case kCodeGamma: return -1.0 - log(y);
+    case kCodeInvGauss: return 0.5 / y;
+    default: return 0.0;
+  }
+}
+
+// log(1 + e^x) without overflow.
+__device__ __forceinline__ float softplus(float x) {
+  const float z = fast_exp(-fabsf(x));
+  return fmaxf(x, 0.f) + log1p_pos(z, __builtin_amdgcn_rcpf(1.0f + z));
+}
+
+// Generic epilogue: the six families with their links (Poisson, NB, Gamma and
+// inverse Gaussian with the log link, Gaussian with the identity link,
+// Bernoulli with the logit link), alpha the entry's NB shape.  A missing entry
+// (y NaN) is imputed by its mean, y <- mu (Section 3.2.2): D1 = 0, D2 the
+// Fisher weight at mu, no deviance.  dev: w times the mu part of half the
+// unit deviance (HALF), or of the unit deviance:
+//   Gamma     D/2 = c(y) + y/mu + log mu
+//   inv. Gau. D/2 = c(y) + y/(2 mu^2) - 1/mu
+//   Bernoulli D/2 = y softplus(-eta) + (1 - y) softplus(eta)   (c = 0)
+//   Gaussian  D/2 = (y - mu)^2 / 2                             (c = 0)
+// and D1, D2 = -w (y - mu)/(phi nu g'), w/(phi nu g'^2):
+//   Gamma-log D1 = w (1 - y/mu)/phi, D2 = w/phi; inv. Gaussian-log
+//   D1 = w (mu - y)/(phi mu^2), D2 = w/(phi mu); Bernoulli-logit
+//   D1 = w (mu - y)/phi, D2 = w mu (1 - mu)/phi.
+template <bool WANT_DEV, bool HALF = false>
+__device__ __forceinline__ void family_entry_generic(float eta, float y, float w, float alpha,
+                                                     const FamilyConst& c, float& d1, float& d2,
+                                                     float& dev) {
+  const bool miss = !(y == y);
+  float ec, mu;
+  if (c.link == kLinkIdentity) {
+    ec = eta;
+    mu = eta;
+  } else if (c.link == kLinkLogit) {
+    ec = __builtin_amdgcn_fmed3f(eta, -c.hi, c.hi);
+    mu = __builtin_amdgcn_rcpf(1.0f + fast_exp(-ec));
+  } else {
+    ec = __builtin_amdgcn_fmed3f(eta, c.lo, c.hi);
+    mu = fast_exp(ec);
+  }
+  const float yy = miss ? mu : y;
+  const float wp = w * c.phi_inv;
+  float dh = 0.f;
+  switch (c.code) {
+    case kCodePoisson:
+      d1 = wp * (mu - yy);
+      d2 = wp * mu;
+      dh = fmaf(-yy, ec, mu);
+      break;
+    case kCodeNegBin: {
+      const float inv = __builtin_amdgcn_rcpf(alpha + mu);
+      const float wa = wp * alpha * inv;
+      d1 = wa * (mu - yy);
+      d2 = wa * mu;
+      dh = fmaf(yy + alpha, log1p_pos(mu / alpha, alpha * inv), -yy * ec);
+      break;
+    }
+    case kCodeGamma: {
+      const float r = yy * __builtin_amdgcn_rcpf(mu);
+      d1 = wp * (1.0f - r);
+      d2 = wp;
+      dh = r + ec;
+      break;
+    }
+    case kCodeInvGauss: {
+      const float inv = __builtin_amdgcn_rcpf(mu);
+      d1 = wp * (mu - yy) * inv * inv;
+      d2 = wp * inv;
+      dh = fmaf(0.5f * yy * inv, inv, -inv);
+      break;
+    }
+    case kCodeBernoulli:
+      d1 = wp * (mu - yy);
+      d2 = wp * mu * (1.0f - mu);
+      dh = fmaf(yy, softplus(-ec), (1.0f - yy) * softplus(ec));
+      break;
+    default: {   // Gaussian
+      const float r = mu - yy;
+      d1 = wp * r;
+      d2 = wp;
+      dh = 0.5f * r * r;
+      break;
+    }
+  }
+  if constexpr (WANT_DEV) dev = miss ? 0.f : (HALF ? 1.f : 2.f) * w * dh;
+}
+
+// Mean of the linear predictor for a link code, with the fit's clamps.
+__device__ __forceinline__ float inverse_link_code(int link, float eta, float lo, float hi) {
+  if (link == kLinkIdentity) return eta;
+  if (link == kLinkLogit) return 1.0f / (1.0f + expf(-fminf(fmaxf(eta, -hi), hi)));
+  return expf(fminf(fmaxf(eta, lo), hi));
+}
+
+// Variance function nu(mu) of a family code (Supplementary Table 1).
+__device__ __forceinline__ float variance_code(int code, float mu, float alpha) {
+  switch (code) {
+    case kCodePoisson: return mu;
+    case kCodeNegBin: return mu * (1.0f + mu / alpha);
+    case kCodeGamma: return mu * mu;
+    case kCodeInvGauss: return mu * mu * mu;
+    case kCodeBernoulli: return mu * (1.0f - mu);
+    default: return 1.0f;
+  }
+}
+
+// The unit deviance D(y, mu) of a family code in its plain form (float32,
+// accurate libm functions; for monitoring outside the fit).
+__device__ __forceinline__ float unit_deviance_code(int code, float y, float mu, float alpha) {
+  const float ylog = y > 0.f ? y * logf(y / mu) : 0.f;
+  switch (code) {
+    case kCodePoisson: return 2.f * (ylog - (y - mu));
+    case kCodeNegBin: return 2.f * (ylog - (y + alpha) * logf((y + alpha) / (mu + alpha)));
+    case kCodeGamma: return 2.f * ((y - mu) / mu - logf(y / mu));
+    case kCodeInvGauss: return (y - mu) * (y - mu) / (y * mu * mu);
+    case kCodeBernoulli: {
+      const float ylog1 = y < 1.f ? (1.f - y) * logf((1.f - y) / (1.f - mu)) : 0.f;
+      return 2.f * (ylog + ylog1);
+    }
+    default: return (y - mu) * (y - mu);
+  }
 }
 
 // eta: linear predictor, y: response, w: weight (1 when there are none).

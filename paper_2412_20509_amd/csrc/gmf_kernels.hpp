@@ -19,7 +19,15 @@ constexpr int kWaveCols = 32;
 constexpr int kTileCols = kWaveCols * kTileWaves;
 constexpr int kRowGroup = 32;
 
-enum Family { kPoisson = 0, kNegBin = 1, kGaussian = 2 };
+// Kernel family selector: three fast paths (complete data, fixed dispersion)
+// and kGeneric, whose epilogue switches at run time on FamilyArgs::code over
+// the six families of Supplementary Table 1 (codes as GMF_POISSON ..
+// GMF_INVGAUSS), imputes missing entries (NaN) by their mean and reads the
+// NB shape per column and the estimated dispersion / NB shape when given.
+enum Family { kPoisson = 0, kNegBin = 1, kGaussian = 2, kGeneric = 7 };
+enum FamilyCode { kCodePoisson = 0, kCodeNegBin = 1, kCodeGaussian = 2, kCodeGamma = 3,
+                  kCodeBernoulli = 4, kCodeInvGauss = 5 };
+enum LinkCode { kLinkLog = 0, kLinkIdentity = 1, kLinkLogit = 2 };
 // kBF16X3: bfloat16 MFMA on operands split into a high and a low bfloat16
 // part (x = hi + lo), three products per contraction (hi*hi + hi*lo + lo*hi).
 enum Prec { kF32 = 0, kBF16 = 1, kBF16X3 = 2 };
@@ -28,7 +36,10 @@ struct FamilyArgs {
   float phi_inv;       // 1 / phi
   float nb_alpha;      // NB shape
   float eta_lo;        // log(eps)   (log link)
-  float eta_hi;        // eta_max    (log link)
+  float eta_hi;        // eta_max    (log link; the logit link clamps to +-eta_max)
+  int code, link;      // generic path: family and link codes
+  const float* alpha_col;   // generic path: NB shape per permuted column, or null
+  const double* est;        // generic path: [phi, alpha] in use (estimated), or null
 };
 
 // Starting values of projected rows (warm.hip).  Y: the caller's new rows in
@@ -208,7 +219,8 @@ hipError_t launch_permute_y(const void* Y, int y_is_int, const float* W, int64_t
                             const int* col_block, const int* col_local,
                             const int64_t* blk_row_base, const int* blk_nrows,
                             const int64_t* blk_col_off, const int* blk_ld, float* Yb,
-                            float* Wb, int* err_flag, hipStream_t s);
+                            float* Wb, int* err_flag, hipStream_t s, int allow_missing = 0,
+                            int check = 0);
 hipError_t launch_pack_panel(const float* M0, int c0, const float* M1, int c1,
                              const float* M2, int c2, const int* perm, int64_t rows,
                              int KP, float* P, hipStream_t s);
@@ -224,7 +236,8 @@ hipError_t launch_sumsq(const float* P, int KP, int64_t rows, int col0, int ncol
 
 // Parameter initialization (init.hip).  A pass computes each entry of one of
 // mode 0: L = g(y + c_off); 1: L - eta; 2: Pearson residual; 3: deviance
-// residual (eta over the first ke panel columns, mu clamped as in the fit)
+// residual; 4: 1 for an observed entry (eta over the first ke panel columns,
+// mu clamped as in the fit)
 // and contracts it with the dense operand Q (kq <= 64 columns, permuted
 // order): the row pass writes part[s][i][:] = sum_{j in J_s} E_ij Q[j][:] for
 // every column block s (grid: row tiles x S); the column pass writes
@@ -259,6 +272,51 @@ hipError_t launch_apply(const double* A, int64_t rows, int ka, int kb, const dou
                         int col0, hipStream_t st);
 hipError_t launch_panel_cols(float* P, int KP, int64_t rows, int col0, int ncols, double* out64,
                              float* out32, int zero, hipStream_t st);
+hipError_t launch_ratio(const double* num, const double* den, int64_t count, float* out,
+                        hipStream_t st);
+
+// Stochastic dispersion / NB-shape estimation (Appendix B, aux.hip).
+// block_stats: per workgroup of 16 block rows, float64 sums over the observed
+// entries of the block of w (y - mu)^2 / nu(mu), w mu^2 and
+// w ((y - mu)^2 - mu) at the current (pre-step) parameters -> partial[3 wg +
+// 0..2].  est_update: sums the partials in order, phi^ = scale_phi * S0,
+// alpha^ = S1 / S2, and smooths est[0] (phi) and est[1] (alpha) with weight
+// rho (alpha^ floored at eps).
+struct BlockStatsArgs {
+  const float* Y; const float* W;   // the block (row stride ldy)
+  const float* Prow; const float* Pcol;   // the block's panel rows (stride KP)
+  int ldy, n_b, m_b, KP;
+  int64_t col0;                     // first permuted column of the block
+  FamilyArgs f;
+  double* partial;
+};
+hipError_t launch_block_stats(const BlockStatsArgs& a, hipStream_t s);
+int block_stats_workgroups(int n_b);
+hipError_t launch_est_update(const double* partial, int nwg, double* est, double scale_phi,
+                             double rho, double eps, int est_phi, int est_alpha, hipStream_t s);
+
+// Held-out reconstruction error (Section 5.2).  observed_sum: per deviance
+// tile, the sum and the count of the observed (non-NaN) training entries ->
+// partial[2 tile + 0..1].  heldout: per workgroup of 16 permuted rows, over
+// the entries that Ytest (caller order, n x m) holds a value for (an int32
+// >= 0 or a finite float32; negative ints and NaN mark the other entries):
+// float64 sums of [log((1+y)/(1+mu))]^2, [log((1+y)/(1+ybar))]^2, the Poisson
+// deviances D(y, mu), D(y, ybar), the family's deviances D(y, mu), D(y, ybar)
+// and the count -> partial[8 wg + 0..6].
+hipError_t launch_observed_sum(const DevArgs& a, double* partial, hipStream_t s);
+struct HeldoutArgs {
+  const void* Ytest; int y_int;
+  const float* Prow; const float* Pcol; int KP;
+  const int* row_perm; const int* col_perm;   // permuted -> caller index
+  int64_t n, m;
+  double ybar;
+  FamilyArgs f;
+  double* partial;
+};
+hipError_t launch_heldout(const HeldoutArgs& a, hipStream_t s);
+// Sets bit 2 of *err_flag if an entry is not a positive finite number.
+hipError_t launch_check_positive(const float* x, int64_t count, int* err_flag, hipStream_t s);
+int heldout_workgroups(int64_t n);
 
 // Identifiability post-processing (float64).
 struct PostArgs {

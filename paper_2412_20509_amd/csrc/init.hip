@@ -8,6 +8,7 @@
 //   mode 1  L - eta,  eta = [X|Gamma] [B|Z]'      (link-scale residual)
 //   mode 2  (y - mu) sqrt(w / nu(mu))             (Pearson residual)
 //   mode 3  sign(y - mu) sqrt(w D(y, mu))         (deviance residual)
+//   mode 4  1 for an observed entry, 0 for a missing one
 // with mu = g^-1(eta) clamped like the fit's mean, and contracts it with a
 // dense operand in the same pass:
 //   row pass     out_s[i, :] = sum_{j in J_s} E_ij Om[j, :]   (E Om, per column block s)
@@ -34,33 +35,37 @@ constexpr int kT = 64;        // tile edge (rows and columns)
 constexpr int kThreads = 256;
 
 struct EntryConst {
-  int fam, log_link;
+  int fam, link;
   float c_off, alpha, lo, hi;
+  const float* alpha_col;   // NB shape per permuted column, or null
 };
 
+// L = g(y + c): log(y + c), y + c, or for the logit link logit((y + c)/(1 + 2c)).
+__device__ __forceinline__ float link_transform(float y, const EntryConst& c) {
+  if (c.link == kLinkLog) return logf(y + c.c_off);
+  if (c.link == kLinkLogit) {
+    const float q = (y + c.c_off) / (1.f + 2.f * c.c_off);
+    return logf(q / (1.f - q));
+  }
+  return y + c.c_off;
+}
+
 template <int MODE>
-__device__ __forceinline__ float init_entry(float y, float w, float eta, float fill,
+__device__ __forceinline__ float init_entry(float y, float w, float eta, float fill, float alpha,
                                             const EntryConst& c) {
   if (y != y) return MODE == 0 ? fill : 0.f;          // missing: imputed value
-  if constexpr (MODE == 0) {
-    return c.log_link ? logf(y + c.c_off) : y + c.c_off;
+  if constexpr (MODE == 4) {
+    return 1.f;                                       // observed indicator
+  } else if constexpr (MODE == 0) {
+    return link_transform(y, c);
   } else if constexpr (MODE == 1) {
-    const float L = c.log_link ? logf(y + c.c_off) : y + c.c_off;
-    return L - eta;
+    return link_transform(y, c) - eta;
   } else {
-    const float mu = c.log_link ? expf(fminf(fmaxf(eta, c.lo), c.hi)) : eta;
+    const float mu = inverse_link_code(c.link, eta, c.lo, c.hi);
     if constexpr (MODE == 2) {
-      float var = 1.f;
-      if (c.fam == kPoisson) var = mu;
-      else if (c.fam == kNegBin) var = mu * (1.f + mu / c.alpha);
-      return (y - mu) * sqrtf(w / var);
+      return (y - mu) * sqrtf(w / variance_code(c.fam, mu, alpha));
     } else {
-      float D;
-      const float ylog = y > 0.f ? y * logf(y / mu) : 0.f;
-      if (c.fam == kGaussian) D = (y - mu) * (y - mu);
-      else if (c.fam == kPoisson) D = 2.f * (ylog - (y - mu));
-      else D = 2.f * (ylog - (y + c.alpha) * logf((y + c.alpha) / (mu + c.alpha)));
-      const float r = sqrtf(w * fmaxf(D, 0.f));
+      const float r = sqrtf(w * fmaxf(unit_deviance_code(c.fam, y, mu, alpha), 0.f));
       return y > mu ? r : (y < mu ? -r : 0.f);
     }
   }
@@ -104,9 +109,10 @@ __device__ __forceinline__ void entry_tile(const InitPassArgs& a, int r, int s, 
       const float y = a.Yb[off];
       const float w = a.Wb ? a.Wb[off] : 1.f;
       float eta = 0.f;
-      if constexpr (MODE != 0)
+      if constexpr (MODE == 1 || MODE == 2 || MODE == 3)
         for (int k = 0; k < a.ke; ++k) eta = fmaf(sA[row][k], sBt[k][col], eta);
-      e = init_entry<MODE>(y, w, eta, fill, c);
+      const float alpha = c.alpha_col ? c.alpha_col[a.co[s] + lj0 + col] : c.alpha;
+      e = init_entry<MODE>(y, w, eta, fill, alpha, c);
     }
     sE[row][col] = e;
   }
@@ -114,12 +120,13 @@ __device__ __forceinline__ void entry_tile(const InitPassArgs& a, int r, int s, 
 
 EntryConst entry_const(const InitPassArgs& a) {
   EntryConst c;
-  c.fam = a.fam;
-  c.log_link = a.log_link;
+  c.fam = a.f.code;
+  c.link = a.f.link;
   c.c_off = a.c_off;
   c.alpha = a.f.nb_alpha;
   c.lo = a.f.eta_lo;
   c.hi = a.f.eta_hi;
+  c.alpha_col = a.f.alpha_col;
   return c;
 }
 
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void init_row_pass_kernel(InitPassArgs a,
   const int nr = min(kT, a.nrows[r] - li0);
   const int ms = a.mcols[s];
   const int64_t prow0 = (int64_t)a.ro[r] + li0;
-  if (MODE != 0) load_panel_rows(a.Prow, a.KP, prow0, nr, a.ke, sA);
+  if (MODE >= 1 && MODE <= 3) load_panel_rows(a.Prow, a.KP, prow0, nr, a.ke, sA);
   const int row = threadIdx.x >> 2, g = threadIdx.x & 3;
   const int per = (a.kq + 3) / 4;   // outputs per thread, contiguous
   float acc[16];
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void init_row_pass_kernel(InitPassArgs a,
     const int nc = min(kT, ms - lj0);
     const int64_t pcol0 = (int64_t)a.co[s] + lj0;
     __syncthreads();
-    if (MODE != 0)
+    if (MODE >= 1 && MODE <= 3)
       for (int idx = threadIdx.x; idx < kT * a.ke; idx += kThreads) {
         const int cc = idx / a.ke, k = idx % a.ke;
         sBt[k][cc] = cc < nc ? a.Pcol[(pcol0 + cc) * a.KP + k] : 0.f;
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void init_col_pass_kernel(InitPassArgs a,
   const int crows = a.chunks[3 * blockIdx.y + 2];
   const int nc = min(kT, a.mcols[s] - lj0);
   const int64_t pcol0 = (int64_t)a.co[s] + lj0;
-  if (MODE != 0)
+  if (MODE >= 1 && MODE <= 3)
     for (int idx = threadIdx.x; idx < kT * a.ke; idx += kThreads) {
       const int cc = idx / a.ke, k = idx % a.ke;
       sBt[k][cc] = cc < nc ? a.Pcol[(pcol0 + cc) * a.KP + k] : 0.f;
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void init_col_pass_kernel(InitPassArgs a,
     const int nr = min(kT, ci0 + crows - li0);
     const int64_t prow0 = (int64_t)a.ro[r] + li0;
     __syncthreads();
-    if (MODE != 0) load_panel_rows(a.Prow, a.KP, prow0, nr, a.ke, sA);
+    if (MODE >= 1 && MODE <= 3) load_panel_rows(a.Prow, a.KP, prow0, nr, a.ke, sA);
     load_dense_rows(a.Q, a.kq, prow0, nr, sQ);
     __syncthreads();
     entry_tile<MODE>(a, r, s, li0, nr, lj0, nc, sA, sBt, sE, c);
@@ -234,6 +241,7 @@ hipError_t launch_init_pass(const InitPassArgs& a, bool row_pass, int grid_x, in
     GMF_INIT_CASE(1)
     GMF_INIT_CASE(2)
     GMF_INIT_CASE(3)
+    GMF_INIT_CASE(4)
     default: return hipErrorInvalidValue;
   }
 #undef GMF_INIT_CASE
@@ -370,6 +378,20 @@ hipError_t launch_panel_cols(float* P, int KP, int64_t rows, int col0, int ncols
   if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(panel_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P,
                      KP, rows, col0, ncols, out64, out32, zero);
+  return hipGetLastError();
+}
+
+// out[x] = num[x] / den[x] (0 where den is 0), float32.
+__global__ void ratio_kernel(const double* num, const double* den, int64_t count, float* out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < count) out[x] = den[x] > 0.0 ? (float)(num[x] / den[x]) : 0.f;
+}
+
+hipError_t launch_ratio(const double* num, const double* den, int64_t count, float* out,
+                        hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ratio_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, num,
+                     den, count, out);
   return hipGetLastError();
 }
 

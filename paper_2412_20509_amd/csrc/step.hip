@@ -97,6 +97,7 @@ struct TileView {
   float* Upart;                    // this strip's partial rows: [n_b][2KU]
   float* Vpart;                    // this range's partial cols: [m_b][2KV]
   unsigned long long* stamps;      // optional: 3 timestamps (profiling), or null
+  const float* alpha;              // generic path: NB shape of the block's columns, or null
 };
 
 template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool HAS_W>
@@ -331,7 +332,12 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         // eta, mu, D1, D2 are finite.  Only the deviance sum is masked.
         for (int v = 0; v < 4; ++v) {
           float dv = 0.f;
-          family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+          if constexpr (FAM == kGeneric) {
+            const float av = tv.alpha ? tv.alpha[min(colb + v, tv.m_b - 1)] : fc.a;
+            family_entry_generic<WANT_DEV, true>(e[v], ys[v], ws[v], av, fc, d1[C][v], d2[C][v], dv);
+          } else {
+            family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+          }
           if constexpr (WANT_DEV) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
         }
       }
@@ -663,6 +669,7 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     tv.Upart = a.Upart + (int64_t)st.slot * a.slot_u_elems + (int64_t)ct * n_b * (2 * a.KU);
     tv.Vpart = a.Vpart + (int64_t)st.slot * a.slot_v_elems + (int64_t)rr * m_b * (2 * a.KV);
     tv.stamps = stamps;
+    tv.alpha = a.f.alpha_col ? a.f.alpha_col + st.co : nullptr;
     const FamilyConst fc = family_const(a.f);
     const double dev =
         tv.W ? compute_tile<PREC, FAM, KP, WANT_DEV, NW, true>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile)
@@ -761,6 +768,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
   switch (a.fam) {
     case kPoisson: run_task<PREC, kPoisson, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
     case kNegBin: run_task<PREC, kNegBin, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
+    case kGeneric:   // FP32 only (the host refuses other precisions for these fits)
+      if constexpr (PREC == kF32) run_task<PREC, kGeneric, KP, false, 4>(a, st, tile_task, local, L, nullptr);
+      break;
     default: run_task<PREC, kGaussian, KP, false, 4>(a, st, tile_task, local, L, nullptr); break;
   }
 }
@@ -805,6 +815,7 @@ static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev, in
       case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev, nw);
       case kNegBin: return kernel_ptr_kp<kF32, kNegBin>(KP, want_dev, nw);
       case kGaussian: return kernel_ptr_kp<kF32, kGaussian>(KP, want_dev, nw);
+      case kGeneric: return kernel_ptr_kp<kF32, kGeneric>(KP, want_dev, nw);
     }
   } else if (prec == kBF16) {
     switch (fam) {

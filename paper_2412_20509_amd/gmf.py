@@ -18,13 +18,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgmf.so")
 
 GMF_OK, GMF_EINVAL, GMF_EWORKSPACE, GMF_EDEVICE, GMF_ENUMERIC, GMF_ENOTCONV = 0, -1, -2, -3, -4, -5
-GMF_POISSON, GMF_NEGBIN, GMF_GAUSSIAN = 0, 1, 2
-GMF_LINK_LOG, GMF_LINK_IDENTITY = 0, 1
+GMF_POISSON, GMF_NEGBIN, GMF_GAUSSIAN, GMF_GAMMA, GMF_BERNOULLI, GMF_INVGAUSS = 0, 1, 2, 3, 4, 5
+GMF_LINK_LOG, GMF_LINK_IDENTITY, GMF_LINK_LOGIT = 0, 1, 2
 GMF_PREC_FP32, GMF_PREC_BF16, GMF_PREC_BF16X3 = 0, 1, 2
 GMF_Y_INT32, GMF_Y_FLOAT32 = 0, 1
 
-FAMILY_CODES = {"poisson": GMF_POISSON, "negbin": GMF_NEGBIN, "gaussian": GMF_GAUSSIAN}
-LINK_CODES = {"log": GMF_LINK_LOG, "identity": GMF_LINK_IDENTITY}
+FAMILY_CODES = {"poisson": GMF_POISSON, "negbin": GMF_NEGBIN, "gaussian": GMF_GAUSSIAN,
+                "gamma": GMF_GAMMA, "bernoulli": GMF_BERNOULLI, "invgauss": GMF_INVGAUSS}
+LINK_CODES = {"log": GMF_LINK_LOG, "identity": GMF_LINK_IDENTITY, "logit": GMF_LINK_LOGIT}
 PREC_CODES = {"fp32": GMF_PREC_FP32, "bf16": GMF_PREC_BF16, "bf16x3": GMF_PREC_BF16X3}
 
 
@@ -43,6 +44,7 @@ class gmf_config(C.Structure):
         ("seed", C.c_uint64),
         ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
         ("panel_stride", C.c_int32), ("tile_waves", C.c_int32), ("eval_overlap", C.c_int32),
+        ("allow_missing", C.c_int32), ("estimate_phi", C.c_int32), ("estimate_alpha", C.c_int32),
     ]
 
 
@@ -93,6 +95,12 @@ def load_library(path: str = LIB_PATH):
                                         C.POINTER(i32), C.POINTER(i32)]),
         "gmf_initialize_workspace_bytes": (C.c_size_t, [vp, i32]),
         "gmf_initialize": (C.c_int, [vp, vp, C.c_size_t, vp, i32, i32, i32, C.c_double]),
+        "gmf_set_column_alpha": (C.c_int, [vp, vp]),
+        "gmf_init_spectrum": (C.c_int, [vp, f64p, i32]),
+        "gmf_rank_eigengap": (C.c_int, [f64p, i32, i32, C.POINTER(i32)]),
+        "gmf_rank_select_cv": (C.c_int, [f64p, i32, i32, C.POINTER(i32)]),
+        "gmf_get_dispersion": (C.c_int, [vp, f64p, f64p]),
+        "gmf_heldout_metrics": (C.c_int, [vp, vp, i32, f64p]),
         "gmf_state_bytes": (C.c_size_t, [vp]),
         "gmf_save_state": (C.c_int, [vp, vp, C.c_size_t]),
         "gmf_load_state": (C.c_int, [vp, vp, C.c_size_t]),
@@ -331,6 +339,9 @@ class FitConfig:
     panel_stride: int = 0
     tile_waves: int = 0
     eval_overlap: int = 0
+    allow_missing: int = 0
+    estimate_phi: int = 0
+    estimate_alpha: int = 0
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -352,6 +363,9 @@ class FitConfig:
         c.panel_stride = self.panel_stride
         c.tile_waves = self.tile_waves
         c.eval_overlap = self.eval_overlap
+        c.allow_missing = self.allow_missing
+        c.estimate_phi = self.estimate_phi
+        c.estimate_alpha = self.estimate_alpha
         return c
 
 
@@ -473,6 +487,42 @@ class GMF:
                                   int(power_iters), {"pearson": 0, "deviance": 1}[residual],
                                   float(y_offset)))
         self.stream.synchronize()
+
+    def set_column_alpha(self, alpha):
+        """gmf_set_column_alpha: one NB shape per column (caller's column order)."""
+        t = self.torch
+        a = t.as_tensor(np.ascontiguousarray(alpha, np.float32), device=self.device)
+        _check(load_library().gmf_set_column_alpha(self.ctx, _ptr(a)))
+        self.stream.synchronize()
+
+    def init_spectrum(self, count):
+        """gmf_init_spectrum: leading singular values of the last initialization's
+        residual matrix."""
+        out = (C.c_double * count)()
+        _check(load_library().gmf_init_spectrum(self.ctx, out, int(count)))
+        return list(out)
+
+    def dispersion(self):
+        """gmf_get_dispersion: (phi, NB shape) in use."""
+        phi, alpha = C.c_double(), C.c_double()
+        _check(load_library().gmf_get_dispersion(self.ctx, C.byref(phi), C.byref(alpha)))
+        return phi.value, alpha.value
+
+    def heldout_metrics(self, Ytest):
+        """gmf_heldout_metrics: Ytest (n x m) holds the held-out values and NaN
+        (or a negative int) elsewhere.  Returns (relative squared log error,
+        relative Poisson deviance, relative family deviance, held-out count,
+        training mean, training count)."""
+        t = self.torch
+        if np.issubdtype(np.asarray(Ytest).dtype, np.integer):
+            Yt = t.as_tensor(np.ascontiguousarray(Ytest, np.int32), device=self.device)
+            ydt = GMF_Y_INT32
+        else:
+            Yt = t.as_tensor(np.ascontiguousarray(Ytest, np.float32), device=self.device)
+            ydt = GMF_Y_FLOAT32
+        out = (C.c_double * 6)()
+        _check(load_library().gmf_heldout_metrics(self.ctx, _ptr(Yt), ydt, out))
+        return tuple(out)
 
     def save_state(self) -> bytes:
         """gmf_save_state: the fit's state as bytes (host memory)."""
@@ -812,3 +862,62 @@ def tune(fc: FitConfig, Y, X, Z, B0, A0, U0, V0, candidates=(32, 64, 128, 256, 5
                                    _ptr(Ut), _ptr(Vt), cands, len(candidates), int(steps),
                                    C.byref(best), us))
     return best.value, {int(c): float(u) for c, u in zip(candidates, us)}
+
+
+# ------------------------------------------------------------ rank selection --
+
+def rank_eigengap(eigenvalues, rmax):
+    """gmf_rank_eigengap (Onatski's edge-distribution estimator) on host values."""
+    ev = np.ascontiguousarray(eigenvalues, dtype=np.float64)
+    r = C.c_int32()
+    _check(load_library().gmf_rank_eigengap(ev.ctypes.data_as(C.POINTER(C.c_double)), len(ev),
+                                            int(rmax), C.byref(r)))
+    return r.value
+
+
+def rank_select_cv(dev_table):
+    """gmf_rank_select_cv: index of the candidate with the smallest mean held-out
+    deviance; dev_table is candidates x folds."""
+    t = np.ascontiguousarray(dev_table, dtype=np.float64)
+    best = C.c_int32()
+    _check(load_library().gmf_rank_select_cv(t.ctypes.data_as(C.POINTER(C.c_double)), t.shape[0],
+                                             t.shape[1], C.byref(best)))
+    return best.value
+
+
+def cv_rank_table(fc: FitConfig, Y, X, Z, B0, A0, starts, folds, epochs, metric=2,
+                  device="cuda:0", use_graph=True):
+    """Out-of-sample rank selection (Section 4.2) on the batched engine: for
+    every candidate rank d (starts: {d: (U0, V0)}) and fold (a boolean mask of
+    held-out entries), a fit of Y with the fold's entries missing; all fits
+    advance together in one batch (gmf_batch_*) for `epochs` epochs, then
+    gmf_heldout_metrics scores each on its held-out entries.  Returns
+    (ranks, table[rank][fold] = metric `metric` of gmf_heldout_metrics, best
+    rank by gmf_rank_select_cv)."""
+    import dataclasses
+    ranks = sorted(starts)
+    p = X.shape[1] if X is not None else 0
+    q = Z.shape[1] if Z is not None else 0
+    stride = max(((p + q + d + 15) // 16) * 16 for d in ranks)
+    Yf = np.asarray(Y, dtype=np.float64)
+    fits = []
+    for d in ranks:
+        for mask in folds:
+            f = dataclasses.replace(fc, d=d, allow_missing=1, panel_stride=stride,
+                                    skip_block_deviance=1)
+            Ytr = np.where(mask, np.nan, Yf).astype(np.float32)
+            U0, V0 = starts[d]
+            fits.append(GMF(f, Ytr, X, Z, B0, A0, U0, V0, device=device))
+    b = Batch(fits, table_epochs=max(epochs, 1), use_graph=use_graph)
+    b.run(epochs, trace=False)
+    b.close()
+    table = np.zeros((len(ranks), len(folds)))
+    k = 0
+    for i, _ in enumerate(ranks):
+        for j, mask in enumerate(folds):
+            Ytest = np.where(mask, Yf, np.nan).astype(np.float32)
+            table[i, j] = fits[k].heldout_metrics(Ytest)[metric]
+            fits[k].close()
+            k += 1
+    return ranks, table, ranks[rank_select_cv(table)]
+

@@ -142,3 +142,9 @@ def test_gaussian_exact_low_rank_is_reproduced():
     s = np.linalg.svd(Rc, compute_uv=False)
     err = np.sum((Y - X @ B.T - A @ Z.T - U @ V.T) ** 2)
     assert abs(err - s[d - 1] ** 2) <= 1e-8 * s[0] ** 2
+
+
+def test_logit_transform_maps_binary_values():
+    y = np.array([0.0, 1.0])
+    np.testing.assert_allclose(I.link_transform("logit", y), [-np.log(3.0), np.log(3.0)],
+                               rtol=1e-14)

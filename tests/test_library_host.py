@@ -213,3 +213,24 @@ def test_null_handles_elsewhere(lib):
                         ("gmf_encoder_get_weights", (None,) * 6)):
         assert getattr(so, name)(None, *extra) == lib.GMF_EINVAL, name
         assert so.gmf_encoder_last_error(), name
+
+
+def test_rank_eigengap_matches_oracle(lib):
+    """gmf_rank_eigengap (pure host code) against the oracle's estimator on
+    spectra with 0 to 7 planted factors, and its argument checks."""
+    from oracle import rank_oracle as K
+    for d, seed in [(0, 1), (2, 2), (4, 3), (7, 4)]:
+        rng = np.random.default_rng(seed)
+        E = rng.normal(size=(400, 200))
+        if d:
+            P = np.linalg.qr(rng.normal(size=(400, d)))[0]
+            Q = np.linalg.qr(rng.normal(size=(200, d)))[0]
+            E += (P * (0.35 * np.sqrt(400 * 200) * np.linspace(1.0, 0.6, d))) @ Q.T
+        lam = np.linalg.svd(E, compute_uv=False) ** 2
+        for rmax in (8, 12):
+            assert lib.rank_eigengap(lam, rmax) == K.eigengap_rank(lam, rmax)
+    with pytest.raises(lib.GMFError):
+        lib.rank_eigengap(np.arange(10.0), 3)          # ascending
+    with pytest.raises(lib.GMFError):
+        lib.rank_eigengap(np.arange(10.0)[::-1], 8)    # fewer than rmax + 5 values
+    assert lib.rank_select_cv([[0.5, 0.7], [0.4, 0.6], [0.45, 0.7]]) == 1
