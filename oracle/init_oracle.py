@@ -82,15 +82,27 @@ def _orth(M):
     return Q
 
 
-def randomized_left_vectors(E, Omega, power_iters: int, d: int):
-    """First d left singular vectors of E (n x m) from the test matrix Omega."""
+def _range_basis(E, Omega, power_iters: int):
     Yk = E @ Omega
     for _ in range(power_iters):
         Q = _orth(Yk)
         Yk = E @ _orth(E.T @ Q)
-    Q = _orth(Yk)
+    return _orth(Yk)
+
+
+def randomized_left_vectors(E, Omega, power_iters: int, d: int):
+    """First d left singular vectors of E (n x m) from the test matrix Omega."""
+    Q = _range_basis(E, Omega, power_iters)
     Ub, _, _ = np.linalg.svd(Q.T @ E, full_matrices=False)
     return Q @ Ub[:, :d]
+
+
+def randomized_singular_values(E, Omega, power_iters: int):
+    """The singular values of Q'E, the range finder's estimates of the k
+    leading singular values of E (exact for the leading ones when the power
+    iterations have converged; below the true values in a flat tail)."""
+    Q = _range_basis(E, Omega, power_iters)
+    return np.linalg.svd(Q.T @ E, compute_uv=False)
 
 
 def initialize(cfg: G.Config, Y, X, Z, d: int, Omega, power_iters: int = 2,
