@@ -382,11 +382,12 @@ def batch_specs(nfits, scale, seed=1004):
     return out
 
 
-def run_batched(nfits, scale, epochs, torch):
+def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", solo=True):
     """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
     against batched epochs (gmf_batch_*, with and without the recorded graph).
     Fits are grouped into batches by panel stride (p + q + d <= 32 -> 32,
-    else 48); every fit uses 128-row tiles."""
+    else 48, 64 for the bfloat16 precisions); every fit uses `tile_rows`-row
+    tiles (0: the library's rule)."""
     from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF
     from synth import gen_nb
     specs = batch_specs(nfits, scale)
@@ -395,12 +396,13 @@ def run_batched(nfits, scale, epochs, torch):
     for sp in specs:
         pr = gen_nb(n=sp["n"], m=sp["m"], d=sp["d"], R=10, S=5, seed=sp["seed"],
                     family=sp["family"], chunked=True)
-        stride = 32 if pr.k <= 32 else 48
-        # 128-row tiles: in a batch the other fits supply the parallelism, and
-        # deeper tiles pipeline their row groups (61 vs 51 epochs/s at 32 rows)
+        stride = 32 if pr.k <= 32 else (48 if precision == "fp32" else 64)
+        # 128-row tiles by default: in a batch the other fits supply the
+        # parallelism, and deeper tiles pipeline their row groups (61 vs 51
+        # epochs/s at 32 rows)
         fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
                        seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1,
-                       tile_rows=128)
+                       tile_rows=tile_rows, precision=precision)
         fits.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
         entries += pr.n * pr.m
         del pr
@@ -416,21 +418,22 @@ def run_batched(nfits, scale, epochs, torch):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    def solo():
+    def solo_epochs():
         for _ in range(epochs):
             for g in fits:
                 g.step(g.cfg.R * g.cfg.S)
 
-    timed(lambda: [g.step(g.cfg.R * g.cfg.S) for g in fits])      # warm-up epoch
-    t_solo = timed(solo)
+    t_solo = None
+    if solo:
+        timed(lambda: [g.step(g.cfg.R * g.cfg.S) for g in fits])      # warm-up epoch
+        t_solo = timed(solo_epochs)
     res = {}
-    for use_graph in (False, True):
-        batches = [Batch(gs, table_epochs=max(epochs, 1), use_graph=use_graph)
-                   for gs in groups.values()]
+    for mode, name in ((1, "graph"), (2, "leveled")):
+        batches = [Batch(gs, table_epochs=max(epochs, 1), mode=mode) for gs in groups.values()]
         for b in batches:
             b.run(1, trace=False)                                   # warm-up epoch
         t = timed(lambda: [b.run(epochs, trace=False) for b in batches])
-        res["graph" if use_graph else "direct"] = t
+        res[name] = t
         for b in batches:
             b.close()
     for g in fits:
@@ -439,11 +442,13 @@ def run_batched(nfits, scale, epochs, torch):
         workload=(f"{nfits} fits: family coin Poisson/NB, n ~ U{{2000..50000}} x {scale}, "
                   f"m ~ U{{1000..5000}} x {scale}, d ~ U{{5..30}}, p = 3, q = 1, blocks 10 % x 20 %"),
         entries=entries, epochs=epochs, groups={int(k): len(v) for k, v in groups.items()},
-        separate_epochs_per_s=epochs / t_solo,
-        batched_epochs_per_s=epochs / res["direct"],
+        tile_rows=tile_rows, precision=precision,
+        separate_epochs_per_s=None if t_solo is None else epochs / t_solo,
         batched_graph_epochs_per_s=epochs / res["graph"],
-        batched_graph_entries_per_s=entries * epochs / res["graph"],
-        speedup_vs_separate=t_solo / res["graph"],
+        batched_leveled_epochs_per_s=epochs / res["leveled"],
+        batched_leveled_entries_per_s=entries * epochs / res["leveled"],
+        batched_leveled_count_GBs=4.0 * entries * epochs / res["leveled"] / 1e9,
+        speedup_vs_separate=None if t_solo is None else t_solo / res["leveled"],
     )
 
 
@@ -550,6 +555,8 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=0.5,
                     help="factor on n and m of every batched fit")
     ap.add_argument("--batch-epochs", type=int, default=5)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched-fits section and print its result")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known size, to scale HBM byte counters) and exit")
@@ -573,6 +580,9 @@ def main():
     from paper_2412_20509_amd import gmf as _gmf  # noqa: F401  (fails if not built)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_batched:      # the batched-fits section alone (for profiling)
+        print(json.dumps(run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)))
+        return
     log("generating the 100000x5000 NB workload (rank 20)")
     pr = make_problem("c3")
     target = load_target("c3")
@@ -621,8 +631,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)
-        log(f"batched fits: {batched['batched_graph_epochs_per_s']:.1f} epochs/s batched "
-            f"(graph), {batched['separate_epochs_per_s']:.1f} separately")
+        log(f"batched fits: {batched['batched_leveled_epochs_per_s']:.1f} epochs/s batched "
+            f"(level placement), {batched['batched_graph_epochs_per_s']:.1f} (fixed graph), "
+            f"{batched['separate_epochs_per_s']:.1f} separately")
 
     out = dict(
         metric=METRIC, value=head["epochs_per_s"], unit="epochs/s", n_gpus=1,

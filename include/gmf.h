@@ -467,11 +467,19 @@ int gmf_project_noalloc(void* ctx, const void* Ynew, int32_t y_dtype, int64_t n_
 size_t gmf_batch_workspace_bytes(void* const* ctxs, int32_t nfits, int32_t table_epochs);
 /* gmf_batch_init -- set up a batch over ctxs[0..nfits) with a step table of
  * table_epochs epochs (refilled from the host when used up: one stream
- * synchronisation per refill).  use_graph != 0 records the epoch as a HIP
- * graph.  Errors: GMF_EINVAL (mixed precision / panel stride, repeated or NULL
- * contexts), GMF_EWORKSPACE, GMF_EDEVICE. */
+ * synchronisation per refill).  mode 0: the fixed launch sequence above,
+ * launched directly; 1: the same sequence recorded once as a HIP graph and
+ * replayed; 2: level placement -- each fit's steps of a table are placed by
+ * the rule of a single fit (gmf_step: a step waits only for the previous steps
+ * on its row block, column block and partial slot), so launch k runs the
+ * tiles of every fit's level-k steps and the updates of every fit's
+ * level-(k-1) steps (about 27 launches per epoch of R = 10, S = 5 fits
+ * instead of 100), launched directly.  All modes give the results of stepping
+ * each fit on its own.  Errors: GMF_EINVAL (mixed precision / panel stride,
+ * repeated or NULL contexts, a fit that estimates its dispersion, bad mode),
+ * GMF_EWORKSPACE, GMF_EDEVICE. */
 int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits, void* ws,
-                   size_t ws_bytes, int32_t table_epochs, int32_t use_graph);
+                   size_t ws_bytes, int32_t table_epochs, int32_t mode);
 /* gmf_batch_run -- run `epochs` epochs of every fit (fit f: R_f * S_f steps
  * each).  Every eval_every epochs, when dev_trace_host is not NULL, the full
  * deviance of every fit is evaluated (float64, as gmf_deviance) into

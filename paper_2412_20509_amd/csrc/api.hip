@@ -2371,6 +2371,9 @@ struct Batch {
   double* scal = nullptr;            // 8 doubles per fit
   std::vector<BatchLaunch> launches;
   bool use_graph = false;
+  int mode = 0;                      // 0 fixed sequence, 1 its graph, 2 level placement
+  std::vector<int> tile_wgs, upd_wgs;   // per fit: workgroups of a step's tiles / updates
+  std::vector<gmf::BatchSeg> host_segs; // level placement: the segments of the current table
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t used = 0, valid = 0;       // epochs of the current table consumed / available
@@ -2394,7 +2397,11 @@ bool batch_sizes(void* const* ctxs, int nfits, int table_epochs, BatchSizes& z) 
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   z.o_fits = take(sizeof(gmf::LevelArgs) * (size_t)nfits);
-  z.o_segs = take(sizeof(gmf::BatchSeg) * 2 * (size_t)z.L * nfits);
+  // the fixed sequence: 2 segments per step index and fit; level placement:
+  // 2 per step of the table
+  z.o_segs = take(sizeof(gmf::BatchSeg) *
+                  std::max<size_t>(2 * (size_t)z.L * nfits,
+                                   2 * (size_t)z.steps_per_epoch * table_epochs));
   z.o_steps = take(sizeof(gmf::LevelStep) * (size_t)table_epochs * z.steps_per_epoch);
   z.o_cursor = take(sizeof(int) * 4);
   z.o_scal = take(sizeof(double) * 8 * (size_t)nfits);
@@ -2415,6 +2422,69 @@ int enqueue_batch_epoch(Batch* b) {
     HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st));
   }
   HIP_TRY(gmf::launch_advance_cursor(b->cursor, b->st));
+  return GMF_OK;
+}
+
+// Level placement of the table's `ne` epochs (mode 2): each fit's steps get
+// the level rule of a single fit, T(t) = 2 + the largest level of the previous
+// step on its row block, its column block and its partial slot; launch k runs
+// the tiles of every fit's level-k steps and the updates of every fit's
+// level-(k-1) steps.  Each fit's steps keep their order and dependencies, so
+// the results equal stepping the fits one by one.
+int enqueue_batch_leveled(Batch* b, int ne) {
+  const int nf = (int)b->fits.size();
+  std::vector<std::vector<std::vector<int>>> by_level(nf);
+  int max_level = 0;
+  for (int f = 0; f < nf; ++f) {
+    const Plan& P = b->fits[f]->P;
+    const int rs = P.R * P.S;
+    std::vector<int> lr(P.R, -1), ls(P.S, -1), lslot(P.nslot, -1);
+    for (int k = 0; k < ne * rs; ++k) {
+      const int idx = (int)((int64_t)(k / rs) * b->steps_per_epoch + b->step_off[f] + (k % rs));
+      const gmf::LevelStep& st = b->host_steps[idx];
+      int lv = 0;
+      if (lr[st.r] >= 0) lv = std::max(lv, lr[st.r] + 2);
+      if (ls[st.s] >= 0) lv = std::max(lv, ls[st.s] + 2);
+      if (lslot[st.slot] >= 0) lv = std::max(lv, lslot[st.slot] + 2);
+      lr[st.r] = ls[st.s] = lslot[st.slot] = lv;
+      if ((int)by_level[f].size() <= lv) by_level[f].resize(lv + 1);
+      by_level[f][lv].push_back(idx);
+      max_level = std::max(max_level, lv);
+    }
+  }
+  b->host_segs.clear();
+  std::vector<BatchLaunch> launches;
+  for (int lv = 0; lv <= max_level + 1; ++lv) {
+    BatchLaunch l{(int)b->host_segs.size(), 0, 0};
+    for (int f = 0; f < nf; ++f)
+      if (lv < (int)by_level[f].size())
+        for (int idx : by_level[f][lv]) {
+          b->host_segs.push_back(gmf::BatchSeg{l.grid, f, 0, idx});
+          l.grid += b->tile_wgs[f];
+          ++l.nsegs;
+        }
+    for (int f = 0; f < nf; ++f)
+      if (lv >= 1 && lv - 1 < (int)by_level[f].size())
+        for (int idx : by_level[f][lv - 1]) {
+          b->host_segs.push_back(gmf::BatchSeg{l.grid, f, 1, idx});
+          l.grid += b->upd_wgs[f];
+          ++l.nsegs;
+        }
+    if (l.nsegs > 0) launches.push_back(l);
+  }
+  HIP_TRY(hipMemcpyAsync(b->segs_dev, b->host_segs.data(), sizeof(gmf::BatchSeg) * b->host_segs.size(),
+                         hipMemcpyHostToDevice, b->st));
+  for (const BatchLaunch& l : launches) {
+    gmf::BatchArgs ba;
+    ba.fits = b->fits_dev;
+    ba.segs = b->segs_dev + l.seg0;
+    ba.nsegs = l.nsegs;
+    ba.steps = b->steps_dev;
+    ba.steps_per_epoch = 0;      // segments index the table directly
+    ba.table_epochs = 1;
+    ba.cursor = b->cursor;
+    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st));
+  }
   return GMF_OK;
 }
 
@@ -2507,6 +2577,20 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
     fa[f] = level_args(c);
     fa[f].trace = nullptr;
     fa[f].trace_cap = 0;
+    // In a batch the other fits supply the parallelism: one chunk of rows or
+    // columns per update workgroup (no chunks run one after another); the
+    // chunks and their sums are the same, so the results are too.
+    {
+      const Plan& P = c->P;
+      int per = 1;
+      for (int r = 0; r < P.R; ++r)
+        for (int s = 0; s < P.S; ++s)
+          per = std::max(per, upd_workgroups(P.nrows[r], P.mcols[s], P.row_chunk, P.col_chunk, 1));
+      fa[f].upd_sub = 1;
+      fa[f].upd_per_step = per;
+      b->tile_wgs.push_back(P.rr_max * P.ct_max);
+      b->upd_wgs.push_back(per);
+    }
     b->step_off.push_back(off);
     off += (int64_t)c->P.R * c->P.S;
   }
@@ -2517,7 +2601,7 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
       for (int f = 0; f < nfits; ++f) {
         const Plan& P = b->fits[f]->P;
         if (k >= P.R * P.S) continue;
-        const int wgs = kind == 0 ? P.rr_max * P.ct_max : P.upd_per_step;
+        const int wgs = kind == 0 ? P.rr_max * P.ct_max : fa[f].upd_per_step;
         segs.push_back(gmf::BatchSeg{l.grid, f, kind, (int)(b->step_off[f] + k)});
         l.grid += wgs;
         ++l.nsegs;
@@ -2530,7 +2614,9 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
                      hipMemcpyHostToDevice, b->st) != hipSuccess ||
       hipStreamSynchronize(b->st) != hipSuccess)
     return bail(GMF_EDEVICE, "cannot upload the batch tables");
-  if (use_graph) {
+  if (use_graph < 0 || use_graph > 2) return bail(GMF_EINVAL, "mode must be 0, 1 or 2");
+  b->mode = use_graph;
+  if (use_graph == 1) {
     b->use_graph = true;
     if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bail(GMF_EDEVICE, "cannot capture the batch epoch");
@@ -2561,6 +2647,49 @@ extern "C" int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every,
   // a fresh table at every call: the fits may have been stepped on their own
   b->used = b->valid = 0;
   int ev_i = 0;
+  auto evaluate = [&]() -> int {
+    for (int f = 0; f < nfits; ++f) {
+      Ctx* c = b->fits[f];
+      gmf::DevArgs da = dev_args(c);
+      HIP_TRY(gmf::launch_deviance(c->P.fam, c->P.KP, da, b->st));
+      HIP_TRY(gmf::launch_finalize(da.partial, c->P.dev_tiles, nullptr, 0, c->at<int>(c->P.o_flag),
+                                   b->scal + 8 * f, b->st));
+    }
+    std::vector<double> h(8 * (size_t)nfits);
+    HIP_TRY(hipMemcpyAsync(h.data(), b->scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->st));
+    HIP_TRY(hipStreamSynchronize(b->st));
+    for (int f = 0; f < nfits; ++f) {
+      dev_trace_host[(size_t)f * nevals + ev_i] = h[8 * f] + 2.0 * b->fits[f]->ktotal;
+      if (h[8 * f + 5] != 0.0) {
+        const int rc = check_flag(b->fits[f]);
+        if (rc != GMF_OK) return rc;
+      }
+    }
+    ++ev_i;
+    return GMF_OK;
+  };
+  if (b->mode == 2) {
+    for (int e = 0; e < epochs;) {
+      int ne = std::min(b->table_epochs, epochs - e);
+      if (dev_trace_host) ne = std::min(ne, eval_every - e % eval_every);
+      int rc = refill_batch_table(b, ne);
+      if (rc != GMF_OK) return rc;
+      rc = enqueue_batch_leveled(b, ne);
+      if (rc != GMF_OK) return rc;
+      for (Ctx* c : b->fits) {
+        c->t += (int64_t)ne * c->P.R * c->P.S;
+        c->batched_upto = c->t;
+      }
+      e += ne;
+      if (dev_trace_host && e % eval_every == 0) {
+        rc = evaluate();
+        if (rc != GMF_OK) return rc;
+      }
+    }
+    HIP_TRY(hipEventRecord(b->ev, b->st));
+    for (Ctx* c : b->fits) HIP_TRY(hipStreamWaitEvent(c->st, b->ev, 0));
+    return GMF_OK;
+  }
   for (int e = 0; e < epochs; ++e) {
     if (b->used == b->valid) {
       const int rc = refill_batch_table(b, std::min(b->table_epochs, epochs - e));
@@ -2578,24 +2707,8 @@ extern "C" int gmf_batch_run(void* batch, int32_t epochs, int32_t eval_every,
       c->batched_upto = c->t;
     }
     if ((e + 1) % eval_every == 0 && dev_trace_host) {
-      for (int f = 0; f < nfits; ++f) {
-        Ctx* c = b->fits[f];
-        gmf::DevArgs da = dev_args(c);
-        HIP_TRY(gmf::launch_deviance(c->P.fam, c->P.KP, da, b->st));
-        HIP_TRY(gmf::launch_finalize(da.partial, c->P.dev_tiles, nullptr, 0, c->at<int>(c->P.o_flag),
-                                     b->scal + 8 * f, b->st));
-      }
-      std::vector<double> h(8 * (size_t)nfits);
-      HIP_TRY(hipMemcpyAsync(h.data(), b->scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->st));
-      HIP_TRY(hipStreamSynchronize(b->st));
-      for (int f = 0; f < nfits; ++f) {
-        dev_trace_host[(size_t)f * nevals + ev_i] = h[8 * f] + 2.0 * b->fits[f]->ktotal;
-        if (h[8 * f + 5] != 0.0) {
-          const int rc = check_flag(b->fits[f]);
-          if (rc != GMF_OK) return rc;
-        }
-      }
-      ++ev_i;
+      const int rc = evaluate();
+      if (rc != GMF_OK) return rc;
     }
   }
   // the fits' own streams continue after the batch

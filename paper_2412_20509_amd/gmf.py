@@ -765,7 +765,9 @@ class Encoder:
 class Batch:
     """Several GMF contexts advanced together (gmf_batch_*)."""
 
-    def __init__(self, gmfs, table_epochs=4, use_graph=True):
+    def __init__(self, gmfs, table_epochs=4, use_graph=True, mode=None):
+        """mode: 0 fixed launch sequence, 1 its recorded HIP graph, 2 level
+        placement (gmf_batch_init); None: 1 if use_graph else 0."""
         import torch
         self.torch = torch
         self.gmfs = list(gmfs)
@@ -779,9 +781,11 @@ class Batch:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         off = (-self.workspace.data_ptr()) % 256
         self.batch = C.c_void_p()
+        if mode is None:
+            mode = 1 if use_graph else 0
         _check(lib.gmf_batch_init(C.byref(self.batch), self._ctxs, n,
                                   self.workspace.data_ptr() + off, nbytes, int(table_epochs),
-                                  int(bool(use_graph))))
+                                  int(mode)))
 
     def run(self, epochs, eval_every=1, trace=True):
         """Run `epochs` epochs; returns the deviance trace (nfits x evaluations) or None."""
@@ -886,7 +890,7 @@ def rank_select_cv(dev_table):
 
 
 def cv_rank_table(fc: FitConfig, Y, X, Z, B0, A0, starts, folds, epochs, metric=2,
-                  device="cuda:0", use_graph=True):
+                  device="cuda:0", mode=2):
     """Out-of-sample rank selection (Section 4.2) on the batched engine: for
     every candidate rank d (starts: {d: (U0, V0)}) and fold (a boolean mask of
     held-out entries), a fit of Y with the fold's entries missing; all fits
@@ -908,7 +912,7 @@ def cv_rank_table(fc: FitConfig, Y, X, Z, B0, A0, starts, folds, epochs, metric=
             Ytr = np.where(mask, np.nan, Yf).astype(np.float32)
             U0, V0 = starts[d]
             fits.append(GMF(f, Ytr, X, Z, B0, A0, U0, V0, device=device))
-    b = Batch(fits, table_epochs=max(epochs, 1), use_graph=use_graph)
+    b = Batch(fits, table_epochs=max(epochs, 1), mode=mode)
     b.run(epochs, trace=False)
     b.close()
     table = np.zeros((len(ranks), len(folds)))

@@ -34,15 +34,15 @@ def _state(g):
     return [np.asarray(x) for x in g.params()] + [np.asarray(x) for x in g.moments()]
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_equals_separate_fits(problems, use_graph):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_equals_separate_fits(problems, mode):
     from paper_2412_20509_amd.gmf import Batch
-    print(f"[case] batch of 4 fits, graph={use_graph}", flush=True)
+    print(f"[case] batch of 4 fits, mode={mode}", flush=True)
     solo = _make(problems, 32)
     for g, pr in zip(solo, problems):
         g.step(2 * pr.R * pr.S)
     fits = _make(problems, 32)
-    b = Batch(fits, table_epochs=4, use_graph=use_graph)
+    b = Batch(fits, table_epochs=4, mode=mode)
     tr = b.run(2, eval_every=1, trace=True)
     for g, h, pr in zip(fits, solo, problems):
         assert g.steps_done() == 2 * pr.R * pr.S
@@ -57,16 +57,17 @@ def test_batch_equals_separate_fits(problems, use_graph):
         g.close()
 
 
-def test_batch_table_refill_and_continuation(problems):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_table_refill_and_continuation(problems, mode):
     """Three epochs through a 2-epoch table, then two more epochs in a second
     call, equal five epochs stepped separately."""
     from paper_2412_20509_amd.gmf import Batch
-    print("[case] batch refill + continuation", flush=True)
+    print(f"[case] batch refill + continuation, mode={mode}", flush=True)
     solo = _make(problems[:3], 32)
     for g, pr in zip(solo, problems):
         g.step(5 * pr.R * pr.S)
     fits = _make(problems[:3], 32)
-    b = Batch(fits, table_epochs=2, use_graph=True)
+    b = Batch(fits, table_epochs=2, mode=mode)
     b.run(3, trace=False)
     b.run(2, eval_every=2, trace=True)
     for g, h in zip(fits, solo):
