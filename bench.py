@@ -345,6 +345,26 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
                          ms_per_epoch=(msx[-1] - msx[0]) / max_epochs)
     ec, tc = first_hit(trc, msc, dstar)
     ew, tw = first_hit(trw, msw, dstar)
+    # the FP64 oracle's D* on its seeded 1 % subset of the new rows (rows are
+    # independent: projecting the subset alone equals the full projection
+    # restricted to it): each arm's distance to it and epochs to 1e-4 of it
+    oracle_subset = None
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_warm_subset_c5.json")
+    if os.path.exists(gold) and n_new == json.load(open(gold))["n_new"]:
+        gs = json.load(open(gold))
+        idx = torch.as_tensor(np.asarray(gs["rows"], np.int64), device="cuda:0")
+        Ys, Xs = Yd[idx].contiguous(), Xd[idx].contiguous()
+        cs = enc.forward(Ys, bf16=True)
+        oracle_subset = dict(rows=gs["subset_rows"], dstar=gs["dstar"],
+                             oracle_last_rel_change=gs["last_rel_change"])
+        for name, prec, cand in (("cold", "fp32", None), ("warm", "fp32", cs),
+                                 ("warm_bf16x3", "bf16x3", cs), ("warm_bf16", "bf16", cs)):
+            g.set_precision(prec)
+            _, _, trs, mss, _ = g.project_warm(Ys, Xs, cand, max_epochs, frozen=1, trace=True)
+            g.set_precision("fp32")
+            es, _ = first_hit(trs, mss, gs["dstar"])
+            oracle_subset[name] = dict(final_rel_to_oracle_dstar=abs(trs[-1] - gs["dstar"]) /
+                                       gs["dstar"], epochs_to_1e4_of_oracle_dstar=es)
     enc.close()
     g.close()
     return dict(
@@ -363,6 +383,7 @@ def run_warm_start(pr, n_new, max_epochs, enc_epochs, torch):
                   ms_per_epoch=(msw[-1] - msw[0]) / max_epochs),
         warm_bf16x3=bfa["bf16x3"],
         warm_bf16=bfa["bf16"],
+        oracle_subset=oracle_subset,
     )
 
 
@@ -382,30 +403,44 @@ def batch_specs(nfits, scale, seed=1004):
     return out
 
 
-def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", solo=True):
-    """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
-    against batched epochs (gmf_batch_*, with and without the recorded graph).
-    Fits are grouped into batches by panel stride (p + q + d <= 32 -> 32,
-    else 48, 64 for the bfloat16 precisions); every fit uses `tile_rows`-row
-    tiles (0: the library's rule)."""
-    from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF
+def gen_batched(nfits, scale):
+    """The seeded problems of the batched-fits workload (host arrays)."""
     from synth import gen_nb
-    specs = batch_specs(nfits, scale)
     log(f"batched fits: generating {nfits} problems (scale {scale})")
+    return [gen_nb(n=sp["n"], m=sp["m"], d=sp["d"], R=10, S=5, seed=sp["seed"],
+                   family=sp["family"], chunked=True) for sp in batch_specs(nfits, scale)]
+
+
+def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", solo=True,
+                problems=None, modes=((1, "graph"), (2, "leveled"))):
+    """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
+    against batched epochs (gmf_batch_*: the fixed launch sequence as a
+    recorded graph, and level placement).  Fits are grouped into batches by
+    panel stride (p + q + d <= 32 -> 32, else 48, 64 for the bfloat16
+    precisions); every fit uses `tile_rows`-row tiles (0: the library's rule,
+    -1: the autotuner's table, the first fit of each shape class tuned)."""
+    from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF, tune, tune_lookup
+    if problems is None:
+        problems = gen_batched(nfits, scale)
+    tuned = {}
     fits, entries = [], 0
-    for sp in specs:
-        pr = gen_nb(n=sp["n"], m=sp["m"], d=sp["d"], R=10, S=5, seed=sp["seed"],
-                    family=sp["family"], chunked=True)
+    for pr in problems:
         stride = 32 if pr.k <= 32 else (48 if precision == "fp32" else 64)
         # 128-row tiles by default: in a batch the other fits supply the
         # parallelism, and deeper tiles pipeline their row groups (61 vs 51
         # epochs/s at 32 rows)
         fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
                        seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1,
-                       tile_rows=tile_rows, precision=precision)
+                       tile_rows=max(tile_rows, 0), precision=precision)
+        if tile_rows < 0:
+            fc.tile_rows = 0
+            cfg = fc.to_c(pr.n, pr.m, pr.p, pr.q)
+            if tune_lookup(cfg) == 0:
+                best, _ = tune(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0,
+                               candidates=(64, 128, 256, 512), steps=20)
+                tuned[best] = tuned.get(best, 0) + 1
         fits.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
         entries += pr.n * pr.m
-        del pr
     torch.cuda.synchronize()
     groups = {}
     for g in fits:
@@ -428,7 +463,7 @@ def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", so
         timed(lambda: [g.step(g.cfg.R * g.cfg.S) for g in fits])      # warm-up epoch
         t_solo = timed(solo_epochs)
     res = {}
-    for mode, name in ((1, "graph"), (2, "leveled")):
+    for mode, name in modes:
         batches = [Batch(gs, table_epochs=max(epochs, 1), mode=mode) for gs in groups.values()]
         for b in batches:
             b.run(1, trace=False)                                   # warm-up epoch
@@ -438,18 +473,23 @@ def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", so
             b.close()
     for g in fits:
         g.close()
-    return dict(
+    del fits
+    torch.cuda.empty_cache()
+    out = dict(
         workload=(f"{nfits} fits: family coin Poisson/NB, n ~ U{{2000..50000}} x {scale}, "
                   f"m ~ U{{1000..5000}} x {scale}, d ~ U{{5..30}}, p = 3, q = 1, blocks 10 % x 20 %"),
         entries=entries, epochs=epochs, groups={int(k): len(v) for k, v in groups.items()},
-        tile_rows=tile_rows, precision=precision,
-        separate_epochs_per_s=None if t_solo is None else epochs / t_solo,
-        batched_graph_epochs_per_s=epochs / res["graph"],
-        batched_leveled_epochs_per_s=epochs / res["leveled"],
-        batched_leveled_entries_per_s=entries * epochs / res["leveled"],
-        batched_leveled_count_GBs=4.0 * entries * epochs / res["leveled"] / 1e9,
-        speedup_vs_separate=None if t_solo is None else t_solo / res["leveled"],
-    )
+        tile_rows=tile_rows if tile_rows >= 0 else "autotuned", tuned_classes=tuned,
+        precision=precision,
+        separate_epochs_per_s=None if t_solo is None else epochs / t_solo)
+    for name, t in res.items():
+        out[f"batched_{name}_epochs_per_s"] = epochs / t
+        out[f"batched_{name}_count_GBs"] = 4.0 * entries * epochs / t / 1e9
+    if "leveled" in res:
+        out["batched_leveled_hbm_frac_counts"] = out["batched_leveled_count_GBs"] / HBM_PEAK_GBS
+        if t_solo is not None:
+            out["speedup_vs_separate"] = t_solo / res["leveled"]
+    return out
 
 
 def cpu_info():
@@ -552,7 +592,7 @@ def main():
     ap.add_argument("--encoder-epochs", type=int, default=40)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-fits section")
     ap.add_argument("--batch-fits", type=int, default=64)
-    ap.add_argument("--batch-scale", type=float, default=0.5,
+    ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="factor on n and m of every batched fit")
     ap.add_argument("--batch-epochs", type=int, default=5)
     ap.add_argument("--only-batched", action="store_true",
@@ -630,7 +670,13 @@ def main():
             f"{warm['warm']['fallback_rows']} fallback rows")
     batched = None
     if not args.no_batched:
-        batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)
+        probs = gen_batched(args.batch_fits, args.batch_scale)
+        batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
+                              problems=probs)
+        batched["bf16"] = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
+                                      precision="bf16", solo=False, problems=probs,
+                                      modes=((2, "leveled"),))
+        del probs
         log(f"batched fits: {batched['batched_leveled_epochs_per_s']:.1f} epochs/s batched "
             f"(level placement), {batched['batched_graph_epochs_per_s']:.1f} (fixed graph), "
             f"{batched['separate_epochs_per_s']:.1f} separately")

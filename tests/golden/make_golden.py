@@ -7,7 +7,10 @@ epoch of the seeded schedule, for the workloads:
       measure the seed-to-seed spread of the final deviance);
   c2: NB(alpha=5) 10000 x 2000, d = 10, p = 3, q = 1, 200 epochs;
   c3: NB(alpha=5) 100000 x 5000, d = 20, p = 3, q = 1, 200 epochs (full
-      deviance every 10 epochs).
+      deviance every 10 epochs);
+  c5: the learned warm start's D* on a seeded 1 % subset of its 1,000,000
+      new rows (oracle fit, Algorithm 2, oracle projection of the subset;
+      tests/golden/oracle_warm_subset_c5.json).
 Run: python tests/golden/make_golden.py [c1|c2|c3 ...] [--checkpoint DIR]
 
 With --checkpoint DIR the oracle's whole state (parameters, moments, step
@@ -88,6 +91,48 @@ def trace(name, epochs, seed_shift=0, eval_every=1, ckpt_dir=None):
     return _record(name, cfg, epochs, evals, devs)
 
 
+def warm_subset(n_new=1_000_000, frac=0.01, epochs=180, subset_seed=5006):
+    """D* of the learned warm-start workload on a seeded 1 % subset of its new
+    rows: the oracle's 200-epoch fit of the 10000 x 2000 NB workload, its
+    Algorithm 2 column side, and the oracle's projection of the subset rows
+    from the cold start (row intercept, U = 0) run for `epochs` epochs (rows
+    are independent, so the subset's projection is the full projection
+    restricted to it).  Records the subset's row indices, the deviance trace
+    of the subset every 10 epochs and its last relative change."""
+    from synth import gen_nb_rows
+    pr = make_problem("c2")
+    cfg = G.Config(family=pr.family, link=pr.link, phi=pr.phi, nb_alpha=pr.nb_alpha,
+                   R=pr.R, S=pr.S, seed=pr.sched_seed)
+    o = G.OracleGMF(cfg, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0)
+    t0 = time.time()
+    for e in range(200):
+        o.epoch()
+        if (e + 1) % 50 == 0:
+            print(f"c5: oracle fit epoch {e + 1} ({time.time() - t0:.0f}s)", flush=True)
+    B, _, _, V = G.postprocess_A_B1(pr.X, pr.Z, o.B, o.A, o.U, o.V)
+    Ynew, Xnew, _, _ = gen_nb_rows(pr, n_new, seed=5005)
+    rows = np.sort(np.random.default_rng(subset_seed).choice(n_new, int(frac * n_new),
+                                                             replace=False))
+    Ys = np.asarray(Ynew[rows])
+    Xs = np.asarray(Xnew[rows], np.float64)
+    del Ynew, Xnew
+    cols = G.partition(G.permutation(cfg.seed, G.STREAM_COLS, pr.m), pr.S)
+    A0 = G.row_intercept_start(cfg, Ys, Xs, B, pr.q)
+    U0 = np.zeros((len(rows), pr.d))
+    rec = []
+    G.project_rows(cfg, Ys, Xs, pr.Z, B, V, A0, U0, epochs, cols, record=rec)
+    # the subset's deviance at the start and after every 10th epoch (S steps each)
+    trace = [float(G.row_deviance(cfg, Ys, Xs, pr.Z, B, A0, U0, V).sum())]
+    for e in range(10, epochs + 1, 10):
+        A, U = rec[e * pr.S - 1]
+        trace.append(float(G.row_deviance(cfg, Ys, Xs, pr.Z, B, A, U, V).sum()))
+    return dict(workload="learned warm start: new NB rows of the 10000x2000 workload's column side",
+                n_new=n_new, subset_rows=int(len(rows)), subset_seed=subset_seed,
+                rows=[int(r) for r in rows], epochs=epochs, deviance_every_10_epochs=trace,
+                last_rel_change=abs(trace[-1] - trace[-2]) / trace[-1], dstar=trace[-1],
+                fit_epochs=200, fit_final_deviance=o.full_deviance())
+
+
 def main(argv):
     ckpt_dir = None
     names = []
@@ -98,6 +143,13 @@ def main(argv):
         else:
             names.append(a)
     for name in names or ["c1", "c2"]:
+        if name == "c5":
+            out = warm_subset()
+            path = os.path.join(HERE, "oracle_warm_subset_c5.json")
+            with open(path, "w") as f:
+                json.dump(out, f)
+            print("wrote", path, flush=True)
+            continue
         out = trace(name, 200, eval_every=10 if name == "c3" else 1, ckpt_dir=ckpt_dir)
         if name == "c1":
             out["seed_spread_finals"] = [trace(name, 200, k)["final"] for k in range(1, 5)]

@@ -72,6 +72,30 @@ def test_c2_fit_tracks_oracle_trace_every_epoch(c2_problem, precision):
     g.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_bfloat16_arms_reach_oracle_final_deviance(c2_problem, precision):
+    """The spec claim for the bfloat16 arms: continued past the oracle's
+    200-epoch budget (to 300 epochs), the fit comes within 1e-4 of D* (the
+    oracle's deviance after 200 epochs) -- plain BF16 trails the FP32
+    trajectory by about 1e-3 at epoch 200 and catches up about 20 epochs
+    later -- and stays below D* (1 + 1e-4) from there on."""
+    tr = json.load(open(os.path.join(GOLDEN, "oracle_trace_c2.json")))
+    dstar = tr["final"]
+    pr = c2_problem
+    say(f"c2 {precision}, 300 epochs, first epoch within 1e-4 of the oracle's D*")
+    g = gpu_for(pr, precision=precision, rate0=tr["rate0"], decay=tr["decay"], tau=tr["tau"],
+                alpha1=tr["alpha1"], alpha2=tr["alpha2"], damping=tr["damping"],
+                lam=tr["lam"])
+    devs, _ = g.run(300, eval_every=1)
+    devs = np.asarray(devs)
+    hit = np.nonzero(np.abs(devs - dstar) <= 1e-4 * dstar)[0]
+    print(f"{precision}: first epoch within 1e-4 of D*: {hit[0] + 1 if len(hit) else None}, "
+          f"epoch 300 {(devs[-1] - dstar) / dstar:+.3e}")
+    assert len(hit) > 0 and hit[0] + 1 <= 260
+    assert np.all(devs[hit[0]:] <= dstar * (1 + 1e-4))
+    g.close()
+
+
 def test_bias_mode_printed_formula_one_step_and_epoch():
     pr = gen_poisson_small()
     say("bias_mode = 1 (printed alpha_t): one step, one epoch, c1")
