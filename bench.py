@@ -267,10 +267,16 @@ def roofline_of(pr, arm, precision):
         achieved = steps * w["flops"] / t / 1e12
         out = dict(bound="mfma", achieved=achieved, peak=FP32_PEAK_TFS, unit="TFLOP/s",
                    frac=achieved / FP32_PEAK_TFS)
-    out.update(traffic=recorded_traffic(pr, precision), kernel=f"level_kernel ({precision})",
+    traffic = recorded_traffic(pr, precision)
+    out.update(traffic=traffic, kernel=step_kernel_name(pr, precision),
                bytes_per_step=w["bytes"], flops_per_step=w["flops"],
                steps_per_launch=steps / launches, mean_launch_us=1e6 * t / launches,
                launches=arm["launches"])
+    if traffic is not None:
+        # the same launch time against the bytes the HBM counters measured
+        out["measured_GBs"] = traffic / (t / launches) / 1e9
+        out["measured_frac_hbm"] = out["measured_GBs"] / HBM_PEAK_GBS
+        out["traffic_over_algorithmic"] = traffic / (w["bytes"] * steps / launches)
     return out
 
 

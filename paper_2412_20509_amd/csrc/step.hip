@@ -636,6 +636,42 @@ __device__ void sum_block_deviance(const LevelArgs& a, const LevelStep& st, doub
   if (threadIdx.x == 0) a.devring[(st.t - 1) % a.devring_len] = sums[0];
 }
 
+// Update workgroup `local` of step `st`: a range of row chunks, of column
+// chunks, or the block deviance.  Returns the task kind (1 row update, 2
+// column update, 3 block deviance, -1 nothing to do).  sums: kTileThreads
+// doubles of LDS; needs at least kTileThreads threads.
+template <bool WANT_DEV>
+__device__ __forceinline__ int run_update(const LevelArgs& a, const LevelStep& st, int local,
+                                          double* sums) {
+  int u = local;
+  const int n_b = st.n_b, m_b = st.m_b;
+  const int sub = a.upd_sub;
+  const int rspan = a.row_chunk * sub, cspan = a.col_chunk * sub;
+  const int nrw = (n_b + rspan - 1) / rspan;
+  const int ncw = (m_b + cspan - 1) / cspan;
+  if (u < nrw) {
+    const int end = min(n_b, (u + 1) * rspan);
+    for (int r0 = u * rspan; r0 < end; r0 += a.row_chunk) {
+      update_rows(a, st, r0, min(end, r0 + a.row_chunk), sums);
+      __syncthreads();   // sums is reused by the next chunk
+    }
+    return 1;
+  }
+  if ((u -= nrw) < ncw) {
+    const int end = min(m_b, (u + 1) * cspan);
+    for (int c0 = u * cspan; c0 < end; c0 += a.col_chunk) {
+      update_cols(a, st, c0, min(end, c0 + a.col_chunk), sums);
+      __syncthreads();
+    }
+    return 2;
+  }
+  if (u == ncw) {
+    if (WANT_DEV) sum_block_deviance(a, st, sums);
+    return 3;
+  }
+  return -1;
+}
+
 // ------------------------------------------------------------- kernel -----
 template <int PREC, int KP, int NW>
 union LevelLds {
@@ -678,33 +714,7 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
       a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
     return 0;
   }
-  int u = local;
-  const int n_b = st.n_b, m_b = st.m_b;
-  const int sub = a.upd_sub;
-  const int rspan = a.row_chunk * sub, cspan = a.col_chunk * sub;
-  const int nrw = (n_b + rspan - 1) / rspan;
-  const int ncw = (m_b + cspan - 1) / cspan;
-  if (u < nrw) {
-    const int end = min(n_b, (u + 1) * rspan);
-    for (int r0 = u * rspan; r0 < end; r0 += a.row_chunk) {
-      update_rows(a, st, r0, min(end, r0 + a.row_chunk), L.sums);
-      __syncthreads();   // sums is reused by the next chunk
-    }
-    return 1;
-  }
-  if ((u -= nrw) < ncw) {
-    const int end = min(m_b, (u + 1) * cspan);
-    for (int c0 = u * cspan; c0 < end; c0 += a.col_chunk) {
-      update_cols(a, st, c0, min(end, c0 + a.col_chunk), L.sums);
-      __syncthreads();
-    }
-    return 2;
-  }
-  if (u == ncw) {
-    if (WANT_DEV) sum_block_deviance(a, st, L.sums);
-    return 3;
-  }
-  return -1;
+  return run_update<WANT_DEV>(a, st, local, L.sums);
 }
 
 // Occupancy: two 4-wavefront tiles per compute unit, three for the bfloat16
@@ -742,6 +752,32 @@ __global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : ((PREC == kBF16 && KP =
       rec[5] = kind == 0 ? stamps[0] : 0;
       rec[6] = kind == 0 ? stamps[1] : 0;
       rec[7] = kind == 0 ? stamps[2] : 0;
+    }
+  }
+}
+
+// A launch of updates only (no tiles): the same update tasks as level_kernel
+// with only their own LDS (kTileThreads doubles), so that many more update
+// workgroups share a compute unit than when they carry a tile's LDS.
+template <bool WANT_DEV>
+__global__ __launch_bounds__(kTileThreads) void update_kernel(LevelArgs a) {
+  __shared__ double sums[kTileThreads];
+  const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
+  const int b = blockIdx.x;
+  const int k = b / a.upd_per_step;
+  if (k >= a.n_upd_steps) return;
+  const int kind = run_update<WANT_DEV>(a, a.steps[k], b % a.upd_per_step, sums);
+  if (kind < 0) return;
+  if (a.trace && threadIdx.x == 0) {
+    const long long gi = (long long)a.trace_base + blockIdx.x;
+    if (gi < a.trace_cap) {
+      unsigned long long* rec = a.trace + 8 * gi;
+      rec[0] = a.launch_id;
+      rec[1] = ((unsigned long long)blockIdx.x << 32) | (unsigned)kind;
+      rec[2] = tr0;
+      rec[3] = wall_clock64();
+      rec[4] = __smid();
+      rec[5] = rec[6] = rec[7] = 0;
     }
   }
 }
@@ -840,6 +876,15 @@ bool level_supports_nw8(int prec, int KP) {
 
 hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const LevelArgs& a,
                         int grid, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (a.n_tile_steps == 0) {   // updates only: the small-LDS kernel, kTileThreads threads
+    if (grid <= 0) return hipSuccess;
+    const void* uk = want_dev ? reinterpret_cast<const void*>(&update_kernel<true>)
+                              : reinterpret_cast<const void*>(&update_kernel<false>);
+    void* uargs[] = {const_cast<LevelArgs*>(&a)};
+    if (ev_start || ev_stop)
+      return hipExtLaunchKernel(uk, dim3(grid), dim3(kTileThreads), uargs, 0, s, ev_start, ev_stop, 0);
+    return hipLaunchKernel(uk, dim3(grid), dim3(kTileThreads), uargs, 0, s);
+  }
   const void* k = level_kernel_for(prec, fam, KP, want_dev, nw);
   if (!k) return hipErrorInvalidValue;
   if (grid <= 0) return hipSuccess;
