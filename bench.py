@@ -35,7 +35,10 @@ Printed JSON line:
                     y per block entry plus the panel and moment traffic
                     2 (|I| (q+d) + |J| (p+d)) (4 + 2 x 8) B per step; the FP32
                     arm on flops against the 157.3 TFLOP/s float32 peak:
-                    2 (3p + 3q + 5d) per block entry.  traffic = measured HBM
+                    2 (3p + 3q + 5d) per block entry.  With the counts held
+                    as 16-bit integers (compact_counts) the tiles read 2 B
+                    per entry: stored_GBs / stored_frac_hbm rate the launch
+                    on those bytes.  traffic = measured HBM
                     bytes per launch (rocprofv3 counters, summary under
                     profiles/), null when the kernel changed since
   from_initialization  the headline arm started from the paper's
@@ -88,17 +91,19 @@ def make_gmf(pr, precision):
 PREC_CODE = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 
-def step_kernel_name(pr, precision):
+def step_kernel_name(pr, precision, compact):
     """Template name of the step kernel that runs a workload: level_kernel<
-    precision, family, panel stride, block deviance, wavefronts per tile>."""
+    precision, family, panel stride, block deviance, wavefronts per tile,
+    16-bit counts>."""
     fam = {"poisson": 0, "negbin": 1, "gaussian": 2}[pr.family]
     k = pr.p + pr.q + pr.d
     # automatic panel stride: k rounded up to 16 (FP32, or k <= 16), else to 32
     stride = (k + 15) // 16 * 16 if (precision == "fp32" or k <= 16) else (k + 31) // 32 * 32
-    return f"level_kernel<{PREC_CODE[precision]}, {fam}, {stride}, true, 4>"
+    cy = "true" if compact and precision != "fp32" else "false"
+    return f"level_kernel<{PREC_CODE[precision]}, {fam}, {stride}, true, 4, {cy}>"
 
 
-def recorded_traffic(pr, precision):
+def recorded_traffic(pr, precision, compact):
     """HBM bytes per launch of a workload's step kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the summary has no
     line for the kernel or the kernel sources (step.hip, family.hpp, mfma.hpp)
@@ -111,7 +116,7 @@ def recorded_traffic(pr, precision):
         with open(os.path.join(ROOT, "paper_2412_20509_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     src = h.hexdigest()[:16]
-    want = step_kernel_name(pr, precision)
+    want = step_kernel_name(pr, precision, compact)
     shape = f"{pr.n}x{pr.m}"
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
         for m in re.finditer(r"traffic_bytes_per_launch: (\d+) source: ([0-9a-f]+) "
@@ -130,11 +135,13 @@ def step_work(pr, bf16):
     block's entries): bytes = 4 B of y per entry plus the panel and moment
     traffic 2 (|I| (q+d) + |J| (p+d)) (4 + 2 s) with s = 8 B (float64 moments)
     on the bfloat16 paths and 4 B on the FP32 path; flops = 2 (3p + 3q + 5d)
-    per entry (eta, the two U-side and the two V-side contractions)."""
+    per entry (eta, the two U-side and the two V-side contractions).
+    bytes_stored: the same with the 2 B per entry the step tiles read when
+    the counts are held as 16-bit integers."""
     ns, ms = pr.n / pr.R, pr.m / pr.S
     s_mom = 8.0 if bf16 else 4.0
     panels = 2.0 * (ns * (pr.q + pr.d) + ms * (pr.p + pr.d)) * (4.0 + 2.0 * s_mom)
-    return dict(bytes=4.0 * ns * ms + panels,
+    return dict(bytes=4.0 * ns * ms + panels, bytes_stored16=2.0 * ns * ms + panels,
                 flops=2.0 * (3 * pr.p + 3 * pr.q + 5 * pr.d) * ns * ms)
 
 
@@ -157,6 +164,7 @@ def run_arm(pr, precision, epochs, warmup, budget, dstar, torch, polish=0):
 
     # the timed region: `epochs` epochs, the full deviance of every epoch
     g = make_gmf(pr, precision)
+    compact = g.compact_counts
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.run(epochs, eval_every=1)
@@ -214,7 +222,7 @@ def run_arm(pr, precision, epochs, warmup, budget, dstar, torch, polish=0):
                 deviance_every_10_epochs=devs[9::10],
                 s_to_1e4=t_hit, epochs_to_1e4=e_hit,
                 launch_ms_total=launch_ms, launches=int(launches), timed_steps=nsteps,
-                postprocess_s=t_pp)
+                postprocess_s=t_pp, compact_counts=compact)
 
 
 def run_init_arm(pr, precision, budget, dstar, torch, power_iters=2, oversample=6):
@@ -267,11 +275,17 @@ def roofline_of(pr, arm, precision):
         achieved = steps * w["flops"] / t / 1e12
         out = dict(bound="mfma", achieved=achieved, peak=FP32_PEAK_TFS, unit="TFLOP/s",
                    frac=achieved / FP32_PEAK_TFS)
-    traffic = recorded_traffic(pr, precision)
-    out.update(traffic=traffic, kernel=step_kernel_name(pr, precision),
+    compact = bool(arm.get("compact_counts")) and precision != "fp32"   # FP32 tiles read float32
+    traffic = recorded_traffic(pr, precision, compact)
+    out.update(traffic=traffic, kernel=step_kernel_name(pr, precision, compact),
                bytes_per_step=w["bytes"], flops_per_step=w["flops"],
+               counts_bytes_per_entry=2 if compact else 4,
                steps_per_launch=steps / launches, mean_launch_us=1e6 * t / launches,
                launches=arm["launches"])
+    if compact:
+        # the bytes the kernel has to move with 16-bit counts, against HBM
+        out["stored_GBs"] = steps * w["bytes_stored16"] / t / 1e9
+        out["stored_frac_hbm"] = out["stored_GBs"] / HBM_PEAK_GBS
     if traffic is not None:
         # the same launch time against the bytes the HBM counters measured
         out["measured_GBs"] = traffic / (t / launches) / 1e9

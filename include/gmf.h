@@ -121,6 +121,17 @@ typedef struct gmf_config {
                            With either estimator every step waits for the
                            previous one (its D1, D2 use the estimate it
                            updated): two launches per step               */
+  int32_t compact_counts; /* 1 (default): for the Poisson and NB families on
+                           their fixed-shape epilogue (no missing entries,
+                           no estimation, no per-column shapes) with every
+                           count in [0, 65535], the workspace also holds the
+                           counts as 16-bit integers (2 B per entry more),
+                           and the bfloat16 step tiles (BF16, BF16X3) and the
+                           full deviance read those instead of the float32
+                           copy: the same values, half the bytes, the same
+                           results bit for bit.  Decided at gmf_init from
+                           the data (gmf_compact_counts reports it); 0: the
+                           float32 counts only                             */
 } gmf_config;
 
 /* Fill *cfg with the defaults: Poisson/log, FP32, n=m=0, d=1, p=q=0, R=10,
@@ -128,7 +139,7 @@ typedef struct gmf_config {
  * tau=0.75, alpha1=0.1, alpha2=0.01, damping=1e-3, eps=1e-8, eta_max=30,
  * bias_mode=0, seed=0, tile_rows=0, skip_block_deviance=0, panel_stride=0,
  * tile_waves=0, eval_overlap=0, allow_missing=0, estimate_phi=0,
- * estimate_alpha=0. */
+ * estimate_alpha=0, compact_counts=1. */
 void gmf_config_default(gmf_config* cfg);
 
 /* Device bytes gmf_init needs for cfg (with_weights != 0 when a weight
@@ -169,6 +180,12 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace,
  * sum_B w D(y, mu) (float64, see gmf_block_deviance).  Asynchronous.
  * Errors: GMF_EINVAL (nsteps < 0), GMF_EDEVICE. */
 int gmf_step(void* ctx, int64_t nsteps);
+
+/* gmf_compact_counts -- 1 if the step tiles and the full deviance of this
+ * context read the 16-bit copy of the counts (cfg.compact_counts, see
+ * there), 0 if they read the float32 counts; GMF_EINVAL for a NULL ctx.
+ * Host only. */
+int gmf_compact_counts(void* ctx);
 
 /* gmf_set_precision -- switch the arithmetic of the following steps and
  * projections (GMF_PREC_FP32 / GMF_PREC_BF16 / GMF_PREC_BF16X3) on the same

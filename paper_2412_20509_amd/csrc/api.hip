@@ -95,7 +95,8 @@ struct Plan {
       o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw, o_bnct, o_devpartial,
       o_scal, o_sumsq, o_post, o_firstnz, o_ro, o_nrows, o_rpw, o_nrr, o_co, o_mcols,
       o_ld, o_nct, o_coP, o_snap, o_devpart2, o_evring, o_alphacol, o_est, o_stats, o_hopart,
-      total;
+      o_Yc, total;
+  bool compact_room = false;   // o_Yc holds room for the 16-bit counts
   int stats_wg = 0, ho_wg = 0;
   int row_chunk = 1, col_chunk = 1, upd_sub = 1, upd_per_step = 1;
 };
@@ -297,6 +298,8 @@ void make_plan(const gmf_config* c, int with_w, Plan& P) {
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   P.o_Yb = take(sizeof(float) * (size_t)P.n * P.LDtot);
   P.o_Wb = take(P.with_w ? sizeof(float) * (size_t)P.n * P.LDtot : 0);
+  P.compact_room = c->compact_counts != 0 && (P.fam == gmf::kPoisson || P.fam == gmf::kNegBin);
+  P.o_Yc = take(P.compact_room ? sizeof(uint16_t) * (size_t)P.n * P.LDtot : 0);
   P.o_Prow = take(sizeof(float) * (size_t)P.n * P.KP);
   P.o_Pcol = take(sizeof(float) * (size_t)P.m * P.KP);
   P.o_Grow = take(sizeof(double) * (size_t)P.n * P.KU);
@@ -387,6 +390,7 @@ struct Ctx {
   int64_t batched_upto = 0;   // last step run by gmf_batch_run (no block deviance)
   int device = 0;             // HIP device of the context
   bool alpha_col = false;     // a per-column NB shape was set (generic path)
+  bool compact = false;       // the 16-bit counts at o_Yc are valid
   double est_init[4] = {1.0, 5.0, 0.0, 0.0};   // starting [phi, alpha] of the estimators
   std::vector<double> init_sv;   // singular values of the residual matrix (last gmf_initialize)
   int want_block_dev = 1;
@@ -463,6 +467,14 @@ int check_flag(Ctx* c) {
   return GMF_OK;
 }
 
+// The 16-bit counts when the context reads them (Poisson or NB on the
+// fixed-shape epilogue, every count in [0, 65535]), else null.
+const uint16_t* compact_counts_of(const Ctx* c) {
+  const Plan& P = c->P;
+  if (!c->compact || !(P.fam == gmf::kPoisson || P.fam == gmf::kNegBin)) return nullptr;
+  return c->at<uint16_t>(P.o_Yc);
+}
+
 gmf::LevelArgs level_args(const Ctx* c) {
   const Plan& P = c->P;
   const gmf_config& cf = c->cfg;
@@ -470,6 +482,7 @@ gmf::LevelArgs level_args(const Ctx* c) {
   std::memset(&a, 0, sizeof(a));
   a.Y = c->at<float>(P.o_Yb);
   a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+  a.Yc = compact_counts_of(c);
   a.Prow = c->at<float>(P.o_Prow);
   a.Pcol = c->at<float>(P.o_Pcol);
   a.Grow = c->at<double>(P.o_Grow);
@@ -662,6 +675,7 @@ gmf::DevArgs dev_args(Ctx* c) {
   gmf::DevArgs a{};
   a.Y = c->at<float>(P.o_Yb);
   a.W = P.with_w ? c->at<float>(P.o_Wb) : nullptr;
+  a.Yc = compact_counts_of(c);
   a.Prow = c->at<float>(P.o_Prow);
   a.Pcol = c->at<float>(P.o_Pcol);
   a.tile_block = c->at<int>(P.o_tileblk);
@@ -810,6 +824,7 @@ void gmf_config_default(gmf_config* c) {
   c->alpha1 = 0.1; c->alpha2 = 0.01;
   c->damping = 1e-3; c->eps = 1e-8; c->eta_max = 30.0;
   c->seed = 0;
+  c->compact_counts = 1;
 }
 
 size_t gmf_workspace_bytes(const gmf_config* cfg, int32_t with_weights) {
@@ -932,6 +947,13 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
                               c->at<int>(P.o_blkld), c->at<float>(P.o_Yb),
                               P.with_w ? c->at<float>(P.o_Wb) : nullptr, c->at<int>(P.o_flag), st,
                               cfg->allow_missing, cfg->family + 1);
+  // the 16-bit copy of the counts; flag[1] is set if a count does not fit
+  int compact_flag = 1;
+  if (e == hipSuccess && P.compact_room)
+    e = gmf::launch_compact_counts(c->at<float>(P.o_Yb), (int64_t)P.n * P.LDtot,
+                                   c->at<uint16_t>(P.o_Yc), c->at<int>(P.o_flag) + 1, st);
+  if (e == hipSuccess && P.compact_room)
+    e = hipMemcpyAsync(&compact_flag, c->at<int>(P.o_flag) + 1, sizeof(int), hipMemcpyDeviceToHost, st);
   c->est_init[0] = cfg->phi;
   c->est_init[1] = cfg->nb_alpha;
   if (e == hipSuccess) e = h2d(P.o_est, c->est_init, sizeof(c->est_init));
@@ -960,6 +982,7 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
     delete c;
     return fail(GMF_EDEVICE, std::string("gmf_init: ") + hipGetErrorString(e));
   }
+  c->compact = P.compact_room && compact_flag == 0;
   int rc = check_flag(c);
   if (rc == GMF_OK)
     rc = count_constants(P.fam, dev_args(c), tileblk, nb, st, c->kblock, c->ktotal);
@@ -969,6 +992,11 @@ int gmf_init(void** ctx_out, const gmf_config* cfg, void* workspace, size_t ws_b
   }
   *ctx_out = c;
   return GMF_OK;
+}
+
+int gmf_compact_counts(void* ctx) {
+  if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
+  return compact_counts_of(as_ctx(ctx)) != nullptr ? 1 : 0;
 }
 
 int gmf_set_precision(void* ctx, int32_t precision) {

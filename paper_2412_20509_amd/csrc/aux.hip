@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "family.hpp"
 #include "gmf_kernels.hpp"
@@ -113,6 +114,23 @@ __global__ void iota_kernel(int* p, int64_t count) {
 hipError_t launch_iota(int* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- 16-bit counts ----
+__global__ void compact_counts_kernel(const float* Yb, int64_t count, uint16_t* Yc, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float y = Yb[i];
+  const bool ok = y >= 0.f && y <= 65535.f && y == floorf(y);   // false for NaN
+  Yc[i] = ok ? (uint16_t)y : (uint16_t)0;
+  if (!ok) atomicOr(flag, 1);
+}
+hipError_t launch_compact_counts(const float* Yb, int64_t count, uint16_t* Yc, int* flag,
+                                 hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_counts_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     Yb, count, Yc, flag);
   return hipGetLastError();
 }
 
@@ -318,10 +336,13 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
 // One workgroup per (block, range of up to 256 rows, strip of 128 columns);
 // each wavefront owns 32 columns and walks the rows in groups of 32 with the
 // next group's counts and panel rows prefetched.  Same 32x32 pieces and MFMA
-// operand layout as the step kernel (float32 products).
-template <int FAM, int KP>
+// operand layout as the step kernel (float32 products).  Rows past the range
+// and columns past the block read the last valid ones (clamped addresses) and
+// are masked out of the sum; groups with none of them skip the mask.
+template <int FAM, int KP, bool HAS_W, bool CY>
 __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float (*sP)[KP + 4],
                                               double* sDev) {
+  using YRaw = typename std::conditional<CY, uint2, float4>::type;   // 4 counts as stored
   const FamilyConst fc = family_const(a.f);
   const int blk = a.tile_block[tile];
   const int local = tile - a.tile_first[blk];
@@ -330,7 +351,8 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
   const int n_ct = a.blk_nct[blk];
   const int rpw = a.blk_rpw[blk];
   const float* Y = a.Y + a.blk_yoff[blk];
-  const float* W = a.W ? a.W + a.blk_yoff[blk] : nullptr;
+  const uint16_t* Yc = CY ? a.Yc + a.blk_yoff[blk] : nullptr;
+  const float* W = HAS_W ? a.W + a.blk_yoff[blk] : nullptr;
   const float* Prow = a.Prow + (int64_t)a.blk_row0[blk] * KP;
   const float* Pcol = a.Pcol + (int64_t)a.blk_col0[blk] * KP;
   const int ct = local % n_ct, rr = local / n_ct;
@@ -338,6 +360,7 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
   const int l16 = lane & 15, g = lane >> 4;
   const int row0 = rr * rpw, row_end = min(n_b, row0 + rpw);
   const int colw = ct * kTileCols + wave * kWaveCols;
+  const int colw_u = __builtin_amdgcn_readfirstlane(colw);   // the same in every lane
 
   constexpr int PF = (kRowGroup * (KP / 4) + kTileThreads - 1) / kTileThreads;
   auto load_p = [&](int rg, float4 (&pf)[PF]) {
@@ -350,17 +373,19 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
       }
     }
   };
-  auto load_y = [&](int rg, float4 (&y)[2][2]) {
+  auto y_offset = [&](int row, int C) {
+    return (int64_t)min(row, row_end - 1) * ldy + min(colw + 16 * C + 4 * g, ldy - 4);
+  };
+  auto load_y = [&](int rg, YRaw (&y)[2][2]) {
     for (int R = 0; R < 2; ++R)
       for (int C = 0; C < 2; ++C) {
-        const int row = rg + 2 * l16 + R;
-        const int colb = colw + 16 * C + 4 * g;
-        y[R][C] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (row < row_end && colb < ldy)
-          y[R][C] = *reinterpret_cast<const float4*>(Y + (int64_t)row * ldy + colb);
+        const int64_t off = y_offset(rg + 2 * l16 + R, C);
+        if constexpr (CY) y[R][C] = *reinterpret_cast<const uint2*>(Yc + off);
+        else y[R][C] = *reinterpret_cast<const float4*>(Y + off);
       }
   };
-  float4 pnext[PF], ynext[2][2];
+  float4 pnext[PF];
+  YRaw ynext[2][2], yalt[2][2];
   load_p(row0, pnext);
   load_y(row0, ynext);
   float pa[2][KP / 4];
@@ -370,10 +395,8 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
       pa[c][kk] = (col < m_b) ? Pcol[(int64_t)col * KP + 4 * kk + g] : 0.f;
   }
   double acc = 0.0;
-  for (int rg = row0; rg < row_end; rg += kRowGroup) {
-    float4 ycur[2][2];
-    for (int R = 0; R < 2; ++R)
-      for (int C = 0; C < 2; ++C) ycur[R][C] = ynext[R][C];
+  // one 32-row group; the count registers alternate between groups
+  auto group = [&](const int rg, const YRaw (&ycur)[2][2], YRaw (&ynxt)[2][2]) {
     __syncthreads();
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * kTileThreads;
@@ -382,37 +405,47 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
     }
     if (rg + kRowGroup < row_end) {
       load_p(rg + kRowGroup, pnext);
-      load_y(rg + kRowGroup, ynext);
+      load_y(rg + kRowGroup, ynxt);
     }
     __syncthreads();
+    const bool full = rg + kRowGroup <= row_end && colw_u + kWaveCols <= m_b;
     float grp = 0.f;
     for (int R = 0; R < 2; ++R) {
       const int lrow = 2 * l16 + R;
       const int row = rg + lrow;
       for (int C = 0; C < 2; ++C) {
-        // every lane takes part in the MFMA; masking happens afterwards
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
         for (int kk = 0; kk < KP / 4; ++kk)
           e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], sP[lrow][4 * kk + g], e, 0, 0, 0);
         const int colb = colw + 16 * C + 4 * g;
-        float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (W && row < row_end && colb < ldy)
-          w4 = *reinterpret_cast<const float4*>(W + (int64_t)row * ldy + colb);
-        const float ys[4] = {ycur[R][C].x, ycur[R][C].y, ycur[R][C].z, ycur[R][C].w};
+        float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);   // a literal 1 without weights
+        if constexpr (HAS_W) w4 = *reinterpret_cast<const float4*>(W + y_offset(row, C));
+        const float4 y4 = counts_f4(ycur[R][C]);
+        const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
-        for (int v = 0; v < 4; ++v) {
-          float x1, x2, dv = 0.f;
-          if constexpr (FAM == kGeneric) {
-            const float av = column_alpha(fc, a.blk_col0[blk] + min(colb + v, m_b - 1));
-            family_entry_generic<true>(e[v], ys[v], ws[v], av, fc, x1, x2, dv);
-          } else {
-            family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+        auto entries = [&](auto masked) {
+          for (int v = 0; v < 4; ++v) {
+            float x1, x2, dv = 0.f;
+            if constexpr (FAM == kGeneric) {
+              const float av = column_alpha(fc, a.blk_col0[blk] + min(colb + v, m_b - 1));
+              family_entry_generic<true>(e[v], ys[v], ws[v], av, fc, x1, x2, dv);
+            } else {
+              family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+            }
+            if constexpr (decltype(masked)::value) grp += (row < row_end && colb + v < m_b) ? dv : 0.f;
+            else grp += dv;
           }
-          grp += (row < row_end && colb + v < m_b) ? dv : 0.f;
-        }
+        };
+        if (full) entries(std::false_type{});
+        else entries(std::true_type{});
       }
     }
     acc += (double)grp;
+  };
+  for (int rg = row0; rg < row_end; rg += 2 * kRowGroup) {
+    group(rg, ynext, yalt);
+    if (rg + kRowGroup >= row_end) break;
+    group(rg + kRowGroup, yalt, ynext);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) sDev[wave] = acc;
@@ -422,14 +455,31 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
 
 // One workgroup per tile, or (grid_cap) fewer workgroups walking the tiles:
 // a capped grid leaves compute units to work running beside it.
-template <int FAM, int KP>
+template <int FAM, int KP, bool HAS_W, bool CY>
 __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
   __shared__ float sP[kRowGroup][KP + 4];
   __shared__ double sDev[kTileWaves];
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-    deviance_tile<FAM, KP>(a, tile, sP, sDev);
+    // the strips of a row range on one XCD (with a grid of a multiple of 8)
+    deviance_tile<FAM, KP, HAS_W, CY>(a, xcd_tile(tile, a.n_tiles), sP, sDev);
     __syncthreads();   // sP and sDev are reused by the next tile
   }
+}
+
+template <int FAM, int KP, bool HAS_W>
+static void launch_dev_y(const DevArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+  if constexpr (FAM == kPoisson || FAM == kNegBin)
+    if (a.Yc) {
+      hipLaunchKernelGGL((deviance_kernel<FAM, KP, HAS_W, true>), grid, block, 0, s, a);
+      return;
+    }
+  hipLaunchKernelGGL((deviance_kernel<FAM, KP, HAS_W, false>), grid, block, 0, s, a);
+}
+
+template <int FAM, int KP>
+static void launch_dev_w(const DevArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+  if (a.W) launch_dev_y<FAM, KP, true>(a, grid, block, s);
+  else launch_dev_y<FAM, KP, false>(a, grid, block, s);
 }
 
 template <int FAM>
@@ -437,10 +487,10 @@ static hipError_t launch_dev_kp(int KP, const DevArgs& a, hipStream_t s) {
   if (a.n_tiles <= 0) return hipSuccess;
   const dim3 grid(a.grid_cap > 0 ? std::min(a.n_tiles, a.grid_cap) : a.n_tiles), block(kTileThreads);
   switch (KP) {
-    case 16: hipLaunchKernelGGL((deviance_kernel<FAM, 16>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((deviance_kernel<FAM, 32>), grid, block, 0, s, a); break;
-    case 48: hipLaunchKernelGGL((deviance_kernel<FAM, 48>), grid, block, 0, s, a); break;
-    case 64: hipLaunchKernelGGL((deviance_kernel<FAM, 64>), grid, block, 0, s, a); break;
+    case 16: launch_dev_w<FAM, 16>(a, grid, block, s); break;
+    case 32: launch_dev_w<FAM, 32>(a, grid, block, s); break;
+    case 48: launch_dev_w<FAM, 48>(a, grid, block, s); break;
+    case 64: launch_dev_w<FAM, 64>(a, grid, block, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -22,9 +22,12 @@
 //   with c(0) = 0.  The per-entry epilogue forms only the mu part ("dev" below);
 //   sums of w c(y) over a block never change during a fit, so they are formed
 //   once, in float64, and added to the block and full deviances.
-//   log1p(mu/a) is log(q) for the rounded q = 1 + mu/a plus the correction
-//   for that rounding, which keeps full relative accuracy for small mu/a (the
-//   zero counts); 1/q = a/(a + mu) reuses the reciprocal of the Fisher weight.
+//   In the NB step epilogue log1p(mu/a) is log2 of q = 1 + mu/a rounded
+//   once (a fused multiply-add), and the mu part is formed in base-2 units,
+//   (y+a) log2(q) - y t with t = eta log2(e) (the exponent of mu), times ln 2:
+//   the rounding of q costs at most 2^-24 absolute in log(q), unbiased, so
+//   per entry at most (y + a) 2^-24 of the deviance.  The generic path keeps
+//   the correction for that rounding (log1p_pos).
 //
 // Arithmetic: the hardware exp2 / log2 / reciprocal instructions (1-ulp
 // class, no denormal range reduction: every argument here is a normal number),
@@ -228,8 +231,13 @@ __device__ __forceinline__ float unit_deviance_code(int code, float y, float mu,
 // eta: linear predictor, y: response, w: weight (1 when there are none).
 // dev (WANT_DEV): the mu part of the unit deviance times w -- the full unit
 // deviance for the Gaussian family, 2 w [D/2 - c(y)] for Poisson and NB
-// (HALF: without that factor 2, which the caller applies to its float sum;
-// doubling is exact, so both give the same sums).
+// (HALF: divided by dev_unit<FAM>(), which the caller applies to its sum:
+// 2 for Poisson, 2 ln 2 for NB, whose entries are then in base-2 units).
+template <int FAM>
+__host__ __device__ constexpr double dev_unit() {
+  return FAM == kGaussian ? 1.0 : (FAM == kNegBin ? 2.0 * 0.6931471805599453 : 2.0);
+}
+
 template <int FAM, bool WANT_DEV, bool HALF = false>
 __device__ __forceinline__ void family_entry(float eta, float y, float w, const FamilyConst& c,
                                              float& d1, float& d2, float& dev) {
@@ -241,7 +249,8 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
     if constexpr (WANT_DEV) dev = w * r * r;
   } else {
     const float ec = __builtin_amdgcn_fmed3f(eta, c.lo, c.hi);   // clamp to [lo, hi]
-    const float mu = fast_exp(ec);
+    const float t = ec * 1.4426950408889634f;                      // eta log2(e)
+    const float mu = __builtin_amdgcn_exp2f(t);
     if constexpr (FAM == kPoisson) {
       const float wp = w * c.phi_inv;
       d1 = wp * (mu - y);
@@ -250,13 +259,15 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
         dev = (HALF ? 1.f : 2.f) * w * fmaf(-y, ec, mu);
       }
     } else {
-      const float s = c.a + mu;
-      const float inv = __builtin_amdgcn_rcpf(s);
+      const float inv = __builtin_amdgcn_rcpf(c.a + mu);
       const float wa = w * c.a_phi * inv;
-      d1 = wa * (mu - y);
       d2 = wa * mu;
+      d1 = fmaf(-wa, y, d2);
       if constexpr (WANT_DEV) {
-        dev = (HALF ? 1.f : 2.f) * w * fmaf(y + c.a, log1p_pos(mu * c.inv_a, c.a * inv), -y * ec);
+        const float l2 = __builtin_amdgcn_logf(fmaf(mu, c.inv_a, 1.0f));   // log2(1 + mu/a)
+        const float dh2 = fmaf(y + c.a, l2, -y * t);   // the mu part / ln 2
+        if constexpr (HALF) dev = w * dh2;
+        else dev = (2.0f * 0.6931471805599453f) * w * dh2;
       }
     }
   }

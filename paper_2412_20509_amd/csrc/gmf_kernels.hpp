@@ -19,6 +19,28 @@ constexpr int kWaveCols = 32;
 constexpr int kTileCols = kWaveCols * kTileWaves;
 constexpr int kRowGroup = 32;
 
+// Four counts as float32: from a float4 of the float32 layout or from the four
+// 16-bit integers (uint2) of the compact one (exact: every count <= 65535).
+__device__ __forceinline__ float4 counts_f4(const float4& y) { return y; }
+__device__ __forceinline__ float4 counts_f4(const uint2& u) {
+  return make_float4((float)(u.x & 0xffffu), (float)(u.x >> 16), (float)(u.y & 0xffffu),
+                     (float)(u.y >> 16));
+}
+
+// Workgroups of a launch are dealt to the eight XCDs in turn (workgroup b to
+// XCD b mod 8), each XCD with its own L2.  xcd_tile(b, n) renumbers the n
+// tiles of a launch so that every XCD takes one contiguous range of them:
+// XCD x takes tiles [x q + min(x, r), ..) with q = n / 8, r = n mod 8 (q + 1
+// tiles when x < r), in dispatch order.  Tiles that share panel rows (the
+// column strips of one row range) then run on one XCD and read those rows
+// from its L2 once.  A bijection of [0, n) for every n.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_tile(int b, int n) {
+  const int x = b % kXcds, k = b / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Kernel family selector: three fast paths (complete data, fixed dispersion)
 // and kGeneric, whose epilogue switches at run time on FamilyArgs::code over
 // the six families of Supplementary Table 1 (codes as GMF_POISSON ..
@@ -82,6 +104,7 @@ constexpr int kMaxLevelSteps = 32;   // tile steps + update steps per launch
 struct LevelArgs {
   // data in the workspace (permuted, block-major)
   const float* Y; const float* W;
+  const uint16_t* Yc;  // the counts as 16-bit integers (same layout), or null: read Y
   float* Prow; float* Pcol;
   double* Grow; double* Hrow; double* Gcol; double* Hcol;
   int64_t LDtot;
@@ -169,6 +192,7 @@ hipError_t launch_project_step(int prec, int fam, int KP, const ProjStepArgs& a,
 
 struct DevArgs {
   const float* Y; const float* W;
+  const uint16_t* Yc;          // 16-bit copy of the counts, or null: read Y
   const float* Prow; const float* Pcol;
   const int* tile_block;       // tile -> block id
   const int* tile_first;       // block id -> first tile id
@@ -182,6 +206,11 @@ struct DevArgs {
   int grid_cap;                // deviance: at most this many workgroups (0 = one per tile)
 };
 hipError_t launch_deviance(int fam, int KP, const DevArgs& a, hipStream_t s);
+// Yc[i] = Yb[i] for the count elements of the block-major layout; sets
+// *flag = 1 if any of them is not an integer in [0, 65535] (then Yc is not
+// to be used).
+hipError_t launch_compact_counts(const float* Yb, int64_t count, uint16_t* Yc, int* flag,
+                                 hipStream_t s);
 
 // Per-row deviance (aux.hip).  Yb, Wb: block-major counts and weights (Wb may
 // be null); rowblk, rowloc: caller row i -> row block and row inside it; ro:

@@ -89,6 +89,7 @@ struct TileLds {
 // One tile's inputs.
 struct TileView {
   const float* Y; const float* W;  // block base, row stride ldy
+  const uint16_t* Yc;              // the counts as 16-bit integers (CY tiles), same layout
   const float* Prow;               // rows of I_r
   const float* Pcol;               // rows of J_s
   int ldy, n_b, m_b;
@@ -100,9 +101,10 @@ struct TileView {
   const float* alpha;              // generic path: NB shape of the block's columns, or null
 };
 
-template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool HAS_W>
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool HAS_W, bool CY>
 __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p, int q, int d,
                                int KU, int KV, TileLds<PREC, KP, NW>& L) {
+  using YRaw = typename std::conditional<CY, uint2, float4>::type;   // 4 counts as stored
   constexpr int NB = KP / 16;
   constexpr int TS = TStride<PREC>::v;
   constexpr int NT = kWave * NW;          // threads
@@ -121,6 +123,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   const int l16 = lane & 15;
   const int g = lane >> 4;
   const int colw = tv.col0 + cg * kWaveCols;
+  const int colw_u = __builtin_amdgcn_readfirstlane(colw);   // the same in every lane
   TE (*sT)[kWaveCols][TS] = reinterpret_cast<TE (*)[kWaveCols][TS]>(L.gbuf[cg]);
   float (*sUw)[2 * KP + 1] = (NW == 8)
       ? reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? wave : 0])
@@ -208,12 +211,13 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   // last valid ones instead of zero-filled: those entries meet zero panel
   // operands in every contraction and are masked out of the deviance, so any
   // finite count serves.
-  auto load_y = [&](int rg, float4 (&y)[NR][2]) {
+  auto load_y = [&](int rg, YRaw (&y)[NR][2]) {
     for (int rr = 0; rr < NR; ++rr) {
       const int row = min(rg + 2 * l16 + R0 + rr, tv.row_end - 1);
       for (int C = 0; C < 2; ++C) {
         const int colb = min(colw + 16 * C + 4 * g, tv.ldy - 4);
-        y[rr][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
+        if constexpr (CY) y[rr][C] = *reinterpret_cast<const uint2*>(tv.Yc + (int64_t)row * tv.ldy + colb);
+        else y[rr][C] = *reinterpret_cast<const float4*>(tv.Y + (int64_t)row * tv.ldy + colb);
       }
     }
   };
@@ -238,7 +242,7 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   const bool s_on = s_r0 < s_rows;
   const int s_src = (s_oo < KU) ? (p + s_oo) : (KP + p + (s_oo - KU));
 
-  float4 ynext[NR][2];
+  YRaw ynext[NR][2];
   float4 pnext[PF];
   load_p(tv.row0, pnext);
   load_y(tv.row0, ynext);
@@ -246,12 +250,12 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     // operands in registers: force the loads to complete before stamping
     float acc0 = 0.f;
     if constexpr (PREC == kF32) acc0 = pa32[0][0] + ub32[0][0][0];
-    acc0 += ynext[0][0].x + pnext[0].x;
+    acc0 += counts_f4(ynext[0][0]).x + pnext[0].x;
     tv.stamps[0] = wall_clock64() + (acc0 == 12345.678f ? 1 : 0);
   }
 
   for (int rg = tv.row0; rg < tv.row_end; rg += kRowGroup) {
-    float4 ycur[NR][2];
+    YRaw ycur[NR][2];
     for (int rr = 0; rr < NR; ++rr)
       for (int C = 0; C < 2; ++C) ycur[rr][C] = ynext[rr][C];
     __syncthreads();   // previous group's readers of sP and of the buffers are done
@@ -288,6 +292,8 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
     __syncthreads();
     float dev_grp = 0.f;
+    // every row and column of this wavefront's part of the group in the block
+    const bool grp_full = rg + kRowGroup <= tv.row_end && colw_u + kWaveCols <= tv.m_b;
 
     // ---- per 16-row sub-tile R: eta, epilogue, transpose store, U-side sums
     floatx4 ug[NR][NB], uh[NR][NB];
@@ -324,22 +330,32 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         if constexpr (HAS_W)   // clamped like the counts
           w4 = *reinterpret_cast<const float4*>(tv.W + (int64_t)min(row, tv.row_end - 1) * tv.ldy +
                                                 min(colb, tv.ldy - 4));
-        const float ys[4] = {ycur[rr][C].x, ycur[rr][C].y, ycur[rr][C].z, ycur[rr][C].w};
+        const float4 y4 = counts_f4(ycur[rr][C]);
+        const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
         // Entries outside the block (rows past the tile end, padded columns)
         // need no masking in D1/D2: every contraction meets them with a zero
         // operand (zero-filled panel rows, zero column operands), and their
         // eta, mu, D1, D2 are finite.  Only the deviance sum is masked.
-        for (int v = 0; v < 4; ++v) {
-          float dv = 0.f;
-          if constexpr (FAM == kGeneric) {
-            const float av = tv.alpha ? tv.alpha[min(colb + v, tv.m_b - 1)] : fc.a;
-            family_entry_generic<WANT_DEV, true>(e[v], ys[v], ws[v], av, fc, d1[C][v], d2[C][v], dv);
-          } else {
-            family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+        // (the mask only where the wavefront's rows or columns reach past the
+        // block: a branch uniform over the wavefront)
+        auto entries = [&](auto masked) {
+          for (int v = 0; v < 4; ++v) {
+            float dv = 0.f;
+            if constexpr (FAM == kGeneric) {
+              const float av = tv.alpha ? tv.alpha[min(colb + v, tv.m_b - 1)] : fc.a;
+              family_entry_generic<WANT_DEV, true>(e[v], ys[v], ws[v], av, fc, d1[C][v], d2[C][v], dv);
+            } else {
+              family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
+            }
+            if constexpr (WANT_DEV) {
+              if constexpr (decltype(masked)::value) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
+              else dev_grp += dv;
+            }
           }
-          if constexpr (WANT_DEV) dev_grp += (row_ok && colb + v < tv.m_b) ? dv : 0.f;
-        }
+        };
+        if (grp_full) entries(std::false_type{});
+        else entries(std::true_type{});
       }
       // the deviance is formed here, not deferred past the contractions (the
       // per-entry values would stay live and cost registers)
@@ -405,8 +421,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     }
     __syncthreads();   // the column group's transposed rows are complete
 
-    // the Poisson and NB entries left out the deviance's factor 2
-    if constexpr (WANT_DEV) dev_acc += (FAM == kGaussian ? 1.0 : 2.0) * (double)dev_grp;
+    // the Poisson and NB entries left out the deviance's factor 2 (NB: 2 ln 2,
+    // its entries are in base-2 units)
+    if constexpr (WANT_DEV) dev_acc += dev_unit<FAM>() * (double)dev_grp;
     if (tv.stamps && tid == 0 && rg == tv.row0) tv.stamps[1] = wall_clock64();
     // ---- V side: G_V[col][o] += sum_row D1[row][col] P[row][o]
     for (int cc = 0; cc < NC; ++cc) {
@@ -682,7 +699,7 @@ union LevelLds {
 // One task of a level launch: tile `local` of step `st` (tile_task) or update
 // workgroup `local` of step `st`.  Returns the task kind (0 tile, 1 row
 // update, 2 column update, 3 block deviance, -1 nothing to do).
-template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool CY = false>
 __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st, bool tile_task,
                                         int local, LevelLds<PREC, KP, NW>& L,
                                         unsigned long long* stamps) {
@@ -694,6 +711,7 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     TileView tv;
     tv.ldy = st.ldy;
     tv.Y = a.Y + st.yoff;
+    tv.Yc = CY ? a.Yc + st.yoff : nullptr;
     tv.W = a.W ? a.W + st.yoff : nullptr;
     tv.Prow = a.Prow + (int64_t)st.ro * a.KP;
     tv.Pcol = a.Pcol + (int64_t)st.co * a.KP;
@@ -708,8 +726,8 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
     tv.alpha = a.f.alpha_col ? a.f.alpha_col + st.co : nullptr;
     const FamilyConst fc = family_const(a.f);
     const double dev =
-        tv.W ? compute_tile<PREC, FAM, KP, WANT_DEV, NW, true>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile)
-             : compute_tile<PREC, FAM, KP, WANT_DEV, NW, false>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
+        tv.W ? compute_tile<PREC, FAM, KP, WANT_DEV, NW, true, CY>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile)
+             : compute_tile<PREC, FAM, KP, WANT_DEV, NW, false, CY>(tv, fc, a.p, a.q, a.d, a.KU, a.KV, L.tile);
     if (WANT_DEV && threadIdx.x == 0)
       a.devpart[(int64_t)st.slot * a.slot_dev_elems + rr * n_ct + ct] = dev;
     return 0;
@@ -719,8 +737,9 @@ __device__ __forceinline__ int run_task(const LevelArgs& a, const LevelStep& st,
 
 // Occupancy: two 4-wavefront tiles per compute unit, three for the bfloat16
 // tile at panel stride 32 (168 registers, a few spilled outside the row-group
-// loop; 29.8 against 34.4 us per 10000 x 1000 step with two).
-template <int PREC, int FAM, int KP, bool WANT_DEV, int NW>
+// loop; 29.8 against 34.4 us per 10000 x 1000 step with two).  CY: the tiles
+// read the 16-bit counts.
+template <int PREC, int FAM, int KP, bool WANT_DEV, int NW, bool CY>
 __global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : ((PREC == kBF16 && KP == 32) ? 3 : 2)) void level_kernel(LevelArgs a) {
   __shared__ LevelLds<PREC, KP, NW> L;
   const unsigned long long tr0 = a.trace ? wall_clock64() : 0;
@@ -730,14 +749,15 @@ __global__ __launch_bounds__(kWave * NW, (NW == 8) ? 1 : ((PREC == kBF16 && KP =
   int b = blockIdx.x;
   int kind;
   if (b < ntile_blocks) {
-    kind = run_task<PREC, FAM, KP, WANT_DEV, NW>(a, a.steps[b / T], true, b % T, L,
-                                                 a.trace ? stamps : nullptr);
+    const int v = xcd_tile(b, ntile_blocks);   // the strips of a row range on one XCD
+    kind = run_task<PREC, FAM, KP, WANT_DEV, NW, CY>(a, a.steps[v / T], true, v % T, L,
+                                                     a.trace ? stamps : nullptr);
   } else {
     b -= ntile_blocks;
     const int k = b / a.upd_per_step;
     if (k >= a.n_upd_steps) return;
-    kind = run_task<PREC, FAM, KP, WANT_DEV, NW>(a, a.steps[a.n_tile_steps + k], false,
-                                                 b % a.upd_per_step, L, nullptr);
+    kind = run_task<PREC, FAM, KP, WANT_DEV, NW, CY>(a, a.steps[a.n_tile_steps + k], false,
+                                                     b % a.upd_per_step, L, nullptr);
   }
   if (kind < 0) return;
   if (a.trace && threadIdx.x == 0) {
@@ -823,47 +843,54 @@ constexpr bool has_nw8() {
   return (PREC == kF32 && (KP == 16 || KP == 32)) || (PREC != kF32 && KP == 32);
 }
 
+// cy: the 16-bit counts (Poisson and NB, bfloat16 products, 4-wavefront
+// tiles; the others read the float32 counts: the FP32 tile is bound by its
+// float32 products, and the conversion of the counts cost it 1 %).
 template <int PREC, int FAM, int KP>
-static const void* kernel_ptr(bool want_dev, int nw) {
+static const void* kernel_ptr(bool want_dev, int nw, bool cy) {
   if constexpr (has_nw8<PREC, KP>())
     if (nw == 8)
-      return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 8>)
-                      : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 8>);
+      return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 8, false>)
+                      : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 8, false>);
   if (nw != 4) return nullptr;
-  return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 4>)
-                  : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 4>);
+  if constexpr ((FAM == kPoisson || FAM == kNegBin) && PREC != kF32)
+    if (cy)
+      return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 4, true>)
+                      : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 4, true>);
+  return want_dev ? reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, true, 4, false>)
+                  : reinterpret_cast<const void*>(&level_kernel<PREC, FAM, KP, false, 4, false>);
 }
 
 template <int PREC, int FAM>
-static const void* kernel_ptr_kp(int KP, bool want_dev, int nw) {
+static const void* kernel_ptr_kp(int KP, bool want_dev, int nw, bool cy) {
   switch (KP) {
-    case 16: return kernel_ptr<PREC, FAM, 16>(want_dev, nw);
-    case 32: return kernel_ptr<PREC, FAM, 32>(want_dev, nw);
-    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(want_dev, nw); else break;
-    case 64: return kernel_ptr<PREC, FAM, 64>(want_dev, nw);
+    case 16: return kernel_ptr<PREC, FAM, 16>(want_dev, nw, cy);
+    case 32: return kernel_ptr<PREC, FAM, 32>(want_dev, nw, cy);
+    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(want_dev, nw, cy); else break;
+    case 64: return kernel_ptr<PREC, FAM, 64>(want_dev, nw, cy);
   }
   return nullptr;
 }
 
-static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev, int nw) {
+static const void* level_kernel_for(int prec, int fam, int KP, bool want_dev, int nw, bool cy) {
   if (prec == kF32) {
     switch (fam) {
-      case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev, nw);
-      case kNegBin: return kernel_ptr_kp<kF32, kNegBin>(KP, want_dev, nw);
-      case kGaussian: return kernel_ptr_kp<kF32, kGaussian>(KP, want_dev, nw);
-      case kGeneric: return kernel_ptr_kp<kF32, kGeneric>(KP, want_dev, nw);
+      case kPoisson: return kernel_ptr_kp<kF32, kPoisson>(KP, want_dev, nw, cy);
+      case kNegBin: return kernel_ptr_kp<kF32, kNegBin>(KP, want_dev, nw, cy);
+      case kGaussian: return kernel_ptr_kp<kF32, kGaussian>(KP, want_dev, nw, cy);
+      case kGeneric: return kernel_ptr_kp<kF32, kGeneric>(KP, want_dev, nw, cy);
     }
   } else if (prec == kBF16) {
     switch (fam) {
-      case kPoisson: return kernel_ptr_kp<kBF16, kPoisson>(KP, want_dev, nw);
-      case kNegBin: return kernel_ptr_kp<kBF16, kNegBin>(KP, want_dev, nw);
-      case kGaussian: return kernel_ptr_kp<kBF16, kGaussian>(KP, want_dev, nw);
+      case kPoisson: return kernel_ptr_kp<kBF16, kPoisson>(KP, want_dev, nw, cy);
+      case kNegBin: return kernel_ptr_kp<kBF16, kNegBin>(KP, want_dev, nw, cy);
+      case kGaussian: return kernel_ptr_kp<kBF16, kGaussian>(KP, want_dev, nw, cy);
     }
   } else if (prec == kBF16X3) {
     switch (fam) {
-      case kPoisson: return kernel_ptr_kp<kBF16X3, kPoisson>(KP, want_dev, nw);
-      case kNegBin: return kernel_ptr_kp<kBF16X3, kNegBin>(KP, want_dev, nw);
-      case kGaussian: return kernel_ptr_kp<kBF16X3, kGaussian>(KP, want_dev, nw);
+      case kPoisson: return kernel_ptr_kp<kBF16X3, kPoisson>(KP, want_dev, nw, cy);
+      case kNegBin: return kernel_ptr_kp<kBF16X3, kNegBin>(KP, want_dev, nw, cy);
+      case kGaussian: return kernel_ptr_kp<kBF16X3, kGaussian>(KP, want_dev, nw, cy);
     }
   }
   return nullptr;
@@ -885,7 +912,7 @@ hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const 
       return hipExtLaunchKernel(uk, dim3(grid), dim3(kTileThreads), uargs, 0, s, ev_start, ev_stop, 0);
     return hipLaunchKernel(uk, dim3(grid), dim3(kTileThreads), uargs, 0, s);
   }
-  const void* k = level_kernel_for(prec, fam, KP, want_dev, nw);
+  const void* k = level_kernel_for(prec, fam, KP, want_dev, nw, a.Yc != nullptr);
   if (!k) return hipErrorInvalidValue;
   if (grid <= 0) return hipSuccess;
   void* args[] = {const_cast<LevelArgs*>(&a)};

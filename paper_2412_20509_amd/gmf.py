@@ -45,6 +45,7 @@ class gmf_config(C.Structure):
         ("tile_rows", C.c_int32), ("skip_block_deviance", C.c_int32),
         ("panel_stride", C.c_int32), ("tile_waves", C.c_int32), ("eval_overlap", C.c_int32),
         ("allow_missing", C.c_int32), ("estimate_phi", C.c_int32), ("estimate_alpha", C.c_int32),
+        ("compact_counts", C.c_int32),
     ]
 
 
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "gmf_deviance": (C.c_int, [vp, f64p, f64p]),
         "gmf_run": (C.c_int, [vp, i32, i32, f64p, f64p]),
         "gmf_set_precision": (C.c_int, [vp, i32]),
+        "gmf_compact_counts": (C.c_int, [vp]),
         "gmf_row_deviance": (C.c_int, [vp, vp]),
         "gmf_block_deviance": (C.c_int, [vp, f64p, i64]),
         "gmf_get_params": (C.c_int, [vp, vp, vp, vp, vp, i32]),
@@ -342,6 +344,7 @@ class FitConfig:
     allow_missing: int = 0
     estimate_phi: int = 0
     estimate_alpha: int = 0
+    compact_counts: int = 1
 
     def to_c(self, n, m, p, q) -> gmf_config:
         c = gmf_config_default()
@@ -366,6 +369,7 @@ class FitConfig:
         c.allow_missing = self.allow_missing
         c.estimate_phi = self.estimate_phi
         c.estimate_alpha = self.estimate_alpha
+        c.compact_counts = self.compact_counts
         return c
 
 
@@ -421,6 +425,15 @@ class GMF:
         """gmf_set_precision: 'fp32', 'bf16' or 'bf16x3' for the following steps
         and projections."""
         _check(load_library().gmf_set_precision(self.ctx, PREC_CODES[precision]))
+
+    @property
+    def compact_counts(self):
+        """gmf_compact_counts: True when the step tiles and the full deviance
+        read the 16-bit copy of the counts."""
+        rc = load_library().gmf_compact_counts(self.ctx)
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def run(self, epochs, eval_every=1, trace=True):
         """gmf_run: epochs with the deviance overlapped every eval_every epochs."""
