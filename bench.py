@@ -28,9 +28,11 @@ Printed JSON line:
   arms              per arm (FP32 plain, BF16, split BF16): epochs/s with and
                     without the per-epoch deviance, s and epochs to 1e-4 of D*,
                     the final distance to D*, the launch statistics
-  roofline          the headline arm's step kernel: algorithmic work of the
-                    timed steps / the summed launch time from HIP events stamped
-                    by the launches themselves on the library's stream.  The
+  roofline          the headline arm's step kernel (the launches that run the
+                    block-step tiles, level_kernel): algorithmic work per
+                    launch (the per-step figure times the steps per launch) /
+                    the mean launch time from HIP events stamped by the
+                    launches themselves on the library's stream.  The
                     bfloat16 arms are rated on bytes against 8 TB/s HBM: 4 B of
                     y per block entry plus the panel and moment traffic
                     2 (|I| (q+d) + |J| (p+d)) (4 + 2 x 8) B per step; the FP32
@@ -180,6 +182,7 @@ def run_arm(pr, precision, epochs, warmup, budget, dstar, torch, polish=0):
     g.set_timing(True)
     for _ in range(2):
         g.step(per_epoch)
+    (tile_ms, tile_launches), (upd_ms, upd_launches) = g.get_timing_by_kind()
     launch_ms, launches, nsteps = g.get_timing()
     g.set_timing(False)
     g.close()
@@ -222,6 +225,8 @@ def run_arm(pr, precision, epochs, warmup, budget, dstar, torch, polish=0):
                 deviance_every_10_epochs=devs[9::10],
                 s_to_1e4=t_hit, epochs_to_1e4=e_hit,
                 launch_ms_total=launch_ms, launches=int(launches), timed_steps=nsteps,
+                tile_launch_ms_total=tile_ms, tile_launches=int(tile_launches),
+                update_launch_ms_total=upd_ms, update_launches=int(upd_launches),
                 postprocess_s=t_pp, compact_counts=compact)
 
 
@@ -261,36 +266,52 @@ def run_init_arm(pr, precision, budget, dstar, torch, power_iters=2, oversample=
 
 
 def roofline_of(pr, arm, precision):
-    """Roofline object of an arm's step kernel (see the module docstring)."""
+    """Roofline object of an arm's step kernel, the dominant kernel: the
+    launches that run the block-step tiles (level_kernel).  Every block entry
+    of the timed steps is processed in those launches, so their algorithmic
+    work per launch is the per-step figure times the steps per tile launch;
+    the launch durations are HIP events stamped by the launches themselves on
+    the library's stream (see the module docstring).  `step_kernels_*` rate
+    the same work over the tile and the update launches together."""
     bf16 = precision != "fp32"
     w = step_work(pr, bf16)
-    launches = max(arm["launches"], 1)
-    t = arm["launch_ms_total"] * 1e-3
     steps = arm["timed_steps"]
+    n_tile = max(arm["tile_launches"], 1)
+    t_tile = arm["tile_launch_ms_total"] * 1e-3
+    t_all = arm["launch_ms_total"] * 1e-3
+    per_launch_bytes = w["bytes"] * steps / n_tile
+    per_launch_flops = w["flops"] * steps / n_tile
+    mean_s = t_tile / n_tile
     if bf16:
-        achieved = steps * w["bytes"] / t / 1e9
+        achieved = per_launch_bytes / mean_s / 1e9
         out = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                   frac=achieved / HBM_PEAK_GBS)
+                   frac=achieved / HBM_PEAK_GBS,
+                   step_kernels_GBs=steps * w["bytes"] / t_all / 1e9)
     else:
-        achieved = steps * w["flops"] / t / 1e12
+        achieved = per_launch_flops / mean_s / 1e12
         out = dict(bound="mfma", achieved=achieved, peak=FP32_PEAK_TFS, unit="TFLOP/s",
-                   frac=achieved / FP32_PEAK_TFS)
+                   frac=achieved / FP32_PEAK_TFS,
+                   step_kernels_TFs=steps * w["flops"] / t_all / 1e12)
     compact = bool(arm.get("compact_counts")) and precision != "fp32"   # FP32 tiles read float32
     traffic = recorded_traffic(pr, precision, compact)
     out.update(traffic=traffic, kernel=step_kernel_name(pr, precision, compact),
                bytes_per_step=w["bytes"], flops_per_step=w["flops"],
+               algorithmic_bytes_per_launch=per_launch_bytes,
+               algorithmic_flops_per_launch=per_launch_flops,
                counts_bytes_per_entry=2 if compact else 4,
-               steps_per_launch=steps / launches, mean_launch_us=1e6 * t / launches,
-               launches=arm["launches"])
+               steps_per_launch=steps / n_tile, mean_launch_us=1e6 * mean_s,
+               launches=int(n_tile), update_launches=arm["update_launches"],
+               mean_update_launch_us=1e6 * arm["update_launch_ms_total"] * 1e-3 /
+               max(arm["update_launches"], 1))
     if compact:
-        # the bytes the kernel has to move with 16-bit counts, against HBM
-        out["stored_GBs"] = steps * w["bytes_stored16"] / t / 1e9
+        # the bytes the tiles have to move with 16-bit counts, against HBM
+        out["stored_GBs"] = w["bytes_stored16"] * steps / n_tile / mean_s / 1e9
         out["stored_frac_hbm"] = out["stored_GBs"] / HBM_PEAK_GBS
     if traffic is not None:
         # the same launch time against the bytes the HBM counters measured
-        out["measured_GBs"] = traffic / (t / launches) / 1e9
+        out["measured_GBs"] = traffic / mean_s / 1e9
         out["measured_frac_hbm"] = out["measured_GBs"] / HBM_PEAK_GBS
-        out["traffic_over_algorithmic"] = traffic / (w["bytes"] * steps / launches)
+        out["traffic_over_algorithmic"] = traffic / per_launch_bytes
     return out
 
 

@@ -397,6 +397,14 @@ int gmf_set_timing(void* ctx, int32_t enable);
 int gmf_get_timing(void* ctx, double* launch_ms_host, double* launches_host,
                    int64_t* steps_host);
 
+/* gmf_get_timing_by_kind -- the same window split by launch kind, without
+ * starting a new one: ms_host[0], launches_host[0] for the launches that run
+ * block-step tiles (the tiles of a level, with any updates that share the
+ * launch: the step kernel), [1] for the update-only launches (the update
+ * kernel).  Both arrays hold 2 doubles.  Synchronises.  Errors: GMF_EINVAL
+ * (NULL argument). */
+int gmf_get_timing_by_kind(void* ctx, double* ms_host, double* launches_host);
+
 /* gmf_project_workspace_bytes -- device bytes gmf_project needs for n_new
  * new rows of the context's shape (0 on error). */
 size_t gmf_project_workspace_bytes(void* ctx, int64_t n_new);

@@ -403,6 +403,7 @@ struct Ctx {
   bool timing = false;
   std::vector<hipEvent_t> events;   // 2 per timed launch
   int64_t timed_launches = 0;
+  std::vector<unsigned char> timed_kind;   // per timed launch: 0 block-step tiles, 1 updates only
   int64_t timed_steps = 0;
   // sums of w c(y), the count-only part of half the unit deviance, per block
   // (r * S + s) and in total (float64; constant during the fit)
@@ -582,6 +583,7 @@ int enqueue_steps_estimating(Ctx* c, int64_t nsteps) {
       hipEvent_t* ev = nullptr;
       if (c->timing && c->timed_launches < kMaxTimedSteps) {
         ev = &c->events[2 * c->timed_launches];
+        c->timed_kind[c->timed_launches] = phase == 0 ? 0 : 1;
         ++c->timed_launches;
       }
       HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, P.nw, a, grid, c->st,
@@ -659,6 +661,7 @@ int enqueue_steps(Ctx* c, int64_t nsteps) {
       hipEvent_t* ev = nullptr;
       if (c->timing && c->timed_launches < kMaxTimedSteps) {
         ev = &c->events[2 * c->timed_launches];
+        c->timed_kind[c->timed_launches] = nt > 0 ? 0 : 1;
         ++c->timed_launches;
       }
       HIP_TRY(gmf::launch_level(P.prec, P.fam, P.KP, want_dev, P.nw, a, grid, c->st,
@@ -1300,7 +1303,9 @@ struct ProjPlan {
   int dev_rpw = 0, dev_tiles = 0;
   size_t o_Yb, o_Prow, o_Pcol, o_Grow, o_Hrow, o_iota, o_zero, o_rowbase,
       o_nrows, o_tileblk, o_tilefirst, o_byoff, o_brow0, o_bcol0, o_bnb, o_bmb, o_bldy, o_brpw,
-      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, o_pcolorig, total;
+      o_bnct, o_devpartial, o_scal, o_tmpB, o_tmpZ, o_tmpV, o_count, o_pcolorig, o_Yc, o_cflag,
+      total;
+  bool compact_room = false;   // room for the new rows' 16-bit counts
 };
 
 bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
@@ -1338,6 +1343,9 @@ bool make_proj_plan(const Ctx* c, int64_t n_new, ProjPlan& Q) {
   Q.o_tmpV = take(sizeof(float) * (size_t)P.m * P.d);
   Q.o_count = take(sizeof(unsigned long long) * 2);
   Q.o_pcolorig = take(sizeof(float) * (size_t)P.m * P.KP);
+  Q.compact_room = P.compact_room;
+  Q.o_Yc = take(Q.compact_room ? sizeof(uint16_t) * (size_t)n_new * P.LDtot : 0);
+  Q.o_cflag = take(sizeof(int));
   Q.total = o;
   return true;
 }
@@ -1418,6 +1426,18 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
                                 reinterpret_cast<int64_t*>(at(Q.o_rowbase)), reinterpret_cast<int*>(at(Q.o_nrows)),
                                 c->at<int64_t>(P.o_blkcoloff), c->at<int>(P.o_blkld), Yb, nullptr,
                                 c->at<int>(P.o_flag), st));
+  // the 16-bit copy of the new counts, used when every count fits
+  const uint16_t* Yc = nullptr;
+  if (Q.compact_room) {
+    int* cflag = reinterpret_cast<int*>(at(Q.o_cflag));
+    uint16_t* Ycw = reinterpret_cast<uint16_t*>(at(Q.o_Yc));
+    HIP_TRY(gmf::launch_fill_i32(cflag, 1, 0, st));
+    HIP_TRY(gmf::launch_compact_counts(Yb, n_new * P.LDtot, Ycw, cflag, st));
+    int h = 1;
+    HIP_TRY(hipMemcpyAsync(&h, cflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h == 0) Yc = Ycw;
+  }
   float* Prow = reinterpret_cast<float*>(at(Q.o_Prow));
   if (init_mode == kInitGiven)
     HIP_TRY(gmf::launch_pack_panel(Xnew, P.p, A0, P.q, U0, P.d, reinterpret_cast<int*>(at(Q.o_iota)),
@@ -1481,7 +1501,7 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
 
   // ---- deviance of the new rows
   gmf::DevArgs da{};
-  da.Y = Yb; da.W = nullptr; da.Prow = Prow; da.Pcol = Pcol;
+  da.Y = Yb; da.W = nullptr; da.Yc = Yc; da.Prow = Prow; da.Pcol = Pcol;
   da.tile_block = reinterpret_cast<int*>(at(Q.o_tileblk));
   da.tile_first = reinterpret_cast<int*>(at(Q.o_tilefirst));
   da.blk_yoff = reinterpret_cast<int64_t*>(at(Q.o_byoff));
@@ -1528,6 +1548,7 @@ int project_impl(Ctx* c, void* ws, size_t ws_bytes, const void* Ynew, int32_t y_
     for (int k = 0; k < P.S; ++k) {
       const int64_t t = (int64_t)e * P.S + k + 1;
       pa.Y = Yb + (int64_t)n_new * P.coP[k];
+      pa.Yc = Yc ? Yc + (int64_t)n_new * P.coP[k] : nullptr;
       pa.ldy = P.ld[k]; pa.m_b = P.mcols[k];
       pa.Pcol = Pcol + (int64_t)P.co[k] * P.KP;
       pa.scale_m = (double)P.m / P.mcols[k];
@@ -1599,10 +1620,26 @@ int gmf_set_timing(void* ctx, int32_t enable) {
   if (!ctx) return fail(GMF_EINVAL, "ctx is NULL");
   Ctx* c = as_ctx(ctx);
   if (enable && c->events.empty()) {
+    c->timed_kind.assign(kMaxTimedSteps, 0);
     c->events.resize(2 * kMaxTimedSteps);
     for (auto& e : c->events) HIP_TRY(hipEventCreate(&e));
   }
   c->timing = enable != 0;
+  return GMF_OK;
+}
+
+int gmf_get_timing_by_kind(void* ctx, double* ms_host, double* launches_host) {
+  if (!ctx || !ms_host || !launches_host) return fail(GMF_EINVAL, "NULL argument");
+  Ctx* c = as_ctx(ctx);
+  HIP_TRY(hipStreamSynchronize(c->st));
+  ms_host[0] = ms_host[1] = 0.0;
+  launches_host[0] = launches_host[1] = 0.0;
+  for (int64_t k = 0; k < c->timed_launches; ++k) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
+    ms_host[c->timed_kind[k]] += ms;
+    launches_host[c->timed_kind[k]] += 1.0;
+  }
   return GMF_OK;
 }
 

@@ -21,6 +21,7 @@
 
 #include "family.hpp"
 #include "gmf_kernels.hpp"
+#include "mfma.hpp"
 
 namespace gmf {
 
@@ -333,15 +334,31 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
 }
 
 // --------------------------------------------------------------- deviance --
+// LDS of a deviance workgroup: the group's row panel, float32 (float32
+// products) or as high and low bfloat16 parts (split products, panel strides
+// that are multiples of 32).
+template <int KP>
+struct DevLds {
+  static constexpr bool SPL = KP % 32 == 0;
+  alignas(16) float sP[SPL ? 1 : kRowGroup][SPL ? 4 : KP + 4];
+  alignas(16) __bf16 sPh[SPL ? kRowGroup : 1][SPL ? KP + 8 : 8];
+  alignas(16) __bf16 sPl[SPL ? kRowGroup : 1][SPL ? KP + 8 : 8];
+  double sDev[kTileWaves];
+};
+
 // One workgroup per (block, range of up to 256 rows, strip of 128 columns);
 // each wavefront owns 32 columns and walks the rows in groups of 32 with the
 // next group's counts and panel rows prefetched.  Same 32x32 pieces and MFMA
-// operand layout as the step kernel (float32 products).  Rows past the range
-// and columns past the block read the last valid ones (clamped addresses) and
-// are masked out of the sum; groups with none of them skip the mask.
+// operand layout as the step kernel.  eta on the matrix cores: at panel
+// strides that are multiples of 32 as split bfloat16 products (each operand
+// x = hi + lo, both bfloat16; hi hi + hi lo + lo hi, float32 accumulation,
+// the products of the split-BF16 step), elsewhere as float32 products.  Rows
+// past the range and columns past the block read the last valid ones
+// (clamped addresses) and are masked out of the sum; groups with none of them
+// skip the mask.
 template <int FAM, int KP, bool HAS_W, bool CY>
-__device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float (*sP)[KP + 4],
-                                              double* sDev) {
+__device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds<KP>& L) {
+  constexpr bool SPL = DevLds<KP>::SPL;
   using YRaw = typename std::conditional<CY, uint2, float4>::type;   // 4 counts as stored
   const FamilyConst fc = family_const(a.f);
   const int blk = a.tile_block[tile];
@@ -388,11 +405,27 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
   YRaw ynext[2][2], yalt[2][2];
   load_p(row0, pnext);
   load_y(row0, ynext);
-  float pa[2][KP / 4];
+  // column operands, fixed over the tile: float32 entries 4kk + g, or the
+  // bfloat16 parts of entries 32kk + 8g .. +7, of column colw + 16c + l16
+  float pa[2][SPL ? 1 : KP / 4];
+  bf16x8 pah[2][SPL ? KP / 32 : 1], pal[2][SPL ? KP / 32 : 1];
   for (int c = 0; c < 2; ++c) {
     const int col = colw + 16 * c + l16;
-    for (int kk = 0; kk < KP / 4; ++kk)
-      pa[c][kk] = (col < m_b) ? Pcol[(int64_t)col * KP + 4 * kk + g] : 0.f;
+    if constexpr (SPL) {
+      for (int kk = 0; kk < KP / 32; ++kk) {
+        floatx8 x = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (col < m_b) {
+          const float4 u = *reinterpret_cast<const float4*>(Pcol + (int64_t)col * KP + 32 * kk + 8 * g);
+          const float4 w = *reinterpret_cast<const float4*>(Pcol + (int64_t)col * KP + 32 * kk + 8 * g + 4);
+          x = floatx8{u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+        }
+        pah[c][kk] = to_bf16(x);
+        pal[c][kk] = lo_bf16(x, pah[c][kk]);
+      }
+    } else {
+      for (int kk = 0; kk < KP / 4; ++kk)
+        pa[c][kk] = (col < m_b) ? Pcol[(int64_t)col * KP + 4 * kk + g] : 0.f;
+    }
   }
   double acc = 0.0;
   // one 32-row group; the count registers alternate between groups
@@ -400,8 +433,18 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
     __syncthreads();
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * kTileThreads;
-      if (idx < kRowGroup * (KP / 4))
-        *reinterpret_cast<float4*>(&sP[idx / (KP / 4)][4 * (idx % (KP / 4))]) = pnext[u];
+      if (idx < kRowGroup * (KP / 4)) {
+        const int r = idx / (KP / 4), c0 = 4 * (idx % (KP / 4));
+        if constexpr (SPL) {
+          const floatx4 x = {pnext[u].x, pnext[u].y, pnext[u].z, pnext[u].w};
+          const bf16x4 h = __builtin_convertvector(x, bf16x4);
+          const bf16x4 l = __builtin_convertvector(x - __builtin_convertvector(h, floatx4), bf16x4);
+          *reinterpret_cast<bf16x4*>(&L.sPh[r][c0]) = h;
+          *reinterpret_cast<bf16x4*>(&L.sPl[r][c0]) = l;
+        } else {
+          *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
+        }
+      }
     }
     if (rg + kRowGroup < row_end) {
       load_p(rg + kRowGroup, pnext);
@@ -415,8 +458,18 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
       const int row = rg + lrow;
       for (int C = 0; C < 2; ++C) {
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < KP / 4; ++kk)
-          e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], sP[lrow][4 * kk + g], e, 0, 0, 0);
+        if constexpr (SPL) {
+          for (int kk = 0; kk < KP / 32; ++kk) {   // the small products first
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&L.sPh[lrow][32 * kk + 8 * g]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&L.sPl[lrow][32 * kk + 8 * g]);
+            e = mfma_bf16(pal[C][kk], bh, e);
+            e = mfma_bf16(pah[C][kk], bl, e);
+            e = mfma_bf16(pah[C][kk], bh, e);
+          }
+        } else {
+          for (int kk = 0; kk < KP / 4; ++kk)
+            e = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[C][kk], L.sP[lrow][4 * kk + g], e, 0, 0, 0);
+        }
         const int colb = colw + 16 * C + 4 * g;
         float4 w4 = make_float4(1.f, 1.f, 1.f, 1.f);   // a literal 1 without weights
         if constexpr (HAS_W) w4 = *reinterpret_cast<const float4*>(W + y_offset(row, C));
@@ -448,21 +501,20 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, float 
     group(rg + kRowGroup, yalt, ynext);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) sDev[wave] = acc;
+  if (lane == 0) L.sDev[wave] = acc;
   __syncthreads();
-  if (tid == 0) a.partial[tile] = ((sDev[0] + sDev[1]) + sDev[2]) + sDev[3];
+  if (tid == 0) a.partial[tile] = ((L.sDev[0] + L.sDev[1]) + L.sDev[2]) + L.sDev[3];
 }
 
 // One workgroup per tile, or (grid_cap) fewer workgroups walking the tiles:
 // a capped grid leaves compute units to work running beside it.
 template <int FAM, int KP, bool HAS_W, bool CY>
 __global__ __launch_bounds__(kTileThreads) void deviance_kernel(DevArgs a) {
-  __shared__ float sP[kRowGroup][KP + 4];
-  __shared__ double sDev[kTileWaves];
+  __shared__ DevLds<KP> L;
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     // the strips of a row range on one XCD (with a grid of a multiple of 8)
-    deviance_tile<FAM, KP, HAS_W, CY>(a, xcd_tile(tile, a.n_tiles), sP, sDev);
-    __syncthreads();   // sP and sDev are reused by the next tile
+    deviance_tile<FAM, KP, HAS_W, CY>(a, xcd_tile(tile, a.n_tiles), L);
+    __syncthreads();   // the LDS is reused by the next tile
   }
 }
 

@@ -178,6 +178,7 @@ bool level_supports_nw8(int prec, int KP);
 // EMAs (n x KU, KU = q + d); scale_m = m / m_b; stepsize = rho_t alpha_t.
 struct ProjStepArgs {
   const float* Y;
+  const uint16_t* Yc;   // the same counts as 16-bit integers, or null: read Y
   int ldy, m_b;
   float* Prow;
   const float* Pcol;

@@ -23,6 +23,8 @@
 // panel stride 16.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "family.hpp"
 #include "gmf_kernels.hpp"
 #include "mfma.hpp"
@@ -45,8 +47,9 @@ __device__ __forceinline__ bf16x4 lo_bf16x4(floatx4 x, bf16x4 hi) {
   return to_bf16x4(x - __builtin_convertvector(hi, floatx4));
 }
 
-// One chunk's loads: column panel rows and counts (float32, converted when used).
-template <int PREC, int KP, int RT>
+// One chunk's loads: column panel rows and counts (float32, or 16-bit
+// integers with CY, converted when used).
+template <int PREC, int KP, int RT, bool CY>
 struct Chunk {
   static constexpr int NB = KP / 16;
   // eta's A operand: column c0 + 16C + l16, panel entries k (FP32: 4kk + g;
@@ -54,12 +57,13 @@ struct Chunk {
   float pa[2][KP / 4];
   // U side B operand: column c0 + 16C + 4g + v, panel entry 16ob + l16
   float ub[2][4][NB];
-  float4 y[RT][2];   // row r0 + 16 rt + l16, columns c0 + 16C + 4g .. +3
+  // row r0 + 16 rt + l16, columns c0 + 16C + 4g .. +3
+  typename std::conditional<CY, uint2, float4>::type y[RT][2];
 };
 
-template <int PREC, int KP, int RT>
+template <int PREC, int KP, int RT, bool CY>
 __device__ __forceinline__ void load_chunk(const ProjStepArgs& a, int c0, int64_t r0,
-                                           int l16, int g, Chunk<PREC, KP, RT>& ch) {
+                                           int l16, int g, Chunk<PREC, KP, RT, CY>& ch) {
   constexpr int NB = KP / 16;
   for (int C = 0; C < 2; ++C) {
     const int col = c0 + 16 * C + l16;
@@ -91,14 +95,20 @@ __device__ __forceinline__ void load_chunk(const ProjStepArgs& a, int c0, int64_
     const int colb = c0 + 16 * C + 4 * g;
     for (int rt = 0; rt < RT; ++rt) {
       const int64_t row = r0 + 16 * rt + l16;
-      ch.y[rt][C] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < a.n && colb < a.ldy)
-        ch.y[rt][C] = *reinterpret_cast<const float4*>(a.Y + row * a.ldy + colb);
+      if constexpr (CY) {
+        ch.y[rt][C] = make_uint2(0u, 0u);
+        if (row < a.n && colb < a.ldy)
+          ch.y[rt][C] = *reinterpret_cast<const uint2*>(a.Yc + row * a.ldy + colb);
+      } else {
+        ch.y[rt][C] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < a.n && colb < a.ldy)
+          ch.y[rt][C] = *reinterpret_cast<const float4*>(a.Y + row * a.ldy + colb);
+      }
     }
   }
 }
 
-template <int PREC, int FAM, int KP, int RT>
+template <int PREC, int FAM, int KP, int RT, bool CY>
 __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjStepArgs a) {
   constexpr int kRows = 16 * RT;   // rows per wavefront
   constexpr int NB = KP / 16;
@@ -145,10 +155,10 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
   for (int rt = 0; rt < RT; ++rt)
     for (int ob = 0; ob < NB; ++ob) ug[rt][ob] = uh[rt][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  Chunk<PREC, KP, RT> cur, nxt{};
-  load_chunk<PREC, KP, RT>(a, 0, r0, l16, g, cur);
+  Chunk<PREC, KP, RT, CY> cur, nxt{};
+  load_chunk<PREC, KP, RT, CY>(a, 0, r0, l16, g, cur);
   for (int c0 = 0; c0 < a.m_b; c0 += kChunk) {
-    if (c0 + kChunk < a.m_b) load_chunk<PREC, KP, RT>(a, c0 + kChunk, r0, l16, g, nxt);
+    if (c0 + kChunk < a.m_b) load_chunk<PREC, KP, RT, CY>(a, c0 + kChunk, r0, l16, g, nxt);
     // the chunk's column operands, converted once for all row tiles
     bf16x8 ah[2][(BF && !K16) ? KP / 32 : 1], al[2][(SPLIT && !K16) ? KP / 32 : 1];
     bf16x8 bh[(BF && !K16) ? NB : 1], bq[(BF && !K16) ? NB : 1], bhl[(SPLIT && !K16) ? NB : 1],
@@ -209,7 +219,8 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
             e = mfma_bf16(ah[C][kk], pb16[rt][kk], e);
           }
         }
-        const float ys[4] = {cur.y[rt][C].x, cur.y[rt][C].y, cur.y[rt][C].z, cur.y[rt][C].w};
+        const float4 y4 = counts_f4(cur.y[rt][C]);
+        const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
         for (int v = 0; v < 4; ++v) {
           float dv;
           family_entry<FAM, false>(e[v], ys[v], 1.f, fc, d1[C][v], d2[C][v], dv);
@@ -289,28 +300,31 @@ __global__ __launch_bounds__(kWave * kWaves, 2) void project_step_kernel(ProjSte
 // 1,000,000 x 2000 projection), one for the larger strides (registers).
 constexpr int rt_of(int prec, int KP) { return (KP <= 32) ? 2 : 1; }
 
+// cy: the 16-bit counts (Poisson and NB only).
 template <int PREC, int FAM, int KP>
-const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&project_step_kernel<PREC, FAM, KP, rt_of(PREC, KP)>);
+const void* kernel_ptr(bool cy) {
+  if constexpr (FAM == kPoisson || FAM == kNegBin)
+    if (cy) return reinterpret_cast<const void*>(&project_step_kernel<PREC, FAM, KP, rt_of(PREC, KP), true>);
+  return reinterpret_cast<const void*>(&project_step_kernel<PREC, FAM, KP, rt_of(PREC, KP), false>);
 }
 
 template <int PREC, int FAM>
-const void* kernel_for_kp(int KP) {
+const void* kernel_for_kp(int KP, bool cy) {
   switch (KP) {
-    case 16: return kernel_ptr<PREC, FAM, 16>();
-    case 32: return kernel_ptr<PREC, FAM, 32>();
-    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(); else break;
-    case 64: return kernel_ptr<PREC, FAM, 64>();
+    case 16: return kernel_ptr<PREC, FAM, 16>(cy);
+    case 32: return kernel_ptr<PREC, FAM, 32>(cy);
+    case 48: if constexpr (PREC == kF32) return kernel_ptr<PREC, FAM, 48>(cy); else break;
+    case 64: return kernel_ptr<PREC, FAM, 64>(cy);
   }
   return nullptr;
 }
 
 template <int PREC>
-const void* kernel_for_fam(int fam, int KP) {
+const void* kernel_for_fam(int fam, int KP, bool cy) {
   switch (fam) {
-    case kPoisson: return kernel_for_kp<PREC, kPoisson>(KP);
-    case kNegBin: return kernel_for_kp<PREC, kNegBin>(KP);
-    case kGaussian: return kernel_for_kp<PREC, kGaussian>(KP);
+    case kPoisson: return kernel_for_kp<PREC, kPoisson>(KP, cy);
+    case kNegBin: return kernel_for_kp<PREC, kNegBin>(KP, cy);
+    case kGaussian: return kernel_for_kp<PREC, kGaussian>(KP, cy);
   }
   return nullptr;
 }
@@ -319,9 +333,10 @@ const void* kernel_for_fam(int fam, int KP) {
 
 hipError_t launch_project_step(int prec, int fam, int KP, const ProjStepArgs& a, hipStream_t s) {
   const void* k = nullptr;
-  if (prec == kF32) k = kernel_for_fam<kF32>(fam, KP);
-  else if (prec == kBF16) k = kernel_for_fam<kBF16>(fam, KP);
-  else if (prec == kBF16X3) k = kernel_for_fam<kBF16X3>(fam, KP);
+  const bool cy = a.Yc != nullptr;
+  if (prec == kF32) k = kernel_for_fam<kF32>(fam, KP, cy);
+  else if (prec == kBF16) k = kernel_for_fam<kBF16>(fam, KP, cy);
+  else if (prec == kBF16X3) k = kernel_for_fam<kBF16X3>(fam, KP, cy);
   if (!k) return hipErrorInvalidValue;
   if (a.n <= 0 || a.m_b <= 0) return hipSuccess;
   const int64_t rows_per_wg = (int64_t)16 * rt_of(prec, KP) * kWaves;

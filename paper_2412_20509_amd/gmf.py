@@ -136,6 +136,7 @@ def load_library(path: str = LIB_PATH):
         "gmf_set_trace": (C.c_int, [vp, vp, i64]),
         "gmf_set_timing": (C.c_int, [vp, i32]),
         "gmf_get_timing": (C.c_int, [vp, f64p, f64p, C.POINTER(i64)]),
+        "gmf_get_timing_by_kind": (C.c_int, [vp, f64p, f64p]),
         "gmf_steps_done": (i64, [vp]),
         "gmf_sync": (C.c_int, [vp]),
         "gmf_destroy": (None, [vp]),
@@ -299,6 +300,14 @@ def gmf_get_timing(ctx):
     a, b, k = C.c_double(), C.c_double(), C.c_int64()
     _check(load_library().gmf_get_timing(ctx, C.byref(a), C.byref(b), C.byref(k)))
     return a.value, b.value, k.value
+
+
+def gmf_get_timing_by_kind(ctx):
+    """((tile-launch ms, tile launches), (update-launch ms, update launches))
+    of the current timing window (not reset)."""
+    ms, n = (C.c_double * 2)(), (C.c_double * 2)()
+    _check(load_library().gmf_get_timing_by_kind(ctx, ms, n))
+    return (ms[0], n[0]), (ms[1], n[1])
 
 
 def gmf_steps_done(ctx) -> int:
@@ -641,6 +650,9 @@ class GMF:
 
     def get_timing(self):
         return gmf_get_timing(self.ctx)
+
+    def get_timing_by_kind(self):
+        return gmf_get_timing_by_kind(self.ctx)
 
     def steps_done(self):
         return gmf_steps_done(self.ctx)

@@ -84,3 +84,21 @@ def test_real_valued_families_keep_float32():
     g = gpu_for(pr, compact_counts=1)
     assert not g.compact_counts
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_projection_with_compact_counts_gives_the_same_bits(precision):
+    from synth import gen_nb_rows
+    pr = gen_nb(n=1200, m=450, d=4, R=2, S=3, seed=1965)
+    Ynew, Xnew, _, _ = gen_nb_rows(pr, 2100, seed=1966)
+    A0 = np.zeros((len(Ynew), pr.q), np.float32)
+    U0 = np.random.default_rng(1967).normal(0.0, 0.1, size=(len(Ynew), pr.d)).astype(np.float32)
+    print(f"[case] projection with compact counts {precision}", flush=True)
+    outs = []
+    for compact in (1, 0):
+        g = gpu_for(pr, precision=precision, compact_counts=compact)
+        g.step(12)
+        A, U, tr = g.project(Ynew, Xnew, A0, U0, 3, frozen=1, trace=True)
+        outs.append([A.cpu().numpy(), U.cpu().numpy(), np.asarray(tr)])
+        g.close()
+    _same(outs[0], outs[1])
