@@ -335,11 +335,11 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out,
 
 // --------------------------------------------------------------- deviance --
 // LDS of a deviance workgroup: the group's row panel, float32 (float32
-// products) or as high and low bfloat16 parts (split products, panel strides
-// that are multiples of 32).
+// products) or as high and low bfloat16 parts (split products: panel
+// strides 16, 32 and 64).
 template <int KP>
 struct DevLds {
-  static constexpr bool SPL = KP % 32 == 0;
+  static constexpr bool SPL = KP == 16 || KP % 32 == 0;
   alignas(16) float sP[SPL ? 1 : kRowGroup][SPL ? 4 : KP + 4];
   alignas(16) __bf16 sPh[SPL ? kRowGroup : 1][SPL ? KP + 8 : 8];
   alignas(16) __bf16 sPl[SPL ? kRowGroup : 1][SPL ? KP + 8 : 8];
@@ -350,15 +350,17 @@ struct DevLds {
 // each wavefront owns 32 columns and walks the rows in groups of 32 with the
 // next group's counts and panel rows prefetched.  Same 32x32 pieces and MFMA
 // operand layout as the step kernel.  eta on the matrix cores: at panel
-// strides that are multiples of 32 as split bfloat16 products (each operand
-// x = hi + lo, both bfloat16; hi hi + hi lo + lo hi, float32 accumulation,
-// the products of the split-BF16 step), elsewhere as float32 products.  Rows
+// strides 16, 32 and 64 as split bfloat16 products (each operand x = hi +
+// lo, both bfloat16; hi hi + hi lo + lo hi, float32 accumulation, the
+// products of the split-BF16 step: 16x16x16 at stride 16, 16x16x32 above),
+// at stride 48 as float32 products.  Rows
 // past the range and columns past the block read the last valid ones
 // (clamped addresses) and are masked out of the sum; groups with none of them
 // skip the mask.
 template <int FAM, int KP, bool HAS_W, bool CY>
 __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds<KP>& L) {
   constexpr bool SPL = DevLds<KP>::SPL;
+  constexpr bool K16 = KP == 16;   // 16x16x16 bfloat16 products
   using YRaw = typename std::conditional<CY, uint2, float4>::type;   // 4 counts as stored
   const FamilyConst fc = family_const(a.f);
   const int blk = a.tile_block[tile];
@@ -408,10 +410,19 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds
   // column operands, fixed over the tile: float32 entries 4kk + g, or the
   // bfloat16 parts of entries 32kk + 8g .. +7, of column colw + 16c + l16
   float pa[2][SPL ? 1 : KP / 4];
-  bf16x8 pah[2][SPL ? KP / 32 : 1], pal[2][SPL ? KP / 32 : 1];
+  bf16x8 pah[2][(SPL && !K16) ? KP / 32 : 1], pal[2][(SPL && !K16) ? KP / 32 : 1];
+  bf16x4 kah[2], kal[2];   // stride 16: entries 4g .. 4g+3
   for (int c = 0; c < 2; ++c) {
     const int col = colw + 16 * c + l16;
-    if constexpr (SPL) {
+    if constexpr (K16) {
+      floatx4 x = {0.f, 0.f, 0.f, 0.f};
+      if (col < m_b) {
+        const float4 u = *reinterpret_cast<const float4*>(Pcol + (int64_t)col * KP + 4 * g);
+        x = floatx4{u.x, u.y, u.z, u.w};
+      }
+      kah[c] = __builtin_convertvector(x, bf16x4);
+      kal[c] = __builtin_convertvector(x - __builtin_convertvector(kah[c], floatx4), bf16x4);
+    } else if constexpr (SPL) {
       for (int kk = 0; kk < KP / 32; ++kk) {
         floatx8 x = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (col < m_b) {
@@ -458,7 +469,13 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds
       const int row = rg + lrow;
       for (int C = 0; C < 2; ++C) {
         floatx4 e = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (SPL) {
+        if constexpr (K16) {   // the small products first
+          const bf16x4 bh = *reinterpret_cast<const bf16x4*>(&L.sPh[lrow][4 * g]);
+          const bf16x4 bl = *reinterpret_cast<const bf16x4*>(&L.sPl[lrow][4 * g]);
+          e = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kal[C], bh, e, 0, 0, 0);
+          e = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kah[C], bl, e, 0, 0, 0);
+          e = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kah[C], bh, e, 0, 0, 0);
+        } else if constexpr (SPL) {
           for (int kk = 0; kk < KP / 32; ++kk) {   // the small products first
             const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&L.sPh[lrow][32 * kk + 8 * g]);
             const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&L.sPl[lrow][32 * kk + 8 * g]);
