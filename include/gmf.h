@@ -464,7 +464,8 @@ int gmf_project_warm(void* ctx, void* ws, size_t ws_bytes, const void* Ynew, int
  * partials) lives in a resident 64 MiB device array of the library, one per
  * device, held until the process ends; its address is taken at gmf_init.
  * Limit: gmf_project_workspace_bytes(ctx, n_new) must be <= 64 MiB (about
- * 8,000 new rows of 2,000 columns), else GMF_EWORKSPACE.  Every call on a
+ * 8,000 new rows of 2,000 columns, about 5,000 when the context keeps the
+ * 16-bit counts), else GMF_EWORKSPACE.  Every call on a
  * device shares that device's array and overwrites it: calls that overlap on
  * one device (several streams or threads) race and must be serialised by the
  * caller.  Arguments, results and the other errors as gmf_project. */
