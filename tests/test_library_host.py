@@ -190,6 +190,7 @@ def test_binding_signatures_match_header(lib):
     ("gmf_project_warm", (None, 0, None, 0, 1, None, None, 1, 1, None, None, None, None, None)),
     ("gmf_batch_run", (1, 1, None)), ("gmf_set_trace", (None, 0)), ("gmf_set_timing", (1,)),
     ("gmf_get_timing", (None, None, None)), ("gmf_sync", ()),
+    ("gmf_get_timing_by_kind", (None, None)), ("gmf_compact_counts", ()),
 ])
 def test_null_handle_is_rejected_without_touching_the_device(lib, name, extra):
     """A NULL context (or batch) handle is an argument error (GMF_EINVAL, with a
