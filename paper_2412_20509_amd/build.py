@@ -32,13 +32,19 @@ def _flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+# Per-source flags.  aux.hip: matrix-core results in vector registers (the
+# full-deviance kernel otherwise accumulates in AGPRs and copies every result
+# out, one instruction per entry of a vector-ALU-bound loop).
+EXTRA_FLAGS = {"aux.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *_flags(), *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

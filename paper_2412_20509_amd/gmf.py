@@ -65,13 +65,17 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libgmf.so (raises if it has not been built)."""
+    """Load libgmf.so (raises if it has not been built).  torch is imported
+    first, so that the library binds to the HIP runtime torch has loaded (the
+    same soname): loaded the other way round, the process would hold two HIP
+    runtimes, and the library's would see no device."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libgmf.so not found at {path}: build it with "
                           f"`python -m paper_2412_20509_amd.build`")
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     cfgp = C.POINTER(gmf_config)
