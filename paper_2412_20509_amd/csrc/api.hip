@@ -2438,6 +2438,7 @@ namespace {
 
 struct BatchLaunch {
   int seg0, nsegs, grid;
+  bool updates_only;   // no tile segment: the update-only kernel
 };
 
 struct Batch {
@@ -2504,7 +2505,7 @@ int enqueue_batch_epoch(Batch* b) {
     ba.steps_per_epoch = b->steps_per_epoch;
     ba.table_epochs = b->table_epochs;
     ba.cursor = b->cursor;
-    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st));
+    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st, l.updates_only));
   }
   HIP_TRY(gmf::launch_advance_cursor(b->cursor, b->st));
   return GMF_OK;
@@ -2540,13 +2541,14 @@ int enqueue_batch_leveled(Batch* b, int ne) {
   b->host_segs.clear();
   std::vector<BatchLaunch> launches;
   for (int lv = 0; lv <= max_level + 1; ++lv) {
-    BatchLaunch l{(int)b->host_segs.size(), 0, 0};
+    BatchLaunch l{(int)b->host_segs.size(), 0, 0, true};
     for (int f = 0; f < nf; ++f)
       if (lv < (int)by_level[f].size())
         for (int idx : by_level[f][lv]) {
           b->host_segs.push_back(gmf::BatchSeg{l.grid, f, 0, idx});
           l.grid += b->tile_wgs[f];
           ++l.nsegs;
+          l.updates_only = false;
         }
     for (int f = 0; f < nf; ++f)
       if (lv >= 1 && lv - 1 < (int)by_level[f].size())
@@ -2568,7 +2570,7 @@ int enqueue_batch_leveled(Batch* b, int ne) {
     ba.steps_per_epoch = 0;      // segments index the table directly
     ba.table_epochs = 1;
     ba.cursor = b->cursor;
-    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st));
+    HIP_TRY(gmf::launch_batch(b->prec, b->KP, ba, l.grid, b->st, l.updates_only));
   }
   return GMF_OK;
 }
@@ -2682,7 +2684,7 @@ extern "C" int gmf_batch_init(void** batch_out, void* const* ctxs, int32_t nfits
   std::vector<gmf::BatchSeg> segs;
   for (int k = 0; k < b->L; ++k)
     for (int kind = 0; kind < 2; ++kind) {
-      BatchLaunch l{(int)segs.size(), 0, 0};
+      BatchLaunch l{(int)segs.size(), 0, 0, kind == 1};
       for (int f = 0; f < nfits; ++f) {
         const Plan& P = b->fits[f]->P;
         if (k >= P.R * P.S) continue;

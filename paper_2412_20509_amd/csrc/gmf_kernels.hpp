@@ -160,7 +160,10 @@ struct BatchArgs {
   const int* cursor;
 };
 
-hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s);
+// updates_only: every segment of the launch is an update segment (kind 1);
+// they then run in a kernel with only the update tasks' LDS.
+hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s,
+                        bool updates_only = false);
 hipError_t launch_advance_cursor(int* cursor, hipStream_t s);
 
 // nw: wavefronts per tile workgroup, 4 or 8 (level_supports_nw8).

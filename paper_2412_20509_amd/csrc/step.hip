@@ -831,6 +831,27 @@ __global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
   }
 }
 
+// A batched launch of update segments only: the same update tasks with only
+// their own LDS (kTileThreads doubles), so that many more of them share a
+// compute unit than when they carry a tile's LDS (as update_kernel for a
+// single fit).  The update tasks do not depend on the precision, family or
+// panel stride of the fit (read at run time), so one kernel serves every
+// batch.
+__global__ __launch_bounds__(kTileThreads) void batch_update_kernel(BatchArgs ba) {
+  __shared__ double sums[kTileThreads];
+  const int b = blockIdx.x;
+  int lo = 0, hi = ba.nsegs - 1;
+  while (lo < hi) {   // last segment with start <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (ba.segs[mid].start <= b) lo = mid; else hi = mid - 1;
+  }
+  const BatchSeg sg = ba.segs[lo];
+  const LevelArgs& a = ba.fits[sg.fit];
+  const int64_t e = (int64_t)(*ba.cursor % ba.table_epochs);
+  const LevelStep& st = ba.steps[e * ba.steps_per_epoch + sg.step_index];
+  run_update<false>(a, st, b - sg.start, sums);
+}
+
 __global__ void advance_cursor_kernel(int* cursor) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cursor[0] = cursor[0] + 1;
 }
@@ -922,8 +943,14 @@ hipError_t launch_level(int prec, int fam, int KP, bool want_dev, int nw, const 
   return hipLaunchKernel(k, dim3(grid), block, args, 0, s);
 }
 
-hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s) {
+hipError_t launch_batch(int prec, int KP, const BatchArgs& a, int grid, hipStream_t s,
+                        bool updates_only) {
   if (grid <= 0) return hipSuccess;
+  if (updates_only) {
+    void* uargs[] = {const_cast<BatchArgs*>(&a)};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&batch_update_kernel), dim3(grid),
+                           dim3(kTileThreads), uargs, 0, s);
+  }
   const void* k = nullptr;
   if (prec == kF32) {
     switch (KP) {
