@@ -662,7 +662,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only_batched:      # the batched-fits section alone (for profiling)
-        print(json.dumps(run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch)))
+        probs = gen_batched(args.batch_fits, args.batch_scale)
+        out = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
+                          problems=probs)
+        out["bf16"] = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
+                                  precision="bf16", solo=False, problems=probs,
+                                  modes=((2, "leveled"),))
+        print(json.dumps(out))
         return
     log("generating the 100000x5000 NB workload (rank 20)")
     pr = make_problem("c3")

@@ -809,7 +809,8 @@ __global__ __launch_bounds__(kTileThreads) void update_kernel(LevelArgs a) {
 template <int PREC, int KP>
 __global__ __launch_bounds__(kTileThreads, 2) void batch_kernel(BatchArgs ba) {
   __shared__ LevelLds<PREC, KP, 4> L;
-  const int b = blockIdx.x;
+  // tiles numbered per XCD: the strips of a row range of one fit's step on one XCD
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = ba.nsegs - 1;
   while (lo < hi) {   // last segment with start <= b
     const int mid = (lo + hi + 1) >> 1;
