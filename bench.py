@@ -294,7 +294,13 @@ def roofline_of(pr, arm, precision):
                    step_kernels_TFs=steps * w["flops"] / t_all / 1e12)
     compact = bool(arm.get("compact_counts")) and precision != "fp32"   # FP32 tiles read float32
     traffic = recorded_traffic(pr, precision, compact)
-    out.update(traffic=traffic, kernel=step_kernel_name(pr, precision, compact),
+    name = step_kernel_name(pr, precision, compact)
+    # launches of at most one tile per compute unit run the 8-wavefront variant
+    stride = int(name.split(", ")[2])
+    nw8 = (precision == "fp32" and stride in (16, 32)) or (precision != "fp32" and stride == 32)
+    variants = [name] + ([name.replace(", 4, true>", ", 8, false>").replace(", 4, false>", ", 8, false>")]
+                         if nw8 else [])
+    out.update(traffic=traffic, kernel=name, kernel_variants=variants,
                bytes_per_step=w["bytes"], flops_per_step=w["flops"],
                algorithmic_bytes_per_launch=per_launch_bytes,
                algorithmic_flops_per_launch=per_launch_flops,
