@@ -69,11 +69,11 @@ struct TileLds {
   static constexpr int U_ROWS = kRowGroup * 4 / NW;
   static constexpr int U_BYTES = U_ROWS * (2 * KP + 1) * 4;
   static constexpr int GB = (NW == 4 && U_BYTES > T_BYTES) ? U_BYTES : T_BYTES;
-  float sP[kRowGroup][KP + 4];
-  // bfloat16 copies of the group's row panel, converted once per group:
-  // row-major (eta operand) and transposed, plain and squared (V-side operand);
-  // with split operands also their low parts
+  // the group's row panel: float32 (the float32 tile's operands) or bfloat16
+  // copies converted once per group: row-major (eta operand) and transposed,
+  // plain and squared (V-side operand); with split operands also their low parts
   static constexpr int PB = (PREC != kF32) ? 1 : 0;
+  float sP[PB ? 1 : kRowGroup][PB ? 4 : KP + 4];
   static constexpr int PL = (PREC == kBF16X3) ? 1 : 0;
   alignas(16) __bf16 sPb[PB ? kRowGroup : 1][PB ? KP + 8 : 8];
   alignas(16) __bf16 sPT[PB ? 2 : 1][PB ? KP : 1][PB ? kRowGroup + 8 : 8];
@@ -258,12 +258,15 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     YRaw ycur[NR][2];
     for (int rr = 0; rr < NR; ++rr)
       for (int C = 0; C < 2; ++C) ycur[rr][C] = ynext[rr][C];
-    __syncthreads();   // previous group's readers of sP and of the buffers are done
+    // No barrier before these stores: every reader of the row-panel buffers
+    // (eta, the V side) of the previous group ran before that group's last
+    // barrier, and after it the waves read only the U-sum buffers, which the
+    // next writes of those (after the barrier below) cannot overtake.
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * NT;
       if (idx < kRowGroup * (KP / 4)) {
         const int r = idx / (KP / 4), c0 = 4 * (idx % (KP / 4));
-        *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
+        if constexpr (!BF) *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
         if constexpr (BF) {
           const floatx4 x = {pnext[u].x, pnext[u].y, pnext[u].z, pnext[u].w};
           const floatx4 x2 = x * x;
@@ -419,7 +422,10 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
         }
       }
     }
-    __syncthreads();   // the column group's transposed rows are complete
+    // the column group's transposed rows are complete: with 4 wavefronts each
+    // writes and reads only its own column group's rows (LDS operations of
+    // one wavefront stay in order); with 8 the two halves of a group meet
+    if constexpr (NW == 8) __syncthreads();
 
     // the Poisson and NB entries left out the deviance's factor 2 (NB: 2 ln 2,
     // its entries are in base-2 units)
