@@ -642,6 +642,9 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="factor on n and m of every batched fit")
     ap.add_argument("--batch-epochs", type=int, default=5)
+    ap.add_argument("--batch-tile-rows", type=int, default=128,
+                    help="rows per tile of the batched fits (0: the library's rule, "
+                         "-1: the autotuner's table, tuned on the first fit of each shape class)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched-fits section and print its result")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -670,10 +673,10 @@ def main():
     if args.only_batched:      # the batched-fits section alone (for profiling)
         probs = gen_batched(args.batch_fits, args.batch_scale)
         out = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
-                          problems=probs)
+                          tile_rows=args.batch_tile_rows, problems=probs)
         out["bf16"] = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
-                                  precision="bf16", solo=False, problems=probs,
-                                  modes=((2, "leveled"),))
+                                  tile_rows=args.batch_tile_rows, precision="bf16", solo=False,
+                                  problems=probs, modes=((2, "leveled"),))
         print(json.dumps(out))
         return
     log("generating the 100000x5000 NB workload (rank 20)")
@@ -725,10 +728,10 @@ def main():
     if not args.no_batched:
         probs = gen_batched(args.batch_fits, args.batch_scale)
         batched = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
-                              problems=probs)
+                              tile_rows=args.batch_tile_rows, problems=probs)
         batched["bf16"] = run_batched(args.batch_fits, args.batch_scale, args.batch_epochs, torch,
-                                      precision="bf16", solo=False, problems=probs,
-                                      modes=((2, "leveled"),))
+                                      tile_rows=args.batch_tile_rows, precision="bf16",
+                                      solo=False, problems=probs, modes=((2, "leveled"),))
         del probs
         log(f"batched fits: {batched['batched_leveled_epochs_per_s']:.1f} epochs/s batched "
             f"(level placement), {batched['batched_graph_epochs_per_s']:.1f} (fixed graph), "
