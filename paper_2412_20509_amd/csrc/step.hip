@@ -114,6 +114,11 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   constexpr bool SPLIT = PREC == kBF16X3; // with high and low operand parts
   constexpr bool SPLIT_H = SPLIT && kSplitCurvature;
   constexpr bool K16 = BF && KP == 16;    // bfloat16 products of K = 16 (16x16x16)
+  // bfloat16 transposed D1/D2 stored as row pairs: with 4 wavefronts a lane
+  // holds rows 2 l16 and 2 l16 + 1 of its columns (sub-tiles 0 and 1), one
+  // 32-bit store per pair, reusing the conversions of the U side (not with
+  // the 16x16x16 products, where the packing cost more than it saved)
+  constexpr bool PAIR_T = BF && NW == 4 && !K16;
   using TE = TElem<PREC>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -221,16 +226,28 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       }
     }
   };
-  // row-panel rows of a group, float4 granules spread over the workgroup
+  // row-panel rows of a group, granules spread over the workgroup: float32
+  // tiles 4 entries of a row; bfloat16 tiles 2 entries of a row pair (x, y of
+  // row 2i, z, w of row 2i + 1), so that a thread writes both the row-major and
+  // the transposed copies as 32-bit pairs
   constexpr int PF = (kRowGroup * (KP / 4) + NT - 1) / NT;
   auto load_p = [&](int rg, float4 (&pf)[PF]) {
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * NT;
       pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (idx < kRowGroup * (KP / 4)) {
-        const int r = idx / (KP / 4), c4 = idx % (KP / 4);
-        if (rg + r < tv.row_end)
-          pf[u] = reinterpret_cast<const float4*>(tv.Prow + (int64_t)(rg + r) * KP)[c4];
+        if constexpr (BF) {
+          const int r = 2 * (idx / (KP / 2)), c = 2 * (idx % (KP / 2));
+          float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+          if (rg + r < tv.row_end) a = *reinterpret_cast<const float2*>(tv.Prow + (int64_t)(rg + r) * KP + c);
+          if (rg + r + 1 < tv.row_end)
+            b = *reinterpret_cast<const float2*>(tv.Prow + (int64_t)(rg + r + 1) * KP + c);
+          pf[u] = make_float4(a.x, a.y, b.x, b.y);
+        } else {
+          const int r = idx / (KP / 4), c4 = idx % (KP / 4);
+          if (rg + r < tv.row_end)
+            pf[u] = reinterpret_cast<const float4*>(tv.Prow + (int64_t)(rg + r) * KP)[c4];
+        }
       }
     }
   };
@@ -241,6 +258,23 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
   const int s_oo = tid - s_r0 * (2 * KU);
   const bool s_on = s_r0 < s_rows;
   const int s_src = (s_oo < KU) ? (p + s_oo) : (KP + p + (s_oo - KU));
+  // Where 2 KP divides the thread count, a thread instead takes one column f_o
+  // of the padded U-sum rows (2 KP wide) and rows f_r0 + j RS: the passes and
+  // the LDS offsets are compile-time constants, so the reads of all passes
+  // issue together.  Columns outside the row side's parameters are read and
+  // dropped (f_oo < 0).
+  constexpr bool SFIX = NT % (2 * KP) == 0;
+  constexpr int RS = SFIX ? NT / (2 * KP) : 1;
+  constexpr int SJ = SFIX ? kRowGroup / RS : 1;
+  const int f_o = tid % (2 * KP), f_r0 = tid / (2 * KP);
+  const int f_c = (f_o < KP) ? f_o - p : f_o - KP - p;
+  const int f_oo = (f_c >= 0 && f_c < KU) ? ((f_o < KP) ? f_c : KU + f_c) : -1;
+  auto usum_row = [&](int c, int r) -> const float* {
+    if constexpr (NW == 8)
+      return reinterpret_cast<const float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? c + 4 * (r & 1) : 0])[r >> 1];
+    else
+      return reinterpret_cast<const float (*)[2 * KP + 1]>(L.gbuf[c])[r];
+  };
 
   YRaw ynext[NR][2];
   float4 pnext[PF];
@@ -265,25 +299,31 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * NT;
       if (idx < kRowGroup * (KP / 4)) {
-        const int r = idx / (KP / 4), c0 = 4 * (idx % (KP / 4));
-        if constexpr (!BF) *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
-        if constexpr (BF) {
-          const floatx4 x = {pnext[u].x, pnext[u].y, pnext[u].z, pnext[u].w};
-          const floatx4 x2 = x * x;
-          const bf16x4 xb = __builtin_convertvector(x, bf16x4);
-          const bf16x4 xq = __builtin_convertvector(x2, bf16x4);
-          *reinterpret_cast<bf16x4*>(&L.sPb[r][c0]) = xb;
-          for (int i = 0; i < 4; ++i) {
-            L.sPT[0][c0 + i][r] = xb[i];
-            L.sPT[1][c0 + i][r] = xq[i];
-          }
+        if constexpr (!BF) {
+          const int r = idx / (KP / 4), c0 = 4 * (idx % (KP / 4));
+          *reinterpret_cast<float4*>(&L.sP[r][c0]) = pnext[u];
+        } else {
+          // entries (r, c), (r, c + 1), (r + 1, c), (r + 1, c + 1)
+          const int r = 2 * (idx / (KP / 2)), c = 2 * (idx % (KP / 2));
+          const float x00 = pnext[u].x, x01 = pnext[u].y, x10 = pnext[u].z, x11 = pnext[u].w;
+          auto pair = [](float a, float b) { return __builtin_convertvector(floatx2{a, b}, bf16x2); };
+          auto st = [](__bf16* p, bf16x2 v) { *reinterpret_cast<bf16x2*>(p) = v; };
+          st(&L.sPb[r][c], pair(x00, x01));
+          st(&L.sPb[r + 1][c], pair(x10, x11));
+          st(&L.sPT[0][c][r], pair(x00, x10));
+          st(&L.sPT[0][c + 1][r], pair(x01, x11));
+          const float q00 = x00 * x00, q01 = x01 * x01, q10 = x10 * x10, q11 = x11 * x11;
+          st(&L.sPT[1][c][r], pair(q00, q10));
+          st(&L.sPT[1][c + 1][r], pair(q01, q11));
           if constexpr (SPLIT) {
-            const bf16x4 xbl = __builtin_convertvector(x - __builtin_convertvector(xb, floatx4), bf16x4);
-            *reinterpret_cast<bf16x4*>(&L.sPbl[r][c0]) = xbl;
-            for (int i = 0; i < 4; ++i) L.sPTl[0][c0 + i][r] = xbl[i];
+            auto lo = [](float a) { return a - (float)(__bf16)a; };
+            st(&L.sPbl[r][c], pair(lo(x00), lo(x01)));
+            st(&L.sPbl[r + 1][c], pair(lo(x10), lo(x11)));
+            st(&L.sPTl[0][c][r], pair(lo(x00), lo(x10)));
+            st(&L.sPTl[0][c + 1][r], pair(lo(x01), lo(x11)));
             if constexpr (kSplitCurvature) {
-              const bf16x4 xql = __builtin_convertvector(x2 - __builtin_convertvector(xq, floatx4), bf16x4);
-              for (int i = 0; i < 4; ++i) L.sPTl[kSplitCurvature ? 1 : 0][c0 + i][r] = xql[i];
+              st(&L.sPTl[kSplitCurvature ? 1 : 0][c][r], pair(lo(q00), lo(q10)));
+              st(&L.sPTl[kSplitCurvature ? 1 : 0][c + 1][r], pair(lo(q01), lo(q11)));
             }
           }
         }
@@ -300,6 +340,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
 
     // ---- per 16-row sub-tile R: eta, epilogue, transpose store, U-side sums
     floatx4 ug[NR][NB], uh[NR][NB];
+    // bfloat16 D1, D2 (and their low parts) of columns colw + 16C + 4g + v,
+    // element 4C + v, per sub-tile: the transposed stores of the row pairs
+    bf16x8 th[PAIR_T ? NR : 1][SPLIT_H ? 4 : (SPLIT ? 3 : 2)];
     for (int rr = 0; rr < NR; ++rr) {
       const int R = R0 + rr;
       const int lrow = 2 * l16 + R;
@@ -364,15 +407,16 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
       // per-entry values would stay live and cost registers)
       if constexpr (WANT_DEV) asm volatile("" ::"v"(dev_grp));
       // transposed copies for the V side: sT[h][col][row]
-      for (int C = 0; C < 2; ++C)
-        for (int v = 0; v < 4; ++v) {
-          const int cc = 16 * C + 4 * g + v;
-          const TE h1 = (TE)d1[C][v], h2 = (TE)d2[C][v];
-          sT[0][cc][lrow] = h1;
-          sT[1][cc][lrow] = h2;
-          if constexpr (SPLIT) sT[2][cc][lrow] = lo_bf16(d1[C][v], h1);
-          if constexpr (SPLIT_H) sT[SPLIT_H ? 3 : 2][cc][lrow] = lo_bf16(d2[C][v], h2);
-        }
+      if constexpr (!PAIR_T)
+        for (int C = 0; C < 2; ++C)
+          for (int v = 0; v < 4; ++v) {
+            const int cc = 16 * C + 4 * g + v;
+            const TE h1 = (TE)d1[C][v], h2 = (TE)d2[C][v];
+            sT[0][cc][lrow] = h1;
+            sT[1][cc][lrow] = h2;
+            if constexpr (SPLIT) sT[2][cc][lrow] = lo_bf16(d1[C][v], h1);
+            if constexpr (SPLIT_H) sT[SPLIT_H ? 3 : 2][cc][lrow] = lo_bf16(d2[C][v], h2);
+          }
       // U side: G_U[row][o] = sum over this wavefront's cols of D1[row][col] P[col][o]
       for (int ob = 0; ob < NB; ++ob) {
         ug[rr][ob] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -387,40 +431,68 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
             }
       } else if constexpr (K16) {
         // A = D1 (D2) of row lrow, columns colw + 16C + 4g .. +3 from the accumulators
+        bf16x4 k1[2], k2[2], k1l[2], k2l[2];
         for (int C = 0; C < 2; ++C) {
           const floatx4 f1 = {d1[C][0], d1[C][1], d1[C][2], d1[C][3]};
           const floatx4 f2 = {d2[C][0], d2[C][1], d2[C][2], d2[C][3]};
           const bf16x4 b1 = to_bf16x4(f1), b2 = to_bf16x4(f2);
+          k1[C] = b1;
+          k2[C] = b2;
           if constexpr (SPLIT) {
-            ug[rr][0] = mfma_bf16_k16(lo_bf16x4(f1, b1), kb[C], ug[rr][0]);
+            k1l[C] = lo_bf16x4(f1, b1);
+            ug[rr][0] = mfma_bf16_k16(k1l[C], kb[C], ug[rr][0]);
             ug[rr][0] = mfma_bf16_k16(b1, kbl[C], ug[rr][0]);
           }
           if constexpr (SPLIT_H) {
-            uh[rr][0] = mfma_bf16_k16(lo_bf16x4(f2, b2), kq[C], uh[rr][0]);
+            k2l[C] = lo_bf16x4(f2, b2);
+            uh[rr][0] = mfma_bf16_k16(k2l[C], kq[C], uh[rr][0]);
             uh[rr][0] = mfma_bf16_k16(b2, kql[C], uh[rr][0]);
           }
           ug[rr][0] = mfma_bf16_k16(b1, kb[C], ug[rr][0]);
           uh[rr][0] = mfma_bf16_k16(b2, kq[C], uh[rr][0]);
         }
+        if constexpr (PAIR_T) {
+          th[rr][0] = __builtin_shufflevector(k1[0], k1[1], 0, 1, 2, 3, 4, 5, 6, 7);
+          th[rr][1] = __builtin_shufflevector(k2[0], k2[1], 0, 1, 2, 3, 4, 5, 6, 7);
+          if constexpr (SPLIT) th[rr][2] = __builtin_shufflevector(k1l[0], k1l[1], 0, 1, 2, 3, 4, 5, 6, 7);
+          if constexpr (SPLIT_H)
+            th[rr][SPLIT_H ? 3 : 2] = __builtin_shufflevector(k2l[0], k2l[1], 0, 1, 2, 3, 4, 5, 6, 7);
+        }
       } else {
         const floatx8 f1 = {d1[0][0], d1[0][1], d1[0][2], d1[0][3], d1[1][0], d1[1][1], d1[1][2], d1[1][3]};
         const floatx8 f2 = {d2[0][0], d2[0][1], d2[0][2], d2[0][3], d2[1][0], d2[1][1], d2[1][2], d2[1][3]};
         const bf16x8 b1 = to_bf16(f1), b2 = to_bf16(f2);
+        bf16x8 b1l, b2l;
+        if constexpr (SPLIT) b1l = lo_bf16(f1, b1);
+        if constexpr (SPLIT_H) b2l = lo_bf16(f2, b2);
         for (int ob = 0; ob < NB; ++ob) {
           if constexpr (SPLIT) {
-            const bf16x8 b1l = lo_bf16(f1, b1);
             ug[rr][ob] = mfma_bf16(b1l, ub16[ob], ug[rr][ob]);
             ug[rr][ob] = mfma_bf16(b1, ub16l[ob], ug[rr][ob]);
           }
           if constexpr (SPLIT_H) {
-            const bf16x8 b2l = lo_bf16(f2, b2);
             uh[rr][ob] = mfma_bf16(b2l, ub16q[ob], uh[rr][ob]);
             uh[rr][ob] = mfma_bf16(b2, ub16ql[SPLIT_H ? ob : 0], uh[rr][ob]);
           }
           ug[rr][ob] = mfma_bf16(b1, ub16[ob], ug[rr][ob]);
           uh[rr][ob] = mfma_bf16(b2, ub16q[ob], uh[rr][ob]);
         }
+        if constexpr (PAIR_T) {
+          th[rr][0] = b1;
+          th[rr][1] = b2;
+          if constexpr (SPLIT) th[rr][2] = b1l;
+          if constexpr (SPLIT_H) th[rr][SPLIT_H ? 3 : 2] = b2l;
+        }
       }
+    }
+    if constexpr (PAIR_T) {
+      // sT[h][col][2 l16 .. 2 l16 + 1] = (sub-tile 0, sub-tile 1)
+      for (int h = 0; h < (SPLIT_H ? 4 : (SPLIT ? 3 : 2)); ++h)
+        for (int C = 0; C < 2; ++C)
+          for (int v = 0; v < 4; ++v) {
+            const bf16x2 pr = {th[0][h][4 * C + v], th[NR - 1][h][4 * C + v]};
+            *reinterpret_cast<bf16x2*>(&sT[h][16 * C + 4 * g + v][2 * l16]) = pr;
+          }
     }
     // the column group's transposed rows are complete: with 4 wavefronts each
     // writes and reads only its own column group's rows (LDS operations of
@@ -499,20 +571,31 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
     __syncthreads();
 
     // ---- sum over the 4 column groups (fixed order) and store the strip partial
-    if (s_on)
+    if constexpr (SFIX) {
+      auto strip = [&](auto ragged) {
+        if (f_oo >= 0) {
+          float* dst = tv.Upart + (int64_t)(rg + f_r0) * (2 * KU) + f_oo;
+#pragma unroll
+          for (int j = 0; j < SJ; ++j) {
+            const int r = f_r0 + j * RS;
+            float s = 0.f;
+            for (int c = 0; c < 4; ++c) s += usum_row(c, r)[f_o];
+            if (!decltype(ragged)::value || rg + r < tv.row_end) dst[(int64_t)j * RS * (2 * KU)] = s;
+          }
+        }
+      };
+      if (rg + kRowGroup <= tv.row_end) strip(std::false_type{});
+      else strip(std::true_type{});
+    } else if (s_on) {
       for (int r = s_r0; r < kRowGroup; r += s_rows) {
         const int row = rg + r;
         if (row < tv.row_end) {
           float s = 0.f;
-          for (int c = 0; c < 4; ++c) {
-            if constexpr (NW == 8)
-              s += reinterpret_cast<float (*)[2 * KP + 1]>(L.ubuf[NW == 8 ? c + 4 * (r & 1) : 0])[r >> 1][s_src];
-            else
-              s += reinterpret_cast<float (*)[2 * KP + 1]>(L.gbuf[c])[r][s_src];
-          }
+          for (int c = 0; c < 4; ++c) s += usum_row(c, r)[s_src];
           tv.Upart[(int64_t)row * (2 * KU) + s_oo] = s;
         }
       }
+    }
   }
 
   if (tv.stamps && tid == 0) tv.stamps[2] = wall_clock64();
