@@ -273,4 +273,27 @@ __device__ __forceinline__ void family_entry(float eta, float y, float w, const 
   }
 }
 
+// family_entry<FAM, WANT_DEV, true> with the entry's deviance added to `acc`
+// instead of returned: for NB without weights the two terms of the mu part go
+// into the sum by two fused multiply-adds, one operation less per entry.
+template <int FAM, bool WANT_DEV, bool HAS_W>
+__device__ __forceinline__ void family_entry_acc(float eta, float y, float w, const FamilyConst& c,
+                                                 float& d1, float& d2, float& acc) {
+  if constexpr (FAM == kNegBin && WANT_DEV && !HAS_W) {
+    const float ec = __builtin_amdgcn_fmed3f(eta, c.lo, c.hi);
+    const float t = ec * 1.4426950408889634f;
+    const float mu = __builtin_amdgcn_exp2f(t);
+    const float inv = __builtin_amdgcn_rcpf(c.a + mu);
+    const float wa = c.a_phi * inv;
+    d2 = wa * mu;
+    d1 = fmaf(-wa, y, d2);
+    const float l2 = __builtin_amdgcn_logf(fmaf(mu, c.inv_a, 1.0f));
+    acc = fmaf(-y, t, fmaf(y + c.a, l2, acc));
+  } else {
+    float dv = 0.f;
+    family_entry<FAM, WANT_DEV, true>(eta, y, w, c, d1, d2, dv);
+    if constexpr (WANT_DEV) acc += dv;
+  }
+}
+
 }  // namespace gmf

@@ -391,6 +391,9 @@ __device__ double compute_tile(const TileView& tv, const FamilyConst& fc, int p,
             if constexpr (FAM == kGeneric) {
               const float av = tv.alpha ? tv.alpha[min(colb + v, tv.m_b - 1)] : fc.a;
               family_entry_generic<WANT_DEV, true>(e[v], ys[v], ws[v], av, fc, d1[C][v], d2[C][v], dv);
+            } else if constexpr (!decltype(masked)::value) {
+              family_entry_acc<FAM, WANT_DEV, HAS_W>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dev_grp);
+              continue;
             } else {
               family_entry<FAM, WANT_DEV, true>(e[v], ys[v], ws[v], fc, d1[C][v], d2[C][v], dv);
             }
