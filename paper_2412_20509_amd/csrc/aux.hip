@@ -493,14 +493,18 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds
         const float4 y4 = counts_f4(ycur[R][C]);
         const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
         const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        // entries in the units of the HALF epilogues (the tile scales its sum)
         auto entries = [&](auto masked) {
           for (int v = 0; v < 4; ++v) {
             float x1, x2, dv = 0.f;
             if constexpr (FAM == kGeneric) {
               const float av = column_alpha(fc, a.blk_col0[blk] + min(colb + v, m_b - 1));
-              family_entry_generic<true>(e[v], ys[v], ws[v], av, fc, x1, x2, dv);
+              family_entry_generic<true, true>(e[v], ys[v], ws[v], av, fc, x1, x2, dv);
+            } else if constexpr (!decltype(masked)::value) {
+              family_entry_acc<FAM, true, HAS_W>(e[v], ys[v], ws[v], fc, x1, x2, grp);
+              continue;
             } else {
-              family_entry<FAM, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
+              family_entry<FAM, true, true>(e[v], ys[v], ws[v], fc, x1, x2, dv);
             }
             if constexpr (decltype(masked)::value) grp += (row < row_end && colb + v < m_b) ? dv : 0.f;
             else grp += dv;
@@ -520,7 +524,7 @@ __device__ __forceinline__ void deviance_tile(const DevArgs& a, int tile, DevLds
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) L.sDev[wave] = acc;
   __syncthreads();
-  if (tid == 0) a.partial[tile] = ((L.sDev[0] + L.sDev[1]) + L.sDev[2]) + L.sDev[3];
+  if (tid == 0) a.partial[tile] = dev_unit<FAM>() * (((L.sDev[0] + L.sDev[1]) + L.sDev[2]) + L.sDev[3]);
 }
 
 // One workgroup per tile, or (grid_cap) fewer workgroups walking the tiles:
