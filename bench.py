@@ -458,40 +458,40 @@ def gen_batched(nfits, scale):
                    family=sp["family"], chunked=True) for sp in batch_specs(nfits, scale)]
 
 
-def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", solo=True,
-                problems=None, modes=((1, "graph"), (2, "leveled"))):
-    """Many uneven fits: fit-by-fit epochs (each context stepped on its own)
-    against batched epochs (gmf_batch_*: the fixed launch sequence as a
-    recorded graph, and level placement).  Fits are grouped into batches by
-    panel stride (p + q + d <= 32 -> 32, else 48, 64 for the bfloat16
-    precisions); every fit uses `tile_rows`-row tiles (0: the library's rule,
-    -1: the autotuner's table, the first fit of each shape class tuned)."""
+def run_batched(nfits, scale, epochs, torch, tile_rows=384, precision="fp32", solo=True,
+                problems=None, modes=((1, "graph"), (2, "leveled")), solo_tile_rows=128):
+    """Many uneven fits: fit-by-fit epochs (each context stepped on its own,
+    `solo_tile_rows`-row tiles) against batched epochs (gmf_batch_*: the fixed
+    launch sequence as a recorded graph, and level placement; `tile_rows`-row
+    tiles).  Fits are grouped into batches by panel stride (p + q + d <= 32 ->
+    32, else 48, 64 for the bfloat16 precisions); the batches run on their own
+    streams, side by side.  tile_rows 0: the library's rule, -1: the
+    autotuner's table (the first fit of each shape class tuned).  In a batch
+    the other fits supply the parallelism, so deeper tiles than a single fit
+    wants pay (fewer tiles, each pipelining more row groups)."""
     from paper_2412_20509_amd.gmf import Batch, FitConfig, GMF, tune, tune_lookup
     if problems is None:
         problems = gen_batched(nfits, scale)
     tuned = {}
-    fits, entries = [], 0
-    for pr in problems:
-        stride = 32 if pr.k <= 32 else (48 if precision == "fp32" else 64)
-        # 128-row tiles by default: in a batch the other fits supply the
-        # parallelism, and deeper tiles pipeline their row groups (61 vs 51
-        # epochs/s at 32 rows)
-        fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
-                       seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1,
-                       tile_rows=max(tile_rows, 0), precision=precision)
-        if tile_rows < 0:
-            fc.tile_rows = 0
-            cfg = fc.to_c(pr.n, pr.m, pr.p, pr.q)
-            if tune_lookup(cfg) == 0:
-                best, _ = tune(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0,
-                               candidates=(64, 128, 256, 512), steps=20)
-                tuned[best] = tuned.get(best, 0) + 1
-        fits.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
-        entries += pr.n * pr.m
-    torch.cuda.synchronize()
-    groups = {}
-    for g in fits:
-        groups.setdefault(g.cfg.panel_stride, []).append(g)
+    entries = sum(pr.n * pr.m for pr in problems)
+
+    def contexts(rows):
+        out = []
+        for pr in problems:
+            stride = 32 if pr.k <= 32 else (48 if precision == "fp32" else 64)
+            fc = FitConfig(family=pr.family, d=pr.d, R=pr.R, S=pr.S, nb_alpha=pr.nb_alpha,
+                           seed=pr.sched_seed, panel_stride=stride, skip_block_deviance=1,
+                           tile_rows=max(rows, 0), precision=precision)
+            if rows < 0:
+                fc.tile_rows = 0
+                cfg = fc.to_c(pr.n, pr.m, pr.p, pr.q)
+                if tune_lookup(cfg) == 0:
+                    best, _ = tune(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0,
+                                   candidates=(64, 128, 256, 512), steps=20)
+                    tuned[best] = tuned.get(best, 0) + 1
+            out.append(GMF(fc, pr.Y, pr.X, pr.Z, pr.B0, pr.A0, pr.U0, pr.V0, device="cuda:0"))
+        torch.cuda.synchronize()
+        return out
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -500,15 +500,21 @@ def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", so
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    def solo_epochs():
-        for _ in range(epochs):
-            for g in fits:
-                g.step(g.cfg.R * g.cfg.S)
+    def close(fits):
+        for g in fits:
+            g.close()
+        torch.cuda.empty_cache()
 
     t_solo = None
     if solo:
+        fits = contexts(solo_tile_rows)
         timed(lambda: [g.step(g.cfg.R * g.cfg.S) for g in fits])      # warm-up epoch
-        t_solo = timed(solo_epochs)
+        t_solo = timed(lambda: [g.step(g.cfg.R * g.cfg.S) for _ in range(epochs) for g in fits])
+        close(fits)
+    fits = contexts(tile_rows)
+    groups = {}
+    for g in fits:
+        groups.setdefault(g.cfg.panel_stride, []).append(g)
     res = {}
     for mode, name in modes:
         batches = [Batch(gs, table_epochs=max(epochs, 1), mode=mode) for gs in groups.values()]
@@ -518,16 +524,14 @@ def run_batched(nfits, scale, epochs, torch, tile_rows=128, precision="fp32", so
         res[name] = t
         for b in batches:
             b.close()
-    for g in fits:
-        g.close()
+    close(fits)
     del fits
-    torch.cuda.empty_cache()
     out = dict(
         workload=(f"{nfits} fits: family coin Poisson/NB, n ~ U{{2000..50000}} x {scale}, "
                   f"m ~ U{{1000..5000}} x {scale}, d ~ U{{5..30}}, p = 3, q = 1, blocks 10 % x 20 %"),
         entries=entries, epochs=epochs, groups={int(k): len(v) for k, v in groups.items()},
         tile_rows=tile_rows if tile_rows >= 0 else "autotuned", tuned_classes=tuned,
-        precision=precision,
+        separate_tile_rows=solo_tile_rows if solo else None, precision=precision,
         separate_epochs_per_s=None if t_solo is None else epochs / t_solo)
     for name, t in res.items():
         out[f"batched_{name}_epochs_per_s"] = epochs / t
@@ -642,7 +646,7 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="factor on n and m of every batched fit")
     ap.add_argument("--batch-epochs", type=int, default=5)
-    ap.add_argument("--batch-tile-rows", type=int, default=128,
+    ap.add_argument("--batch-tile-rows", type=int, default=384,
                     help="rows per tile of the batched fits (0: the library's rule, "
                          "-1: the autotuner's table, tuned on the first fit of each shape class)")
     ap.add_argument("--only-batched", action="store_true",
