@@ -360,6 +360,35 @@ def test_bf16x3_first_step(family, n, m, d, R, S):
     g.close()
 
 
+@pytest.mark.parametrize("family,n,m,d,R,S", [
+    ("poisson", 1000, 700, 5, 3, 2),     # panel stride 16 (16x16x16 products), a ragged strip
+    ("negbin", 517, 389, 20, 2, 3),      # k = 24 -> panel stride 32, ragged everything
+    ("negbin", 260, 200, 40, 2, 2),      # k = 44 -> panel stride 64
+])
+def test_bf16_first_step(family, n, m, d, R, S):
+    """Plain BF16 (bfloat16 operands in eta and in the four contractions, with
+    weights) at each panel stride: one step against the oracle.  bfloat16
+    keeps 8 bits of each operand (relative rounding up to 2^-9); measured on
+    these cases: parameters within 8.3e-4, moments within 4.2e-3 (the
+    curvature sums of squared operands round the most), the block deviance
+    within 7.1e-5; gated at 3e-3, 1e-2 and 3e-4."""
+    pr = gen_tiny(family, n=n, m=m, d=d, p=2, q=2, R=R, S=S, seed=1702, weights=True)
+    say(f"bf16 first step {family} n={n} m={m} d={d}")
+    lam = (0.2, 0.3, 0.7, 0.5)
+    o = oracle_for(pr, lam=lam)
+    g = gpu_for(pr, precision="bf16", lam=lam)
+    dev_o = o.step()
+    g.step(1)
+    errs = compare_state(g, o, 1e-2, f"bf16 {family}")
+    print("bf16 one-step relative errors:", errs)
+    for k in ("B", "Gamma", "U", "V"):
+        assert errs[k] <= 3e-3, (k, errs[k])
+    dev_err = rel_err([g.block_deviance(1)[0]], [dev_o])
+    print("bf16 block deviance relative error:", dev_err)
+    assert dev_err <= 3e-4
+    g.close()
+
+
 def test_bf16x3_reaches_oracle_deviance():
     pr = gen_poisson_small()
     say("bf16x3 c1: one epoch, final deviance after 20 epochs")
