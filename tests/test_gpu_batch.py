@@ -57,6 +57,28 @@ def test_batch_equals_separate_fits(problems, mode):
         g.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_bfloat16_batch_equals_separate_fits(problems, precision):
+    """The bfloat16 step tiles in a batch (level placement): the same bits as
+    the fits stepped on their own (which read the 16-bit counts and run the
+    8-wavefront tile in their one-step launches)."""
+    from paper_2412_20509_amd.gmf import Batch
+    print(f"[case] batch of 4 fits, {precision}, mode=2", flush=True)
+    solo = _make(problems, 32, precision=precision)
+    for g, pr in zip(solo, problems):
+        g.step(2 * pr.R * pr.S)
+    fits = _make(problems, 32, precision=precision)
+    b = Batch(fits, table_epochs=4, mode=2)
+    b.run(2, trace=False)
+    for g, h, pr in zip(fits, solo, problems):
+        assert g.steps_done() == 2 * pr.R * pr.S
+        for x, y in zip(_state(g), _state(h)):
+            assert np.array_equal(x, y)
+    b.close()
+    for g in fits + solo:
+        g.close()
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_batch_table_refill_and_continuation(problems, mode):
     """Three epochs through a 2-epoch table, then two more epochs in a second
