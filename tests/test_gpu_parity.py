@@ -190,6 +190,25 @@ def test_steps_are_deterministic():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3"])
+def test_steps_are_deterministic_under_load(precision):
+    """Two runs of the same fit, with many workgroups per compute unit and
+    many 32-row groups per tile (blocks of 5000 x 1000): every parameter,
+    moment, block deviance and the full deviance the same bits.  Tolerance
+    tests cannot see a race between the wavefronts of a tile; this one can."""
+    pr = gen_nb(n=20000, m=3000, d=20, R=4, S=3, seed=1035)
+    say(f"determinism under load, {precision}")
+    outs = []
+    for _ in range(2):
+        g = gpu_for(pr, precision=precision)
+        g.step(24)
+        outs.append([*g.params(), *g.moments(), np.asarray(g.block_deviance(24)),
+                     np.asarray(g.deviance())])
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
 def test_postprocess_matches_oracle_projection():
     pr = gen_nb(n=900, m=400, d=5, R=3, S=2, seed=1034)
     say("postprocess A+B1")
